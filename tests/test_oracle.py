@@ -1,0 +1,179 @@
+"""Pins for the oracle (CPU only).
+
+Each check ties the oracle to something other than itself: a brute-force
+Kronecker-product unitary, a stabilizer tableau on T-free Clifford circuits,
+the closed form of a T gate right before measurement, unitarity, and the
+log-XEB interval printed in the paper.  ``test_planted_mistakes_are_caught``
+shows that plausible mistakes planted in the oracle fail these pins.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.pinlib import brute, tableau
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _random_general_circuit(n, d, seed, dense_frac=0.3):
+    rng = W.rng_for(101, seed)
+    c = W.brickwork_circuit(n, d, 0, rng)
+    c = W.with_gate_values(c, rng)
+    gates = []
+    for (l, q, kind, m) in c.gates:
+        u = rng.random()
+        if u < dense_frac / 2:
+            gates.append((l, q, W.GATE_DENSE4, W.random_rank2_gate(rng, "zz")))
+        elif u < dense_frac:
+            z = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+            gates.append((l, q, W.GATE_DENSE4, np.linalg.qr(z)[0]))
+        else:
+            gates.append((l, q, kind, m))
+    c.gates = gates
+    return c
+
+
+@pytest.mark.parametrize("n,d,seed", [(2, 1, 1), (2, 4, 2), (3, 3, 3), (4, 5, 4), (5, 6, 5),
+                                      (6, 7, 6), (6, 4, 7), (5, 9, 8)])
+def test_matches_bruteforce(n, d, seed):
+    c = _random_general_circuit(n, d, seed)
+    ref = brute.all_amplitudes(c)
+    got = oracle.statevector(c)
+    assert np.max(np.abs(got - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("first_parity", [0, 1])
+def test_doped_clifford_bruteforce(first_parity):
+    c = W.brickwork_circuit(6, 8, 5, W.rng_for(102, first_parity), first_parity=first_parity)
+    assert np.max(np.abs(oracle.statevector(c) - brute.all_amplitudes(c))) < 1e-13
+
+
+def test_normalised():
+    c = W.brickwork_circuit(14, 14, 12, W.rng_for(103, 1))
+    psi = oracle.statevector(c)
+    assert abs(float(np.vdot(psi, psi).real) - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("n,d,seed", [(8, 8, 1), (10, 11, 2), (9, 12, 3)])
+def test_clifford_all_probabilities_match_tableau(n, d, seed):
+    c = W.brickwork_circuit(n, d, 0, W.rng_for(104, seed))
+    _, words = W.clifford_table()
+    tab = tableau.run_clifford(c, words)
+    p = np.abs(oracle.statevector(c)) ** 2
+    for x in range(1 << n):
+        bits = [(x >> (n - 1 - j)) & 1 for j in range(n)]
+        pt = tab.prob(bits)
+        assert abs(p[x] - pt) < 1e-12, (x, p[x], pt)
+        if p[x] > 1e-12:
+            r = -math.log2(p[x])
+            assert abs(r - round(r)) < 1e-9
+
+
+def test_clifford_sampled_probabilities_match_tableau():
+    n, d = 18, 18
+    c = W.brickwork_circuit(n, d, 0, W.rng_for(105, 1))
+    _, words = W.clifford_table()
+    tab = tableau.run_clifford(c, words)
+    psi = oracle.statevector(c)
+    rng = W.rng_for(105, 2)
+    xs = [tab.sample(rng) for _ in range(24)] + list(W.random_bitstrings(n, 24, rng))
+    nonzero = 0
+    for bits in xs:
+        idx = int(oracle.prefix_index(bits[None, :], 0)[0])
+        pt = tab.prob(bits)
+        assert abs(abs(psi[idx]) ** 2 - pt) < 1e-12
+        nonzero += pt > 0
+    assert nonzero >= 24
+
+
+@pytest.mark.parametrize("q", [0, 3, 7])
+def test_t_right_before_measurement_is_a_phase(q):
+    c = W.brickwork_circuit(8, 9, 6, W.rng_for(106, q))
+    psi = oracle.statevector(c)
+    c2 = W.Circuit(n=c.n, d=c.d, one_qubit=c.one_qubit.copy(), gates=list(c.gates))
+    c2.one_qubit[c.d, q] = W.T_GATE @ c2.one_qubit[c.d, q]
+    psi2 = oracle.statevector(c2)
+    xq = (np.arange(1 << c.n) >> (c.n - 1 - q)) & 1
+    assert np.max(np.abs(psi2 - psi * np.exp(1j * np.pi / 4 * xq))) < 1e-14
+
+
+def test_amplitude_batches_index_convention():
+    c = W.brickwork_circuit(7, 6, 3, W.rng_for(107, 1))
+    psi = brute.all_amplitudes(c)
+    bits = W.random_bitstrings(7, 5, W.rng_for(107, 2))
+    for k in (0, 1, 3, 7):
+        z = oracle.amplitudes(c, bits, k)
+        for i, row in enumerate(bits):
+            for b in range(1 << k):
+                full = list(row[: 7 - k]) + [(b >> (k - 1 - j)) & 1 for j in range(k)]
+                x = sum(v << (6 - j) for j, v in enumerate(full))
+                assert abs(z[i, b] - psi[x]) < 1e-14
+
+
+def _golden(name):
+    vals = {}
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                vals[k] = float(v)
+    return vals
+
+
+def test_logxeb_interval_matches_paper():
+    g = _golden("logxeb_interval.txt")
+    lo, hi = oracle.ci95(g["F"], g["SE"])
+    # F, SE and the bounds are each printed to 5 decimals (half-unit 0.5e-5),
+    # so the recomputed bounds agree to within 0.5e-5 * (1 + 1.96 + 1).
+    tol = 0.5e-5 * (1 + 1.96 + 1)
+    assert abs(lo - g["LO"]) <= tol and abs(hi - g["HI"]) <= tol
+    assert abs(0.5 * (g["LO"] + g["HI"]) - g["F"]) <= 1e-5
+
+
+def test_logxeb_closed_forms():
+    n = 20
+    # uniform probabilities 2^-n give ln p + n ln 2 = 0, so F = gamma exactly
+    f, se, _, _ = oracle.logxeb(np.full(100, 2.0 ** -n), n)
+    assert abs(f - oracle.EULER_GAMMA) < 1e-12 and se < 1e-12
+    # Porter-Thomas z ~ Exp(1): E[ln z] = -gamma, so uniform draws give F ~ 0
+    z = W.rng_for(108, 1).exponential(size=200000)
+    f, se, _, _ = oracle.logxeb(z * 2.0 ** -n, n)
+    assert abs(f) < 5 * se
+    # exact sampling draws z with density z e^-z: E[ln z] = 1 - gamma, so F ~ 1
+    z = W.rng_for(108, 2).gamma(2.0, size=200000)
+    f, se, _, _ = oracle.logxeb(z * 2.0 ** -n, n)
+    assert abs(f - 1.0) < 5 * se
+
+
+def test_tv_conditional():
+    z = np.array([[1.0, 0.0], [1.0, 1.0]], dtype=np.complex128)
+    w = np.array([[0.0, 1.0], [1.0, 1.0j]], dtype=np.complex128)
+    assert np.allclose(oracle.tv_conditional(z, w), [1.0, 0.0])
+
+
+def _pins_pass(mutation):
+    """True if every pin used here still passes for the mutated oracle."""
+    ok = True
+    c = _random_general_circuit(5, 6, 11, dense_frac=0.0)
+    ok &= np.max(np.abs(oracle.statevector(c, mutation) - brute.all_amplitudes(c))) < 1e-12
+    cc = W.brickwork_circuit(8, 8, 0, W.rng_for(109, 1))
+    _, words = W.clifford_table()
+    tab = tableau.run_clifford(cc, words)
+    p = np.abs(oracle.statevector(cc, mutation)) ** 2
+    for x in range(0, 256, 7):
+        bits = [(x >> (7 - j)) & 1 for j in range(8)]
+        ok &= abs(p[x] - tab.prob(bits)) < 1e-12
+    return bool(ok)
+
+
+def test_unmutated_oracle_passes_pins():
+    assert _pins_pass(0)
+
+
+@pytest.mark.parametrize("mutation", [1, 2, 3, 4, 5])
+def test_planted_mistakes_are_caught(mutation):
+    assert not _pins_pass(mutation)
