@@ -1,0 +1,169 @@
+/*
+ * tnc.h - exact output amplitudes of open-boundary 1D brickwork circuits by
+ * the deterministic temporal-boundary tensor-network contraction, on one
+ * AMD Instinct MI355X (gfx950).  C ABI; no C++ or framework types cross it.
+ *
+ * Method (arXiv 2608.13110):
+ *   - circuit family: n qubits on an open chain, d layers of nearest-
+ *     neighbour entanglers alternating between the pairs (1,2),(3,4),... and
+ *     (2,3),(4,5),... (1-based), arbitrary one-qubit gates before, between
+ *     and after the layers (Sec. 2.1); every entangler must have operator
+ *     Schmidt rank <= 2 (Sec. 2.1, the operator-Schmidt-rank equation);
+ *   - the amplitude psi(x) = <x|U|0^n> (Sec. 2.2) is contracted by the
+ *     unsliced sweep of Alg. 1 (Sec. 3.1), width ceil(d/2) (Prop.
+ *     constructive-memory); with k open output legs the batch
+ *     Z[b] = <a, b|U|0^n> over the last k qubits is contracted by Alg. 2
+ *     (Sec. 4.3) at the same width for 1 <= k <= floor(d/4) (Prop. batched
+ *     width).
+ *
+ * Conventions (0-based): qubit j is row j of the chain.  A bitstring is n
+ * bytes, byte j = output value (0/1) of qubit j.  For k open legs the batch
+ * output index is b = sum_j x_{n-k+j} * 2^(k-1-j), i.e. the last k qubits
+ * read most-significant first, so (a, b) read MSB-first is the full index.
+ * one-qubit layer l (0..d) acts after entangling layer l; its gate on qubit q
+ * is one_qubit[(l*n + q)*4 + 2*row + col] (row = output, col = input).
+ *
+ * Errors: every entry point returns TNC_OK (0) or a negative status and never
+ * throws; tnc_last_error() gives a message for the calling thread.
+ *
+ * Threading: a plan is immutable once built (schedules for each k and the
+ * device tables are created lazily under a lock).  Calls of
+ * tnc_amplitudes on different streams with different workspaces may overlap.
+ */
+#ifndef TNC_H
+#define TNC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tnc_plan_s* tnc_plan_t;
+
+typedef struct {
+  double re, im;
+} tnc_c128;
+
+#define TNC_OK 0
+#define TNC_E_INVALID (-1)   /* malformed input (bad pattern, pointer, size) */
+#define TNC_E_DOMAIN (-2)    /* outside the supported range (k, n, d, width) */
+#define TNC_E_RANK (-3)      /* an entangler has operator Schmidt rank > 2 */
+#define TNC_E_NOMEM (-4)     /* workspace too small or device allocation failed */
+#define TNC_E_DEVICE (-5)    /* a HIP call failed */
+
+#define TNC_GATE_CZ 0     /* diag(1, 1, 1, -1); m ignored */
+#define TNC_GATE_DENSE4 1 /* m: 4x4 row-major [out][in], basis 2*x_q + x_{q+1} */
+
+#define TNC_STORE_C64 0   /* boundary tensor stored as complex64 */
+
+/* One two-qubit gate of entangling layer `layer` (1..d) on qubits (q, q+1). */
+typedef struct {
+  int32_t layer;
+  int32_t q;
+  int32_t kind;
+  int32_t reserved;
+  tnc_c128 m[16];
+} tnc_gate2;
+
+/* Tiling options of the pass kernels; zero fields take the defaults. */
+typedef struct {
+  int32_t max_tile_bits; /* entries per pass tile = 2^max_tile_bits (default 13, 6..13) */
+  int32_t reg_bits;      /* entries per thread = 2^reg_bits (default 5, 1..5) */
+  int32_t low_bits;      /* contiguous low slots in every non-bottom tile (default 4) */
+  int32_t reserved;
+} tnc_options;
+
+typedef struct {
+  int32_t width;              /* W(P): log2 of the largest intermediate (Sec. 2.2) */
+  int32_t boundary_bits;      /* h = max crossings of a cut: device tensor has 2^h entries */
+  int32_t live_slots_fixed;   /* legs of the boundary tensor after the fixed rows */
+  int32_t n_ops;              /* boundary updates in the fixed sweep */
+  int32_t n_passes;           /* HBM passes of the fixed sweep */
+  int32_t n_phases;           /* register phases over all passes */
+  int32_t n_late_launches;    /* device launches of the late phase */
+  int32_t fixed_rows;         /* rows contracted by the sweep (Alg. 2: q_1..q_{n-k}) */
+  int32_t early_layers;       /* c = 2k entangling layers in the early region */
+  int32_t late_layers;        /* d - c layers absorbed after the join */
+  double log2_cost;           /* log2 C(P), C = sum |I||J||K| (Sec. 2.2) */
+  uint64_t workspace_per_batch; /* device bytes per concurrent batch */
+} tnc_info;
+
+/*
+ * Build a plan for an n-qubit, d-layer circuit.
+ *   one_qubit: (d+1)*n*4 entries (see Conventions); copied.
+ *   gates:     n_gate2 gates; each must belong to its layer's brickwork
+ *              pattern (patterns alternate; the first gate fixes the parity;
+ *              with no gates layer 1 uses the 1-based pairs (2,3),(4,5),...).
+ *              Pattern pairs without a gate are identity.  Copied.
+ *   opt:       may be NULL.
+ * Host only: no device memory is touched.  Returns TNC_OK and *out, or
+ * TNC_E_INVALID / TNC_E_DOMAIN (n < 2, d < 2, width > 40) / TNC_E_RANK.
+ */
+int tnc_plan(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, const tnc_gate2* gates,
+             const tnc_options* opt, tnc_plan_t* out);
+
+/* Path metrics and launch counts for k open legs (0 <= k <= min(n-1, 10), 2k <= d). */
+int tnc_plan_info(tnc_plan_t plan, int32_t k, tnc_info* info);
+
+/*
+ * Build and upload the device tables for k open legs on the current HIP
+ * device (synchronous).  tnc_amplitudes does this on first use; call it
+ * beforehand when the launches will be captured into a HIP graph.
+ */
+int tnc_prepare(tnc_plan_t plan, int32_t k);
+
+/* Device workspace needed to run n_batches batches at once with storage mode
+ * `storage` (TNC_STORE_C64). */
+int tnc_workspace_bytes(tnc_plan_t plan, int32_t k, int32_t n_batches, int32_t storage, uint64_t* bytes);
+
+/*
+ * Exact amplitude batches on the device, enqueued on `stream` (asynchronous).
+ *   d_bits:   device, n_batches*n bytes; the last k bits of each are ignored.
+ *   d_out:    device, n_batches * 2^k amplitudes (index b above), FP64.
+ *   d_workspace / workspace_bytes: device scratch owned by the caller; when
+ *             it holds fewer than n_batches batches (tnc_workspace_bytes),
+ *             the batches run in consecutive groups.  At least one batch must
+ *             fit (else TNC_E_NOMEM).
+ *   stream:   hipStream_t (NULL = default stream).
+ * Arithmetic: boundary updates in complex FP32; the row-0 build-up, the join
+ * and all later reductions in FP64.
+ */
+int tnc_amplitudes(tnc_plan_t plan, int32_t n_batches, const uint8_t* d_bits, int32_t k, int32_t storage,
+                   tnc_c128* d_out, void* d_workspace, uint64_t workspace_bytes, void* stream);
+
+/* Same with host buffers: allocates device memory, runs, synchronizes. */
+int tnc_amplitudes_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, int32_t storage,
+                        tnc_c128* out);
+
+/*
+ * log-XEB of Sec. 5.2 (Eq. normalized-log-xeb) in FP64 on the device:
+ *   F = gamma + n ln 2 + (1/N) sum_i ln |amp_i|^2,  SE = sd / sqrt(N).
+ *   d_amp:    device, n_batches * 2^k amplitudes.
+ *   d_select: device, n_batches indices b (one component per batch), or NULL
+ *             to use every component.
+ *   d_result: device, 5 doubles {F, SE, F - 1.96 SE, F + 1.96 SE, N}.
+ */
+int tnc_logxeb(const tnc_c128* d_amp, int32_t n_batches, int32_t k, const int32_t* d_select, int32_t n_qubits,
+               double* d_result, void* stream);
+
+/* Free a plan and its device tables.  NULL is ignored. */
+void tnc_release(tnc_plan_t plan);
+
+const char* tnc_strerror(int code);
+const char* tnc_last_error(void);
+
+/*
+ * Planner self-checks, host only, FP64 (tests; the device path never calls
+ * them).  execute_host runs the plan's own update tables on the host;
+ * emulate_device runs the device tables through a host emulation of the
+ * pass kernel's thread / LDS mapping.  Width <= 24.
+ */
+int tnc_debug_execute_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, tnc_c128* out);
+int tnc_debug_emulate_device(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, tnc_c128* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TNC_H */

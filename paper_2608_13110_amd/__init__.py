@@ -1,0 +1,237 @@
+"""Temporal-boundary amplitude engine for one AMD Instinct MI355X (gfx950).
+
+Thin Python binding of ``libtnc.so`` (C ABI in ``include/tnc.h``): this module
+only marshals arguments.  Planning runs in the library's C++ planner and every
+step of the contraction runs in its HIP kernels; PyTorch provides device
+memory and streams.  If the library is missing the import fails loudly; there
+is no CPU fallback.
+
+    from paper_2608_13110_amd import Plan
+    plan = Plan.from_circuit(circ)            # host planner
+    amps = plan.amplitudes(bits_cuda, k=8)    # torch complex128 on the GPU
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtnc.so")
+
+TNC_OK = 0
+TNC_E_INVALID = -1
+TNC_E_DOMAIN = -2
+TNC_E_RANK = -3
+TNC_E_NOMEM = -4
+TNC_E_DEVICE = -5
+GATE_CZ = 0
+GATE_DENSE4 = 1
+STORE_C64 = 0
+
+EXPORTED = [
+    "tnc_plan", "tnc_plan_info", "tnc_prepare", "tnc_workspace_bytes", "tnc_amplitudes",
+    "tnc_amplitudes_host", "tnc_logxeb", "tnc_release", "tnc_strerror", "tnc_last_error",
+    "tnc_debug_execute_host", "tnc_debug_emulate_device",
+]
+
+
+class TncError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class c128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class Gate2(ctypes.Structure):
+    _fields_ = [("layer", ctypes.c_int32), ("q", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("m", c128 * 16)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("max_tile_bits", ctypes.c_int32), ("reg_bits", ctypes.c_int32),
+                ("low_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("boundary_bits", ctypes.c_int32),
+                ("live_slots_fixed", ctypes.c_int32), ("n_ops", ctypes.c_int32),
+                ("n_passes", ctypes.c_int32), ("n_phases", ctypes.c_int32),
+                ("n_late_launches", ctypes.c_int32), ("fixed_rows", ctypes.c_int32),
+                ("early_layers", ctypes.c_int32), ("late_layers", ctypes.c_int32),
+                ("log2_cost", ctypes.c_double), ("workspace_per_batch", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded ``libtnc.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2608_13110_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64
+    L.tnc_plan.argtypes = [i32, i32, vp, i32, vp, vp, ctypes.POINTER(vp)]
+    L.tnc_plan_info.argtypes = [vp, i32, ctypes.POINTER(Info)]
+    L.tnc_prepare.argtypes = [vp, i32]
+    L.tnc_workspace_bytes.argtypes = [vp, i32, i32, i32, ctypes.POINTER(u64)]
+    L.tnc_amplitudes.argtypes = [vp, i32, vp, i32, i32, vp, vp, u64, vp]
+    L.tnc_amplitudes_host.argtypes = [vp, i32, vp, i32, i32, vp]
+    L.tnc_logxeb.argtypes = [vp, i32, i32, vp, i32, vp, vp]
+    L.tnc_release.argtypes = [vp]
+    L.tnc_release.restype = None
+    L.tnc_strerror.argtypes = [ctypes.c_int]
+    L.tnc_strerror.restype = ctypes.c_char_p
+    L.tnc_last_error.argtypes = []
+    L.tnc_last_error.restype = ctypes.c_char_p
+    L.tnc_debug_execute_host.argtypes = [vp, i32, vp, i32, vp]
+    L.tnc_debug_emulate_device.argtypes = [vp, i32, vp, i32, vp]
+    for name in EXPORTED:
+        if name not in ("tnc_release", "tnc_strerror", "tnc_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != TNC_OK:
+        L = lib()
+        msg = L.tnc_last_error().decode() or L.tnc_strerror(rc).decode()
+        raise TncError(rc, msg)
+
+
+def _c128_array(a: np.ndarray):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a, a.ctypes.data
+
+
+class Plan:
+    """A planned circuit (``tnc_plan``); owns the library handle."""
+
+    def __init__(self, n: int, d: int, one_qubit: np.ndarray, gates: Sequence, options: Optional[dict] = None):
+        L = lib()
+        self.n, self.d = int(n), int(d)
+        one = np.ascontiguousarray(np.asarray(one_qubit, dtype=np.complex128).reshape(-1))
+        if one.size != (self.d + 1) * self.n * 4:
+            raise ValueError("one_qubit must hold (d+1)*n 2x2 gates")
+        garr = (Gate2 * max(1, len(gates)))()
+        for i, g in enumerate(gates):
+            layer, q, kind, m = g[0], g[1], g[2], g[3]
+            garr[i].layer, garr[i].q, garr[i].kind = int(layer), int(q), int(kind)
+            if kind == GATE_DENSE4:
+                mm = np.asarray(m, dtype=np.complex128).reshape(16)
+                for e in range(16):
+                    garr[i].m[e].re, garr[i].m[e].im = float(mm[e].real), float(mm[e].imag)
+        opt = None
+        if options:
+            opt = Options(int(options.get("max_tile_bits", 0)), int(options.get("reg_bits", 0)),
+                          int(options.get("low_bits", 0)), 0)
+        h = ctypes.c_void_p()
+        self._one = one
+        _check(L.tnc_plan(self.n, self.d, one.ctypes.data, len(gates), ctypes.addressof(garr),
+                          ctypes.byref(opt) if opt is not None else None, ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_circuit(cls, circ, options: Optional[dict] = None) -> "Plan":
+        """Plan any object with ``n``, ``d``, ``one_qubit`` and ``gates``."""
+        return cls(circ.n, circ.d, circ.one_qubit, circ.gates, options)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def release(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().tnc_release(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+    def info(self, k: int = 0) -> dict:
+        inf = Info()
+        _check(lib().tnc_plan_info(self._h, int(k), ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def prepare(self, k: int):
+        _check(lib().tnc_prepare(self._h, int(k)))
+
+    def workspace_bytes(self, k: int, n_batches: int, storage: int = STORE_C64) -> int:
+        out = ctypes.c_uint64()
+        _check(lib().tnc_workspace_bytes(self._h, int(k), int(n_batches), int(storage), ctypes.byref(out)))
+        return int(out.value)
+
+    # ----------------------------------------------------------- device path
+    def amplitudes(self, bits, k: int, out=None, workspace=None, stream=None, storage: int = STORE_C64):
+        """Amplitude batches on the GPU (``tnc_amplitudes``).
+
+        bits: torch uint8 (batches, n) on the device.  Returns (or fills)
+        torch complex128 (batches, 2^k).  ``workspace``: torch uint8 device
+        buffer (allocated here when None).  Enqueued on ``stream`` (default:
+        torch's current stream); no synchronization.
+        """
+        import torch
+        if bits.device.type != "cuda" or bits.dtype != torch.uint8 or not bits.is_contiguous():
+            raise ValueError("bits must be a contiguous uint8 CUDA tensor")
+        nb = int(bits.shape[0])
+        if bits.shape[1] != self.n:
+            raise ValueError("bits must have n columns")
+        if out is None:
+            out = torch.empty((nb, 1 << k), dtype=torch.complex128, device=bits.device)
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes(k, nb, storage), dtype=torch.uint8, device=bits.device)
+        s = stream if stream is not None else torch.cuda.current_stream(bits.device)
+        _check(lib().tnc_amplitudes(self._h, nb, bits.data_ptr(), int(k), int(storage), out.data_ptr(),
+                                    workspace.data_ptr(), workspace.numel(), ctypes.c_void_p(s.cuda_stream)))
+        return out
+
+    def amplitudes_host(self, bits: np.ndarray, k: int, storage: int = STORE_C64) -> np.ndarray:
+        bits = np.ascontiguousarray(bits, dtype=np.uint8)
+        out = np.empty((bits.shape[0], 1 << k), dtype=np.complex128)
+        _check(lib().tnc_amplitudes_host(self._h, bits.shape[0], bits.ctypes.data, int(k), int(storage),
+                                         out.ctypes.data))
+        return out
+
+    # ------------------------------------------------------- host self-checks
+    def debug_execute_host(self, bits: np.ndarray, k: int) -> np.ndarray:
+        bits = np.ascontiguousarray(bits, dtype=np.uint8)
+        out = np.empty((bits.shape[0], 1 << k), dtype=np.complex128)
+        _check(lib().tnc_debug_execute_host(self._h, bits.shape[0], bits.ctypes.data, int(k), out.ctypes.data))
+        return out
+
+    def debug_emulate_device(self, bits: np.ndarray, k: int) -> np.ndarray:
+        bits = np.ascontiguousarray(bits, dtype=np.uint8)
+        out = np.empty((bits.shape[0], 1 << k), dtype=np.complex128)
+        _check(lib().tnc_debug_emulate_device(self._h, bits.shape[0], bits.ctypes.data, int(k), out.ctypes.data))
+        return out
+
+
+def logxeb(amps, k: int, n_qubits: int, select=None, stream=None):
+    """log-XEB (Sec. 5.2) of device amplitudes in FP64 on the GPU.
+
+    amps: torch complex128 (batches, 2^k) on the device; select: optional
+    torch int32 (batches,) device tensor choosing one component per batch.
+    Returns a torch float64 device tensor {F, SE, lo, hi, N}.
+    """
+    import torch
+    res = torch.empty(5, dtype=torch.float64, device=amps.device)
+    s = stream if stream is not None else torch.cuda.current_stream(amps.device)
+    _check(lib().tnc_logxeb(amps.data_ptr(), int(amps.shape[0]), int(k),
+                            select.data_ptr() if select is not None else None, int(n_qubits),
+                            res.data_ptr(), ctypes.c_void_p(s.cuda_stream)))
+    return res

@@ -1,0 +1,503 @@
+// HIP kernels for gfx950 (CDNA4) of the temporal-boundary contraction.
+//
+//  k_init   row-0 build-up of the boundary tensor (one write pass)
+//  k_pass   one fused window of staircase updates over every tile of the
+//           boundary tensor (the hot loop); in place, HBM-streaming
+//  k_late   the folded late-phase contraction: the Alg. 2 join and the late
+//           layers, FP64 accumulation
+//  k_logxeb FP64 log-XEB reduction
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace tnc {
+
+// ---------------------------------------------------------------------------
+// Row-0 build-up.  The first row only creates slots: its boundary tensor is
+// the product  v[a_0] * prod_{j>=1} seg_j[a_j][a_{j-1}] * f_x[a_{m-1}]
+// (copy tensors of the down-bonds joined by the one-qubit segments).
+// Each thread writes 32 consecutive entries; factors that only involve bits
+// >= 5 are multiplied once per thread.  Entries above 2^m are zeroed.
+__device__ inline double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
+  __shared__ double2 seg[4 * 64];
+  const int nseg = a.m0 - 1;
+  for (int i = threadIdx.x; i < 4 * nseg; i += blockDim.x) seg[i] = a.seg[i];
+  __syncthreads();
+  const int per = a.h >= 5 ? 32 : 1;
+  const long long total = ((long long)a.n_batches << a.h) / per;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const long long first = gid * per;
+  const long long batch = first >> a.h;
+  const unsigned long long i0 = (unsigned long long)first & ((1ull << a.h) - 1ull);
+  float2* out = a.B + first;
+  if (i0 >= (1ull << a.m0)) {
+    for (int e = 0; e < per; ++e) out[e] = make_float2(0.f, 0.f);
+    return;
+  }
+  const int x0 = a.bits[batch * a.n];
+  const int m = a.m0;
+  // With 32 entries per thread, factors seg_j with j >= 6 (and the end vector
+  // when m-1 >= 5) only involve bits >= 5 and are multiplied once.
+  const int jsplit = per == 32 ? 6 : 1;
+  const bool f_hi = per == 32 && (m - 1) >= 5;
+  double2 hi = make_double2(1.0, 0.0);
+  for (int j = jsplit; j < m; ++j) {
+    const int aj = (int)((i0 >> j) & 1ull), ajm = (int)((i0 >> (j - 1)) & 1ull);
+    hi = zmul(hi, seg[4 * (j - 1) + 2 * aj + ajm]);
+  }
+  if (f_hi) hi = zmul(hi, a.f[x0][(i0 >> (m - 1)) & 1ull]);
+  const int jend = m < jsplit ? m : jsplit;
+  for (int e = 0; e < per; ++e) {
+    const unsigned long long i = i0 + (unsigned long long)e;
+    if (i >> m) {
+      out[e] = make_float2(0.f, 0.f);
+      continue;
+    }
+    double2 val = zmul(hi, a.v[i & 1ull]);
+    for (int j = 1; j < jend; ++j) {
+      const int aj = (int)((i >> j) & 1ull), ajm = (int)((i >> (j - 1)) & 1ull);
+      val = zmul(val, seg[4 * (j - 1) + 2 * aj + ajm]);
+    }
+    if (!f_hi) val = zmul(val, a.f[x0][(i >> (m - 1)) & 1ull]);
+    out[e] = make_float2((float)val.x, (float)val.y);
+  }
+}
+
+hipError_t launch_init(const InitArgs& a, hipStream_t s) {
+  if (a.m0 - 1 > 64) return hipErrorInvalidValue;
+  const int per = a.h >= 5 ? 32 : 1;
+  const long long threads = ((long long)a.n_batches << a.h) / per;
+  const long long blocks = (threads + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The pass kernel.  A tile is 2^T entries of one batch's boundary tensor: the
+// global slots [0, lo_bits) and [win_lo, win_lo + win_len).  A block holds
+// one tile (T - R >= 8 thread bits) or several small ones.  Data path:
+//   HBM -> LDS with 16-byte accesses along the contiguous low slots,
+//   per phase: LDS -> registers (2^R entries per thread, the phase's target
+//   slots as register bits), the phase's updates in registers, registers ->
+//   LDS,
+//   LDS -> HBM, in place.
+template <int R, bool MULTI>
+__global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
+  extern __shared__ float2 lds[];
+  constexpr int E = 1 << R;
+  const int T = a.T;
+  const int TB = T - R;
+  const int tid = threadIdx.x;
+  const int tile_in_block = MULTI ? (tid >> TB) : 0;
+  const uint32_t tt = MULTI ? (uint32_t)(tid & ((1 << TB) - 1)) : (uint32_t)tid;
+  const int tiles_per_block = MULTI ? (kBlock >> TB) : 1;
+  const long long tile = (long long)blockIdx.x * tiles_per_block + tile_in_block;
+  const bool active = tile < a.n_tiles;
+  const int tbits = a.h - T;
+  const long long batch = active ? (tile >> tbits) : 0;
+  const unsigned long long blk = active ? ((unsigned long long)tile & ((1ull << tbits) - 1ull)) : 0ull;
+  float2* __restrict__ Bt = a.B + (batch << a.h) + block_offset(blk, a.lo_bits, a.win_lo, a.win_len);
+  char* region = reinterpret_cast<char*>(lds) + ((size_t)tile_in_block << (T + 3));
+  const uint8_t* xb = a.bits + batch * a.n;
+  const int tpt = 1 << TB;
+
+  if (active) {
+#pragma unroll
+    for (int it = 0; it < E / 2; ++it) {
+      const uint32_t i = (uint32_t)(it * tpt + (int)tt) * 2u;
+      const float4 val = *reinterpret_cast<const float4*>(Bt + tile_offset(i, a.lo_bits, a.win_lo));
+      *reinterpret_cast<float4*>(region + ((size_t)swz(i) << 3)) = val;
+    }
+  }
+  __syncthreads();
+
+  float2 v[E];
+  const uint32_t tmask = (1u << T) - 1u;
+  for (int p = 0; p < a.n_phases; ++p) {
+    const DevPhase P = a.phases[p];
+    uint32_t rm[R];
+    uint32_t rmask = 0;
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+      rm[b] = 1u << P.reg[b];
+      rmask |= rm[b];
+    }
+    const uint32_t tb = pdep32(tt, tmask & ~rmask);
+    const uint32_t vbase = swz(tb) << 3;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      uint32_t r = 0;
+#pragma unroll
+      for (int b = 0; b < R; ++b)
+        if (i & (1 << b)) r |= rm[b];
+      v[i] = *reinterpret_cast<const float2*>(region + (vbase ^ (swz(r) << 3)));
+    }
+    run_phase_ops<R>(v, P, a.ops, a.mats, xb, tb);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      uint32_t r = 0;
+#pragma unroll
+      for (int b = 0; b < R; ++b)
+        if (i & (1 << b)) r |= rm[b];
+      *reinterpret_cast<float2*>(region + (vbase ^ (swz(r) << 3))) = v[i];
+    }
+    __syncthreads();
+  }
+
+  if (active) {
+#pragma unroll
+    for (int it = 0; it < E / 2; ++it) {
+      const uint32_t i = (uint32_t)(it * tpt + (int)tt) * 2u;
+      const float4 val = *reinterpret_cast<const float4*>(region + ((size_t)swz(i) << 3));
+      *reinterpret_cast<float4*>(Bt + tile_offset(i, a.lo_bits, a.win_lo)) = val;
+    }
+  }
+}
+
+template <int R>
+static hipError_t launch_pass_r(const PassArgs& a, hipStream_t s) {
+  const int TB = a.T - R;
+  if (TB < 0 || TB > 8) return hipErrorInvalidValue;
+  const bool multi = TB < 8;
+  const int tiles_per_block = multi ? (kBlock >> TB) : 1;
+  const long long blocks = ((long long)a.n_tiles + tiles_per_block - 1) / tiles_per_block;
+  const size_t lds = (size_t)kBlock * (1 << R) * sizeof(float2);
+  if (multi) {
+    hipLaunchKernelGGL((k_pass<R, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+  } else {
+    hipLaunchKernelGGL((k_pass<R, false>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pass(const PassArgs& a, int R, hipStream_t s) {
+  switch (R) {
+    case 1: return launch_pass_r<1>(a, s);
+    case 2: return launch_pass_r<2>(a, s);
+    case 3: return launch_pass_r<3>(a, s);
+    case 4: return launch_pass_r<4>(a, s);
+    case 5: return launch_pass_r<5>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Host emulation with the same helpers and the same LDS placement.
+template <int R>
+static void emulate_pass_r(const PassArgs& a) {
+  constexpr int E = 1 << R;
+  const int T = a.T, TB = T - R;
+  const int tpt = 1 << TB;
+  const int tbits = a.h - T;
+  std::vector<float2> lds((size_t)1 << T);
+  char* region = reinterpret_cast<char*>(lds.data());
+  std::vector<float2> regs((size_t)tpt * E);
+  const uint32_t tmask = (1u << T) - 1u;
+  for (long long tile = 0; tile < a.n_tiles; ++tile) {
+    const long long batch = tile >> tbits;
+    const unsigned long long blk = (unsigned long long)tile & ((1ull << tbits) - 1ull);
+    float2* Bt = a.B + (batch << a.h) + block_offset(blk, a.lo_bits, a.win_lo, a.win_len);
+    const uint8_t* xb = a.bits + batch * a.n;
+    for (int tt = 0; tt < tpt; ++tt)
+      for (int it = 0; it < E / 2; ++it) {
+        const uint32_t i = (uint32_t)(it * tpt + tt) * 2u;
+        const float2* src = Bt + tile_offset(i, a.lo_bits, a.win_lo);
+        float2* dst = reinterpret_cast<float2*>(region + ((size_t)swz(i) << 3));
+        dst[0] = src[0];
+        dst[1] = src[1];
+      }
+    for (int p = 0; p < a.n_phases; ++p) {
+      const DevPhase P = a.phases[p];
+      uint32_t rm[R];
+      uint32_t rmask = 0;
+      for (int b = 0; b < R; ++b) {
+        rm[b] = 1u << P.reg[b];
+        rmask |= rm[b];
+      }
+      for (int tt = 0; tt < tpt; ++tt) {
+        float2 v[E];
+        const uint32_t tb = pdep32((uint32_t)tt, tmask & ~rmask);
+        const uint32_t vbase = swz(tb) << 3;
+        for (int i = 0; i < E; ++i) {
+          uint32_t r = 0;
+          for (int b = 0; b < R; ++b)
+            if (i & (1 << b)) r |= rm[b];
+          v[i] = *reinterpret_cast<const float2*>(region + (vbase ^ (swz(r) << 3)));
+        }
+        run_phase_ops<R>(v, P, a.ops, a.mats, xb, tb);
+        for (int i = 0; i < E; ++i) {
+          uint32_t r = 0;
+          for (int b = 0; b < R; ++b)
+            if (i & (1 << b)) r |= rm[b];
+          *reinterpret_cast<float2*>(region + (vbase ^ (swz(r) << 3))) = v[i];
+        }
+      }
+    }
+    for (int tt = 0; tt < tpt; ++tt)
+      for (int it = 0; it < E / 2; ++it) {
+        const uint32_t i = (uint32_t)(it * tpt + tt) * 2u;
+        const float2* src = reinterpret_cast<const float2*>(region + ((size_t)swz(i) << 3));
+        float2* dst = Bt + tile_offset(i, a.lo_bits, a.win_lo);
+        dst[0] = src[0];
+        dst[1] = src[1];
+      }
+  }
+}
+
+void emulate_pass_host(const PassArgs& a, int R) {
+  switch (R) {
+    case 1: emulate_pass_r<1>(a); break;
+    case 2: emulate_pass_r<2>(a); break;
+    case 3: emulate_pass_r<3>(a); break;
+    case 4: emulate_pass_r<4>(a); break;
+    case 5: emulate_pass_r<5>(a); break;
+    default: break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Late phase: out[b][r][c] = sum_kk in[b][r][kk] * J[var][kk][c] in FP64.
+// J folds, on the host, the early-region tensor Z_early (first launch), the
+// late layers' one- and two-qubit gates and the removal of the crossing
+// bonds between the fixed rows and the open band (Alg. 2).  Tiled 64 x 64
+// per block, K in steps of 16, 4 x 4 complex accumulators per thread.
+__device__ inline double2 to_d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
+__device__ inline double2 to_d2(double2 v) { return v; }
+
+template <typename TIn>
+__global__ __launch_bounds__(kBlock) void k_late(LateArgs a) {
+  __shared__ double2 As[16][65];
+  __shared__ double2 Bs[16][65];
+  const int b = blockIdx.y;
+  const int tilesN = (a.N + 63) / 64;
+  const int tilesM = (a.M + 63) / 64;
+  // Consecutive block ids go to different XCDs (round robin over 8); the
+  // tilesN column blocks of one row tile are given ids that land on the
+  // same XCD, so they share its L2 for the row tile.
+  const int xcd = blockIdx.x & 7;
+  const int g = blockIdx.x >> 3;
+  const int bn = g % tilesN;
+  const int bm = (g / tilesN) * 8 + xcd;
+  if (bm >= tilesM) return;
+  const int row0 = bm * 64, col0 = bn * 64;
+  const int var = a.xrow >= 0 ? (int)a.bits[(size_t)b * a.n + a.xrow] : 0;
+  const double2* __restrict__ J = a.J + (size_t)var * a.K * a.N;
+  const TIn* __restrict__ in = reinterpret_cast<const TIn*>(a.in) + (size_t)b * a.in_batch_stride;
+  const int tid = threadIdx.x;
+  const int tr = tid >> 4, tc = tid & 15;
+  double2 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < a.K; k0 += 16) {
+    for (int e = tid; e < 1024; e += kBlock) {
+      const int r = e >> 4, kk = e & 15;
+      const int row = row0 + r;
+      double2 val = make_double2(0.0, 0.0);
+      if (row < a.M && k0 + kk < a.K) val = to_d2(in[(size_t)row * a.K + k0 + kk]);
+      As[kk][r] = val;
+    }
+    for (int e = tid; e < 1024; e += kBlock) {
+      const int kk = e >> 6, c = e & 63;
+      const int col = col0 + c;
+      double2 val = make_double2(0.0, 0.0);
+      if (col < a.N && k0 + kk < a.K) val = J[(size_t)(k0 + kk) * a.N + col];
+      Bs[kk][c] = val;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      double2 av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[kk][tr * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tc * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j].x += av[i].x * bv[j].x - av[i].y * bv[j].y;
+          acc[i][j].y += av[i].x * bv[j].y + av[i].y * bv[j].x;
+        }
+    }
+    __syncthreads();
+  }
+  double2* out = a.out + (size_t)b * a.out_batch_stride;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = row0 + tr * 4 + i;
+    if (row >= a.M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = col0 + tc * 4 + j;
+      if (col < a.N) out[(size_t)row * a.N + col] = acc[i][j];
+    }
+  }
+}
+
+hipError_t launch_late(const LateArgs& a, bool in_c64, hipStream_t s) {
+  const long long tilesM8 = ((long long)(a.M + 63) / 64 + 7) / 8 * 8;
+  const long long tiles = tilesM8 * ((a.N + 63) / 64);
+  if (tiles > 0x7fffffffLL || a.n_batches > 65535) return hipErrorInvalidValue;
+  dim3 grid((unsigned)tiles, (unsigned)a.n_batches);
+  if (in_c64) hipLaunchKernelGGL(k_late<float2>, grid, dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL(k_late<double2>, grid, dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Late program on the shrinking tensor, FP64.  A block loads 2^j consecutive
+// rows of 2^s state entries into LDS; one- and two-qubit gates act on the
+// state bits of every live row, a removal sums the lowest remaining row bit
+// against C_u on state bit 0 (Alg. 2, the late ContractLayer steps).  After
+// l removals the live rows are those whose low l row bits are zero.
+__device__ inline double2 zfma2(double2 m0, double2 x0, double2 m1, double2 x1) {
+  return make_double2(m0.x * x0.x - m0.y * x0.y + m1.x * x1.x - m1.y * x1.y,
+                      m0.x * x0.y + m0.y * x0.x + m1.x * x1.y + m1.y * x1.x);
+}
+
+__device__ inline int insert_zero(int x, int bit) {
+  const int lo = x & ((1 << bit) - 1);
+  return ((x - lo) << 1) | lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_late_ops(LateOpsArgs a) {
+  extern __shared__ double2 st[];
+  const long long row_out = blockIdx.x;
+  const int b = blockIdx.y;
+  const int sb = a.s;
+  const int total = 1 << (sb + a.j);
+  const double2* in = a.in + (size_t)b * a.in_batch_stride + ((size_t)row_out << (a.j + sb));
+  for (int i = threadIdx.x; i < total; i += blockDim.x) st[i] = in[i];
+  __syncthreads();
+  int l = 0;
+  for (int o = 0; o < a.n_prog; ++o) {
+    const LateOpDev& op = a.prog[o];
+    const int live = a.j - l;
+    if (op.kind == 1) {
+      const int items = (1 << live) << (sb - 1);
+      for (int w = threadIdx.x; w < items; w += blockDim.x) {
+        const int r = (w >> (sb - 1)) << l;
+        const int t0 = insert_zero(w & ((1 << (sb - 1)) - 1), op.a);
+        const int i0 = (r << sb) | t0, i1 = i0 | (1 << op.a);
+        const double2 x0 = st[i0], x1 = st[i1];
+        st[i0] = zfma2(op.m[0], x0, op.m[1], x1);
+        st[i1] = zfma2(op.m[2], x0, op.m[3], x1);
+      }
+    } else if (op.kind == 2) {
+      const int items = (1 << live) << (sb - 2);
+      for (int w = threadIdx.x; w < items; w += blockDim.x) {
+        const int r = (w >> (sb - 2)) << l;
+        const int t0 = insert_zero(insert_zero(w & ((1 << (sb - 2)) - 1), op.a), op.a + 1);
+        const int base = (r << sb) | t0;
+        const int idx[4] = {base, base | (1 << (op.a + 1)), base | (1 << op.a), base | (3 << op.a)};
+        double2 x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = st[idx[u]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double2 p0 = zfma2(op.m[4 * q + 0], x[0], op.m[4 * q + 1], x[1]);
+          const double2 p1 = zfma2(op.m[4 * q + 2], x[2], op.m[4 * q + 3], x[3]);
+          y[q] = make_double2(p0.x + p1.x, p0.y + p1.y);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) st[idx[u]] = y[u];
+      }
+    } else if (op.kind == 3) {
+      const int items = (1 << (live - 1)) << (sb - 1);
+      for (int w = threadIdx.x; w < items; w += blockDim.x) {
+        const int ra = (w >> (sb - 1)) << (l + 1);
+        const int rb = ra | (1 << l);
+        const int t0 = (w & ((1 << (sb - 1)) - 1)) << 1;
+        const int ia = (ra << sb) | t0, ib = (rb << sb) | t0;
+        const double2 x0 = st[ia], x1 = st[ia | 1], y0 = st[ib], y1 = st[ib | 1];
+        const double2 o0a = zfma2(op.m[0], x0, op.m[1], x1), o0b = zfma2(op.m[4], y0, op.m[5], y1);
+        const double2 o1a = zfma2(op.m[2], x0, op.m[3], x1), o1b = zfma2(op.m[6], y0, op.m[7], y1);
+        st[ia] = make_double2(o0a.x + o0b.x, o0a.y + o0b.y);
+        st[ia | 1] = make_double2(o1a.x + o1b.x, o1a.y + o1b.y);
+      }
+      ++l;
+    }
+    __syncthreads();
+  }
+  double2* out = a.out + (size_t)b * a.out_batch_stride;
+  if (a.final_kind == 5) {
+    for (int bb = threadIdx.x; bb < (1 << a.k); bb += blockDim.x) {
+      int t = 0;
+      for (int q = 0; q < a.k; ++q) t |= ((bb >> (a.k - 1 - q)) & 1) << q;
+      out[bb] = st[t];
+    }
+  } else if (a.final_kind == 4) {
+    if (threadIdx.x == 0) {
+      const int x = a.bits[(size_t)b * a.n + a.final_xrow];
+      out[0] = zfma2(a.dot[x][0], st[0], a.dot[x][1], st[1]);
+    }
+  } else {
+    for (int t = threadIdx.x; t < (1 << sb); t += blockDim.x) out[((size_t)row_out << sb) + t] = st[t];
+  }
+}
+
+hipError_t launch_late_ops(const LateOpsArgs& a, hipStream_t s) {
+  if (a.s + a.j > 12 || a.rows_out > 0x7fffffffLL || a.n_batches > 65535) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double2) << (a.s + a.j);
+  hipLaunchKernelGGL(k_late_ops, dim3((unsigned)a.rows_out, (unsigned)a.n_batches), dim3(kBlock), lds, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// log-XEB (Sec. 5.2): F = gamma + n ln 2 + mean_i ln p_i with p_i = |amp|^2
+// of the selected component of each batch (sel == nullptr: every component).
+// One block, FP64 throughout.  result = {F, SE, F - 1.96 SE, F + 1.96 SE, N}.
+__global__ __launch_bounds__(kBlock) void k_logxeb(const double2* amps, int n_batches, int k,
+                                                   const int32_t* sel, int n_qubits, double* result) {
+  __shared__ double s1[kBlock], s2[kBlock];
+  const long long per = 1ll << k;
+  const long long total = sel ? (long long)n_batches : (long long)n_batches * per;
+  double a1 = 0.0, a2 = 0.0;
+  for (long long i = threadIdx.x; i < total; i += blockDim.x) {
+    const long long idx = sel ? (i * per + sel[i]) : i;
+    const double2 z = amps[idx];
+    const double lp = log(z.x * z.x + z.y * z.y);
+    a1 += lp;
+    a2 += lp * lp;
+  }
+  s1[threadIdx.x] = a1;
+  s2[threadIdx.x] = a2;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      s1[threadIdx.x] += s1[threadIdx.x + off];
+      s2[threadIdx.x] += s2[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double N = (double)total;
+    const double mean = s1[0] / N;
+    const double var = N > 1 ? (s2[0] - N * mean * mean) / (N - 1.0) : 0.0;
+    const double se = N > 1 ? sqrt(var > 0 ? var : 0.0) / sqrt(N) : 0.0;
+    const double gamma = 0.57721566490153286060651209008240243;
+    const double F = gamma + (double)n_qubits * 0.69314718055994530941723212145817657 + mean;
+    result[0] = F;
+    result[1] = se;
+    result[2] = F - 1.96 * se;
+    result[3] = F + 1.96 * se;
+    result[4] = N;
+  }
+}
+
+hipError_t launch_logxeb(const double2* amps, int n_batches, int k, const int32_t* sel, int n_qubits,
+                         double* result, hipStream_t s) {
+  hipLaunchKernelGGL(k_logxeb, dim3(1), dim3(kBlock), 0, s, amps, n_batches, k, sel, n_qubits, result);
+  return hipGetLastError();
+}
+
+}  // namespace tnc

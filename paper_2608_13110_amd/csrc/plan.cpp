@@ -1,0 +1,927 @@
+// Host planner: lowering of the brickwork tensor network into the boundary
+// tensor schedule (see plan.hpp for the formulation).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <set>
+#include <sstream>
+
+namespace tnc {
+
+namespace {
+constexpr int kErrInvalid = -1;
+constexpr int kErrDomain = -2;
+constexpr int kErrRank = -3;
+// The host folds the 2^k x 2^k early-region tensor into the first late
+// launch at O(2^(3k)) cost, which bounds k.
+constexpr int kMaxOpenLegs = 10;
+
+int fail(std::string* err, int code, const std::string& msg) {
+  if (err) *err = msg;
+  return code;
+}
+
+M2 diag(cd a, cd b) {
+  M2 m;
+  m.a[0] = a; m.a[1] = 0; m.a[2] = 0; m.a[3] = b;
+  return m;
+}
+
+M2 inverse(const M2& m) {
+  cd det = m.a[0] * m.a[3] - m.a[1] * m.a[2];
+  M2 r;
+  r.a[0] = m.a[3] / det; r.a[1] = -m.a[1] / det;
+  r.a[2] = -m.a[2] / det; r.a[3] = m.a[0] / det;
+  return r;
+}
+
+cd det2(const M2& m) { return m.a[0] * m.a[3] - m.a[1] * m.a[2]; }
+
+M2 add(const M2& x, const M2& y, cd s = 1.0) {
+  M2 r;
+  for (int i = 0; i < 4; ++i) r.a[i] = x.a[i] + s * y.a[i];
+  return r;
+}
+
+// row vector f times matrix m: (f m)[j] = sum_i f[i] m[i][j]
+void rowvec_mul(const cd f[2], const M2& m, cd out[2]) {
+  out[0] = f[0] * m(0, 0) + f[1] * m(1, 0);
+  out[1] = f[0] * m(0, 1) + f[1] * m(1, 1);
+}
+
+void mat_vec(const M2& m, const cd v[2], cd out[2]) {
+  out[0] = m(0, 0) * v[0] + m(0, 1) * v[1];
+  out[1] = m(1, 0) * v[0] + m(1, 1) * v[1];
+}
+
+double maxabs(const cd* a, int n) {
+  double m = 0;
+  for (int i = 0; i < n; ++i) m = std::max(m, std::abs(a[i]));
+  return m;
+}
+}  // namespace
+
+M2 operator*(const M2& x, const M2& y) {
+  M2 r;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) r(i, j) = x(i, 0) * y(0, j) + x(i, 1) * y(1, j);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Entangler decomposition.  A rank-<=2 operator U = A_0 (x) B_0 + A_1 (x) B_1
+// (found by rank-revealing elimination of the realigned 4x4) is brought to
+// U = (A_0 V (x) I)[sum_a P_a (x) (B_0 + m_a B_1)](V^-1 (x) I) where
+// A_0^-1 A_1 = V diag(m) V^-1.
+int split_entangler(const cd* u, Split* s, std::string* err) {
+  // realigned R[(a a')][(b b')] = U[2a+b][2a'+b']
+  cd R[4][4];
+  for (int a = 0; a < 2; ++a)
+    for (int ap = 0; ap < 2; ++ap)
+      for (int b = 0; b < 2; ++b)
+        for (int bp = 0; bp < 2; ++bp) R[2 * a + ap][2 * b + bp] = u[4 * (2 * a + b) + (2 * ap + bp)];
+  double scale = 0;
+  for (auto& row : R)
+    for (auto& v : row) scale = std::max(scale, std::abs(v));
+  if (scale == 0) return fail(err, kErrRank, "entangler is the zero operator");
+  const double tol = 1e-10 * scale;
+  cd col[2][4], rowv[2][4];
+  int rank = 0;
+  cd W[4][4];
+  std::memcpy(W, R, sizeof(W));
+  for (int step = 0; step < 3; ++step) {
+    int pi = 0, pj = 0;
+    double best = -1;
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        if (std::abs(W[i][j]) > best) { best = std::abs(W[i][j]); pi = i; pj = j; }
+    if (best <= tol) break;
+    if (step == 2) return fail(err, kErrRank, "entangler has operator Schmidt rank > 2");
+    cd piv = W[pi][pj];
+    for (int i = 0; i < 4; ++i) { col[step][i] = W[i][pj]; rowv[step][i] = W[pi][i] / piv; }
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) W[i][j] -= col[step][i] * rowv[step][j];
+    rank = step + 1;
+  }
+  M2 A[2], B[2];
+  for (int t = 0; t < 2; ++t) {
+    A[t] = M2::zero();
+    B[t] = M2::zero();
+  }
+  for (int t = 0; t < rank; ++t)
+    for (int i = 0; i < 4; ++i) { A[t].a[i] = col[t][i]; B[t].a[i] = rowv[t][i]; }
+  // make A_0 invertible by re-mixing the Schmidt pair
+  if (std::abs(det2(A[0])) < 1e-9 * std::max(1e-300, std::norm(A[0].a[0]) + std::norm(A[0].a[1]) +
+                                                        std::norm(A[0].a[2]) + std::norm(A[0].a[3]))) {
+    const cd ts[] = {cd(1), cd(-1), cd(0, 1), cd(2), cd(0, -2), cd(0.5, 0.5)};
+    double bestd = -1;
+    cd bt = 0;
+    for (cd t : ts) {
+      double dd = std::abs(det2(add(A[0], A[1], t)));
+      if (dd > bestd) { bestd = dd; bt = t; }
+    }
+    if (bestd < 1e-12 * scale * scale) return fail(err, kErrRank, "entangler has no copy form (singular Schmidt factors)");
+    A[0] = add(A[0], A[1], bt);
+    B[1] = add(B[1], B[0], -bt);
+  }
+  M2 Mm = inverse(A[0]) * A[1];
+  cd tr = Mm.a[0] + Mm.a[3], dt = det2(Mm);
+  cd disc = std::sqrt(tr * tr - 4.0 * dt);
+  cd lam[2] = {(tr + disc) / 2.0, (tr - disc) / 2.0};
+  M2 V;
+  double mscale = std::max(1.0, maxabs(Mm.a, 4));
+  if (std::abs(lam[0] - lam[1]) > 1e-8 * mscale) {
+    for (int e = 0; e < 2; ++e) {
+      cd v1[2] = {Mm(0, 1), lam[e] - Mm(0, 0)};
+      cd v2[2] = {lam[e] - Mm(1, 1), Mm(1, 0)};
+      double n1 = std::norm(v1[0]) + std::norm(v1[1]), n2 = std::norm(v2[0]) + std::norm(v2[1]);
+      const cd* v = n1 >= n2 ? v1 : v2;
+      double nn = std::sqrt(std::max(n1, n2));
+      V(0, e) = v[0] / nn;
+      V(1, e) = v[1] / nn;
+    }
+  } else {
+    if (std::abs(Mm(0, 1)) > 1e-8 * mscale || std::abs(Mm(1, 0)) > 1e-8 * mscale ||
+        std::abs(Mm(0, 0) - Mm(1, 1)) > 1e-8 * mscale)
+      return fail(err, kErrRank, "entangler has no copy form (defective Schmidt pencil)");
+    V = M2();
+  }
+  s->pre = inverse(V);
+  s->post = A[0] * V;
+  s->C[0] = add(B[0], B[1], lam[0]);
+  s->C[1] = add(B[0], B[1], lam[1]);
+  // verify the reconstruction
+  double worst = 0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int ap = 0; ap < 2; ++ap)
+        for (int bp = 0; bp < 2; ++bp) {
+          cd acc = 0;
+          for (int al = 0; al < 2; ++al) acc += s->post(a, al) * s->pre(al, ap) * s->C[al](b, bp);
+          worst = std::max(worst, std::abs(acc - u[4 * (2 * a + b) + (2 * ap + bp)]));
+        }
+  if (worst > 1e-8 * scale) return fail(err, kErrRank, "entangler decomposition failed to reconstruct");
+  return 0;
+}
+
+namespace {
+
+Split cz_split() {
+  Split s;
+  s.C[0] = M2();
+  s.C[1] = diag(1.0, -1.0);
+  return s;
+}
+
+struct Event {
+  int layer;
+  bool up;  // true: consumes a slot of cut r-1 (row r is the lower qubit)
+  int slot;
+  const Split* sp;
+};
+
+struct RowChain {
+  std::vector<Event> ev;
+  cd v[2];              // start vector entering e_1
+  std::vector<M2> seg;  // seg[i] between ev[i] and ev[i+1]  (size M-1)
+  cd f[2][2];           // end row vector after ev[M-1], per output bit
+};
+
+int pair_index(const Plan& p, int layer, int cut) { return (layer - 1) * (p.n - 1) + cut; }
+
+bool in_pattern(const Plan& p, int layer, int cut) {
+  return ((p.parity1 + layer - 1) & 1) == (cut & 1);
+}
+
+// product L_{b-1} ... L_a on row r (identity when a == b)
+M2 prod1q(const Plan& p, int r, int a, int b) {
+  M2 m;
+  for (int l = a; l < b; ++l) m = p.one[(size_t)l * p.n + r] * m;
+  return m;
+}
+
+RowChain build_chain(const Plan& p, int r) {
+  RowChain rc;
+  for (int l = 1; l <= p.d; ++l) {
+    if (r >= 1 && in_pattern(p, l, r - 1)) {
+      const auto& X = p.X[r - 1];
+      int s = int(std::lower_bound(X.begin(), X.end(), l) - X.begin());
+      rc.ev.push_back({l, true, s, &p.split[pair_index(p, l, r - 1)]});
+    } else if (r <= p.n - 2 && in_pattern(p, l, r)) {
+      const auto& X = p.X[r];
+      int s = int(std::lower_bound(X.begin(), X.end(), l) - X.begin());
+      rc.ev.push_back({l, false, s, &p.split[pair_index(p, l, r)]});
+    }
+  }
+  const int M = int(rc.ev.size());
+  // start vector
+  {
+    M2 m = prod1q(p, r, 0, rc.ev[0].layer);
+    if (!rc.ev[0].up) m = rc.ev[0].sp->pre * m;
+    rc.v[0] = m(0, 0);
+    rc.v[1] = m(1, 0);
+  }
+  for (int i = 0; i + 1 < M; ++i) {
+    M2 m = prod1q(p, r, rc.ev[i].layer, rc.ev[i + 1].layer);
+    if (!rc.ev[i].up) m = m * rc.ev[i].sp->post;
+    if (!rc.ev[i + 1].up) m = rc.ev[i + 1].sp->pre * m;
+    rc.seg.push_back(m);
+  }
+  {
+    M2 m = prod1q(p, r, rc.ev[M - 1].layer, p.d + 1);
+    if (!rc.ev[M - 1].up) m = m * rc.ev[M - 1].sp->post;
+    for (int x = 0; x < 2; ++x) {
+      rc.f[x][0] = m(x, 0);
+      rc.f[x][1] = m(x, 1);
+    }
+  }
+  return rc;
+}
+
+// K[alpha][beta] = (Lm * C_beta * Rm)[rowsel][colsel] variants
+// a_of: function giving the matrix for (control a): returns M2 over (alpha, beta)
+SweepOp make_op(int target, int control, int row) {
+  SweepOp op;
+  op.target = target;
+  op.control = control;
+  op.row = row;
+  for (auto& v : op.mat)
+    for (auto& m : v) m = M2::zero();
+  return op;
+}
+
+// Ops of middle row r.
+int build_row_ops(const Plan& p, int r, std::vector<SweepOp>* ops, int* ascending, std::string* err) {
+  RowChain rc = build_chain(p, r);
+  const auto& ev = rc.ev;
+  const int M = int(ev.size());
+  // events must alternate up/down
+  for (int i = 0; i + 1 < M; ++i)
+    if (ev[i].up == ev[i + 1].up) return fail(err, kErrInvalid, "row events do not alternate");
+  if (M < 2) return fail(err, kErrInvalid, "middle row with fewer than two events");
+  ops->clear();
+  if (ev[0].up) {
+    *ascending = 1;
+    // pairs (ev[2j] up, ev[2j+1] down)
+    int npairs = M / 2;
+    for (int j = 0; j < npairs; ++j) {
+      const Event& up = ev[2 * j];
+      const Event& dn = ev[2 * j + 1];
+      if (up.slot != j || dn.slot != j) return fail(err, kErrInvalid, "slot schedule mismatch (asc)");
+      SweepOp op = make_op(j, j == 0 ? -1 : j - 1, r);
+      for (int a = 0; a < (j == 0 ? 1 : 2); ++a) {
+        for (int beta = 0; beta < 2; ++beta) {
+          cd in[2];
+          if (j == 0) {
+            in[0] = rc.v[0];
+            in[1] = rc.v[1];
+          } else {
+            in[0] = rc.seg[2 * j - 1](0, a);
+            in[1] = rc.seg[2 * j - 1](1, a);
+          }
+          cd t1[2], t2[2];
+          mat_vec(up.sp->C[beta], in, t1);
+          mat_vec(rc.seg[2 * j], t1, t2);
+          for (int al = 0; al < 2; ++al) op.mat[0][a](al, beta) = t2[al];
+        }
+      }
+      if (j == 0) op.mat[0][1] = op.mat[0][0];
+      ops->push_back(op);
+    }
+    if (M % 2 == 0) {
+      // ends with a down event: scale rows by f_x
+      SweepOp& last = ops->back();
+      last.xrow[0] = r;
+      const M2 base[2] = {last.mat[0][0], last.mat[0][1]};
+      for (int x = 0; x < 2; ++x)
+        for (int a = 0; a < 2; ++a) {
+          M2 m = base[a];
+          for (int al = 0; al < 2; ++al)
+            for (int be = 0; be < 2; ++be) m(al, be) *= rc.f[x][al];
+          last.mat[2 * x][a] = m;
+        }
+    } else {
+      // ends with an up event in slot J: remove it, controlled by slot J-1
+      int J = M / 2;
+      const Event& up = ev[M - 1];
+      if (up.slot != J || J < 1) return fail(err, kErrInvalid, "slot schedule mismatch (remove)");
+      SweepOp op = make_op(J, J - 1, r);
+      op.xrow[0] = r;
+      for (int x = 0; x < 2; ++x)
+        for (int a = 0; a < 2; ++a)
+          for (int beta = 0; beta < 2; ++beta) {
+            cd t1[2], t2[2];
+            rowvec_mul(rc.f[x], up.sp->C[beta], t1);
+            rowvec_mul(t1, rc.seg[M - 2], t2);
+            op.mat[2 * x][a](0, beta) = t2[a];
+            op.mat[2 * x][a](1, beta) = 0;
+          }
+      ops->push_back(op);
+    }
+  } else {
+    *ascending = 0;
+    int idx = M - 1;  // walk backward in time
+    bool first = true;
+    if (!ev[M - 1].up) {
+      // odd-depth turn: expand a new top slot (the last down event)
+      int J = M / 2;  // M = 2J+1
+      const Event& dtop = ev[M - 1];
+      if (dtop.slot != J) return fail(err, kErrInvalid, "slot schedule mismatch (expand)");
+      SweepOp dup = make_op(J, -1, r);
+      dup.kind = OP_DUP;
+      ops->push_back(dup);
+      const Event& up = ev[M - 2];
+      const Event& dn = ev[M - 3];
+      if (up.slot != J - 1 || dn.slot != J - 1) return fail(err, kErrInvalid, "slot schedule mismatch (expand pair)");
+      SweepOp op = make_op(J - 1, J, r);
+      op.xrow[0] = r;
+      for (int x = 0; x < 2; ++x)
+        for (int a = 0; a < 2; ++a) {
+          M2 K = rc.seg[M - 2] * up.sp->C[0];  // placeholder, overwritten below
+          for (int beta = 0; beta < 2; ++beta) {
+            M2 prod = rc.seg[M - 2] * up.sp->C[beta] * rc.seg[M - 3];
+            for (int al = 0; al < 2; ++al) op.mat[2 * x][a](al, beta) = rc.f[x][a] * prod(a, al);
+          }
+          (void)K;
+        }
+      ops->push_back(op);
+      idx = M - 4;
+      first = false;
+    }
+    // remaining pairs (ev[idx] up, ev[idx-1] down), idx odd, going down
+    for (; idx >= 1; idx -= 2) {
+      const Event& up = ev[idx];
+      const Event& dn = ev[idx - 1];
+      int j = up.slot;
+      if (dn.slot != j || !up.up || dn.up) return fail(err, kErrInvalid, "slot schedule mismatch (desc)");
+      if (first) {
+        SweepOp op = make_op(j, -1, r);
+        op.xrow[0] = r;
+        for (int x = 0; x < 2; ++x)
+          for (int beta = 0; beta < 2; ++beta) {
+            cd t1[2], t2[2];
+            rowvec_mul(rc.f[x], up.sp->C[beta], t1);
+            rowvec_mul(t1, rc.seg[idx - 1], t2);
+            for (int al = 0; al < 2; ++al) op.mat[2 * x][0](al, beta) = t2[al];
+            op.mat[2 * x][1] = op.mat[2 * x][0];
+          }
+        ops->push_back(op);
+        first = false;
+      } else {
+        SweepOp op = make_op(j, j + 1, r);
+        for (int a = 0; a < 2; ++a)
+          for (int beta = 0; beta < 2; ++beta) {
+            M2 prod = rc.seg[idx] * up.sp->C[beta] * rc.seg[idx - 1];
+            for (int al = 0; al < 2; ++al) op.mat[0][a](al, beta) = prod(a, al);
+          }
+        ops->push_back(op);
+      }
+    }
+    if (idx != -1) return fail(err, kErrInvalid, "descending row pairing mismatch");
+    // multiply the last op's output rows by the start vector v
+    SweepOp& last = ops->back();
+    for (int var = 0; var < 4; ++var)
+      for (int a = 0; a < 2; ++a)
+        for (int al = 0; al < 2; ++al)
+          for (int be = 0; be < 2; ++be) last.mat[var][a](al, be) *= rc.v[al];
+  }
+  // replicate unused variants
+  for (auto& op : *ops) {
+    if (op.kind != OP_CU) continue;
+    if (op.xrow[0] < 0) op.mat[2][0] = op.mat[0][0], op.mat[2][1] = op.mat[0][1];
+    op.mat[1][0] = op.mat[0][0];
+    op.mat[1][1] = op.mat[0][1];
+    op.mat[3][0] = op.mat[2][0];
+    op.mat[3][1] = op.mat[2][1];
+  }
+  return 0;
+}
+
+// Merge B (a no-control CU on A's target) into A: result = B * A.
+SweepOp merge_ops(const SweepOp& A, const SweepOp& B) {
+  SweepOp r = A;
+  int xa = A.xrow[0], xb = B.xrow[0];
+  r.xrow[0] = xa;
+  r.xrow[1] = xb;
+  for (int x0 = 0; x0 < 2; ++x0)
+    for (int x1 = 0; x1 < 2; ++x1) {
+      int var = 2 * x0 + x1;
+      for (int a = 0; a < 2; ++a) r.mat[var][a] = B.mat[2 * x1][0] * A.mat[2 * x0][a];
+    }
+  return r;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+int build_plan(int n, int d, const cd* one_qubit, int n_gate2, const Gate2In* gates,
+               const Options& opt, std::unique_ptr<Plan>* out, std::string* err) {
+  if (n < 2 || d < 2) return fail(err, kErrDomain, "need n >= 2 qubits and d >= 2 layers");
+  if (n > 4096 || d > 4096) return fail(err, kErrDomain, "n or d too large");
+  auto p = std::make_unique<Plan>();
+  p->n = n;
+  p->d = d;
+  p->opt = opt;
+  p->one.resize((size_t)(d + 1) * n);
+  for (size_t i = 0; i < p->one.size(); ++i)
+    for (int e = 0; e < 4; ++e) p->one[i].a[e] = one_qubit[4 * i + e];
+  // brickwork parity from the first gate
+  p->parity1 = 1;
+  if (n_gate2 > 0) p->parity1 = ((gates[0].q - (gates[0].layer - 1)) % 2 + 2) % 2;
+  p->split.assign((size_t)d * (n - 1), Split());
+  p->g4.assign((size_t)d * (n - 1), std::vector<cd>());
+  std::vector<char> seen((size_t)d * (n - 1), 0);
+  const Split idsplit;  // identity entangler: C_0 = C_1 = I
+  Split identity;
+  identity.C[0] = M2();
+  identity.C[1] = M2();
+  for (int i = 0; i < n_gate2; ++i) {
+    const Gate2In& g = gates[i];
+    if (g.layer < 1 || g.layer > d || g.q < 0 || g.q > n - 2)
+      return fail(err, kErrInvalid, "gate out of range");
+    if (!in_pattern(*p, g.layer, g.q))
+      return fail(err, kErrInvalid, "gate breaks the alternating brickwork pattern");
+    size_t pi = (size_t)pair_index(*p, g.layer, g.q);
+    if (seen[pi]) return fail(err, kErrInvalid, "duplicate gate on a pair in one layer");
+    seen[pi] = 1;
+    std::vector<cd> m16(16, cd(0));
+    if (g.kind == 0) {
+      p->split[pi] = cz_split();
+      m16[0] = m16[5] = m16[10] = 1;
+      m16[15] = -1;
+    } else if (g.kind == 1) {
+      for (int e = 0; e < 16; ++e) m16[e] = g.m[e];
+      int rc = split_entangler(g.m, &p->split[pi], err);
+      if (rc) return rc;
+    } else {
+      return fail(err, kErrInvalid, "unknown gate kind");
+    }
+    p->g4[pi] = m16;
+  }
+  for (int l = 1; l <= d; ++l)
+    for (int c = 0; c < n - 1; ++c) {
+      size_t pi = (size_t)pair_index(*p, l, c);
+      if (in_pattern(*p, l, c) && !seen[pi]) {
+        p->split[pi] = identity;
+        std::vector<cd> m16(16, cd(0));
+        m16[0] = m16[5] = m16[10] = m16[15] = 1;
+        p->g4[pi] = m16;
+      }
+    }
+  (void)idsplit;
+  p->X.assign(n - 1, {});
+  p->h = 0;
+  for (int c = 0; c < n - 1; ++c) {
+    for (int l = 1; l <= d; ++l)
+      if (in_pattern(*p, l, c)) p->X[c].push_back(l);
+    p->h = std::max(p->h, int(p->X[c].size()));
+  }
+  if (p->h > 40) return fail(err, kErrDomain, "width above 40 is not supported");
+  // row 0 build-up
+  {
+    RowChain rc = build_chain(*p, 0);
+    p->m0 = int(rc.ev.size());
+    for (auto& e : rc.ev)
+      if (e.up) return fail(err, kErrInvalid, "row 0 has an up event");
+    p->init_v[0] = rc.v[0];
+    p->init_v[1] = rc.v[1];
+    p->init_seg = rc.seg;
+    for (int x = 0; x < 2; ++x)
+      for (int a = 0; a < 2; ++a) p->init_f[x][a] = rc.f[x][a];
+  }
+  p->row_ops.assign(n, {});
+  p->row_ascending.assign(n, 0);
+  for (int r = 1; r <= n - 2; ++r) {
+    int asc = 0;
+    int rc = build_row_ops(*p, r, &p->row_ops[r], &asc, err);
+    if (rc) return rc;
+    p->row_ascending[r] = asc;
+  }
+  *out = std::move(p);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+namespace {
+
+// Live slot count after rows 0..r.
+int live_after_row(const Plan& p, int r) { return int(p.X[r].size()); }
+
+std::vector<Window> window_grid(const Plan& p, int hmax) {
+  const int T = p.opt.max_tile_bits;
+  const int C = p.opt.low_bits;
+  std::vector<Window> ws;
+  if (hmax <= T) {
+    Window w;
+    w.lo_bits = 0;
+    w.win_lo = 0;
+    w.win_len = hmax;
+    ws.push_back(w);
+    return ws;
+  }
+  // boundaries b_0 = 0 < b_1 < ... < b_m = hmax-1, windows [b_i, b_{i+1}]
+  std::vector<int> b;
+  b.push_back(0);
+  int b1 = T - 1;              // bottom window [0, T-1], contiguous
+  int top_lo = hmax - (T - C);  // top window [top_lo, hmax-1] with C low slots
+  if (top_lo <= b1) {
+    b.push_back(b1);
+    b.push_back(hmax - 1);
+  } else {
+    b.push_back(b1);
+    int span = T - C - 1;  // middle window [b_i, b_i + span] has span+1 slots
+    int gap = top_lo - b1;
+    int nmid = (gap + span - 1) / span;
+    for (int i = 1; i < nmid; ++i) b.push_back(b1 + (int)std::lround((double)gap * i / nmid));
+    b.push_back(top_lo);
+    b.push_back(hmax - 1);
+  }
+  for (size_t i = 0; i + 1 < b.size(); ++i) {
+    Window w;
+    if (b[i] == 0) {
+      w.lo_bits = 0;
+      w.win_lo = 0;
+      w.win_len = b[i + 1] + 1;
+    } else {
+      w.lo_bits = C;
+      w.win_lo = b[i];
+      w.win_len = b[i + 1] - b[i] + 1;
+    }
+    ws.push_back(w);
+  }
+  return ws;
+}
+
+bool op_fits(const SweepOp& op, const Window& w) {
+  if (!w.contains(op.target)) return false;
+  if (op.control >= 0 && !w.contains(op.control)) return false;
+  return true;
+}
+
+void plan_phases(Pass& ps, const std::vector<SweepOp>& ops, int R) {
+  const int T = ps.w.tile_bits();
+  const int Reff = std::min(R, T);
+  int i = ps.op_begin;
+  while (i < ps.op_end) {
+    Phase ph;
+    ph.op_begin = i;
+    std::vector<int> tg;  // local target bits, in first-use order
+    int j = i;
+    for (; j < ps.op_end; ++j) {
+      int t = ps.w.local(ops[j].target);
+      bool have = std::find(tg.begin(), tg.end(), t) != tg.end();
+      if (!have && int(tg.size()) == Reff) break;
+      if (!have) tg.push_back(t);
+    }
+    ph.op_end = j;
+    // pad: controls of the phase's ops first, then nearest unused bits
+    std::vector<int> regs = tg;
+    for (int q = ph.op_begin; q < ph.op_end && int(regs.size()) < Reff; ++q) {
+      if (ops[q].control < 0) continue;
+      int c = ps.w.local(ops[q].control);
+      if (std::find(regs.begin(), regs.end(), c) == regs.end()) regs.push_back(c);
+    }
+    for (int dist = 1; int(regs.size()) < Reff && dist <= T; ++dist)
+      for (int base : std::vector<int>(regs)) {
+        for (int c : {base + dist, base - dist}) {
+          if (int(regs.size()) >= Reff) break;
+          if (c < 0 || c >= T) continue;
+          if (std::find(regs.begin(), regs.end(), c) == regs.end()) regs.push_back(c);
+        }
+      }
+    for (int c = 0; int(regs.size()) < Reff && c < T; ++c)
+      if (std::find(regs.begin(), regs.end(), c) == regs.end()) regs.push_back(c);
+    for (int q = 0; q < kMaxReg; ++q) ph.reg[q] = q < int(regs.size()) ? regs[q] : -1;
+    ps.phases.push_back(ph);
+    i = j;
+  }
+}
+
+std::vector<Pass> plan_passes(const Plan& p, const std::vector<SweepOp>& ops, int R) {
+  std::vector<Pass> passes;
+  if (ops.empty()) return passes;
+  auto ws = window_grid(p, p.h);
+  int i = 0;
+  const int nops = int(ops.size());
+  while (i < nops) {
+    // choose the window that contains the longest run of ops from i
+    int best_w = -1, best_len = -1;
+    for (int wi = 0; wi < int(ws.size()); ++wi) {
+      int j = i;
+      while (j < nops && op_fits(ops[j], ws[wi])) ++j;
+      if (j - i > best_len) { best_len = j - i; best_w = wi; }
+    }
+    Pass ps;
+    ps.w = ws[best_w];
+    ps.op_begin = i;
+    ps.op_end = i + best_len;
+    plan_phases(ps, ops, R);
+    passes.push_back(ps);
+    i += best_len;
+  }
+  return passes;
+}
+
+// Band evolution for Z_early: state of k qubits (bit j = qubit n-k+j).
+void band_apply_u1(std::vector<cd>& st, int k, int bit, const M2& m) {
+  const int dim = 1 << k;
+  for (int i = 0; i < dim; ++i) {
+    if (i >> bit & 1) continue;
+    int i1 = i | (1 << bit);
+    cd a0 = st[i], a1 = st[i1];
+    st[i] = m(0, 0) * a0 + m(0, 1) * a1;
+    st[i1] = m(1, 0) * a0 + m(1, 1) * a1;
+  }
+}
+
+void band_apply_g4(std::vector<cd>& st, int k, int bit, const std::vector<cd>& g) {
+  // bits (bit, bit+1) = (upper qubit, lower qubit); basis 2*x_upper + x_lower
+  const int dim = 1 << k;
+  for (int i = 0; i < dim; ++i) {
+    if ((i >> bit & 1) || (i >> (bit + 1) & 1)) continue;
+    int idx[4] = {i, i | (1 << (bit + 1)), i | (1 << bit), i | (1 << bit) | (1 << (bit + 1))};
+    cd a[4], r[4];
+    for (int u = 0; u < 4; ++u) a[u] = st[idx[u]];
+    for (int o = 0; o < 4; ++o) {
+      r[o] = 0;
+      for (int u = 0; u < 4; ++u) r[o] += g[4 * o + u] * a[u];
+    }
+    for (int u = 0; u < 4; ++u) st[idx[u]] = r[u];
+  }
+}
+
+double log2_sum(const std::vector<double>& log2s) {
+  double mx = -1e300;
+  for (double v : log2s) mx = std::max(mx, v);
+  double s = 0;
+  for (double v : log2s) s += std::exp2(v - mx);
+  return mx + std::log2(s);
+}
+
+}  // namespace
+
+int get_schedule(Plan& p, int k, std::shared_ptr<Schedule>* out, std::string* err) {
+  if (k < 0 || k > p.n - 1) return fail(err, kErrDomain, "open legs k must satisfy 0 <= k <= n-1");
+  if (k >= 1 && 2 * k > p.d) return fail(err, kErrDomain, "open legs k must satisfy 2k <= d");
+  if (k > kMaxOpenLegs) return fail(err, kErrDomain, "open legs k above 10 are not supported");
+  std::lock_guard<std::mutex> lk(p.mu);
+  auto it = p.sched.find(k);
+  if (it != p.sched.end()) {
+    *out = it->second;
+    return 0;
+  }
+  auto s = std::make_shared<Schedule>();
+  s->k = k;
+  const int n = p.n;
+  s->last_fixed_row = (k == 0) ? n - 2 : n - k - 1;
+  s->m_fix = live_after_row(p, s->last_fixed_row);
+  // sweep ops: rows 1..last_fixed_row, merged at turns
+  for (int r = 1; r <= s->last_fixed_row; ++r) {
+    const auto& ro = p.row_ops[r];
+    size_t start = 0;
+    if (!s->ops.empty() && !ro.empty()) {
+      SweepOp& prev = s->ops.back();
+      const SweepOp& nx = ro[0];
+      if (prev.kind == OP_CU && nx.kind == OP_CU && nx.control < 0 && nx.target == prev.target &&
+          prev.xrow[1] < 0 && nx.xrow[1] < 0) {
+        prev = merge_ops(prev, nx);
+        start = 1;
+      }
+    }
+    for (size_t i = start; i < ro.size(); ++i) s->ops.push_back(ro[i]);
+  }
+  s->reg_bits = std::max(1, std::min(p.opt.reg_bits, p.h));
+  s->passes = plan_passes(p, s->ops, s->reg_bits);
+  // late program
+  const int d = p.d;
+  std::vector<double> cost;
+  if (k == 0) {
+    s->s_bits = 1;
+    s->join_u_bits = 0;
+    RowChain rc = build_chain(p, n - 1);
+    s->join = {rc.v[0], rc.v[1]};
+    const int M = int(rc.ev.size());
+    for (int j = 0; j < M; ++j) {
+      if (!rc.ev[j].up || rc.ev[j].slot != j) return fail(err, kErrInvalid, "last row schedule mismatch");
+      LateOp rm;
+      rm.kind = L_REMOVE;
+      for (int b = 0; b < 2; ++b)
+        for (int e = 0; e < 4; ++e) rm.m.push_back(rc.ev[j].sp->C[b].a[e]);
+      s->late.push_back(rm);
+      if (j + 1 < M) {
+        LateOp u;
+        u.kind = L_U1;
+        u.a = 0;
+        for (int e = 0; e < 4; ++e) u.m.push_back(rc.seg[j].a[e]);
+        s->late.push_back(u);
+      }
+    }
+    LateOp dot;
+    dot.kind = L_DOT;
+    dot.xrow = n - 1;
+    for (int x = 0; x < 2; ++x)
+      for (int a = 0; a < 2; ++a) dot.m.push_back(rc.f[x][a]);
+    s->late.push_back(dot);
+    s->n_remove = M;
+  } else {
+    s->s_bits = k;
+    s->join_u_bits = k;
+    const int cut = n - k - 1;
+    const auto& X = p.X[cut];
+    const int c = 2 * k;
+    if (int(X.size()) < k || X[k - 1] > c) return fail(err, kErrDomain, "fewer than k crossings in the early layers");
+    const int dim = 1 << k;
+    s->join.assign((size_t)dim * dim, cd(0));
+    for (int u = 0; u < dim; ++u) {
+      std::vector<cd> st(dim, cd(0));
+      st[0] = 1;
+      for (int l = 1; l <= c; ++l) {
+        for (int j = 0; j < k; ++j) band_apply_u1(st, k, j, p.one[(size_t)(l - 1) * n + (n - k + j)]);
+        for (int j = 0; j + 1 < k; ++j) {
+          int q = n - k + j;
+          if (in_pattern(p, l, q)) band_apply_g4(st, k, j, p.g4[pair_index(p, l, q)]);
+        }
+        if (in_pattern(p, l, cut)) {
+          int cj = int(std::lower_bound(X.begin(), X.end(), l) - X.begin());
+          band_apply_u1(st, k, 0, p.split[pair_index(p, l, cut)].C[(u >> cj) & 1]);
+        }
+      }
+      for (int t = 0; t < dim; ++t) s->join[(size_t)u * dim + t] = st[t];
+    }
+    for (int l = c + 1; l <= d + 1; ++l) {
+      for (int j = 0; j < k; ++j) {
+        LateOp u1;
+        u1.kind = L_U1;
+        u1.a = j;
+        const M2& g = p.one[(size_t)(l - 1) * n + (n - k + j)];
+        for (int e = 0; e < 4; ++e) u1.m.push_back(g.a[e]);
+        s->late.push_back(u1);
+      }
+      if (l > d) break;
+      for (int j = 0; j + 1 < k; ++j) {
+        int q = n - k + j;
+        if (in_pattern(p, l, q)) {
+          LateOp g4;
+          g4.kind = L_G4;
+          g4.a = j;
+          g4.m = p.g4[pair_index(p, l, q)];
+          s->late.push_back(g4);
+        }
+      }
+      if (in_pattern(p, l, cut)) {
+        LateOp rm;
+        rm.kind = L_REMOVE;
+        const Split& sp = p.split[pair_index(p, l, cut)];
+        for (int b = 0; b < 2; ++b)
+          for (int e = 0; e < 4; ++e) rm.m.push_back(sp.C[b].a[e]);
+        s->late.push_back(rm);
+        s->n_remove++;
+      }
+    }
+    LateOp o;
+    o.kind = L_OUT;
+    s->late.push_back(o);
+    if (s->n_remove != s->m_fix - k) return fail(err, kErrInvalid, "late removals do not match the live slots");
+  }
+  // Cost model in the |I||J||K| convention of Sec. 2.2: a paired update of
+  // an R-leg boundary tensor costs 2^(R+2), a single absorption 2^(R+1).
+  {
+    int R = p.m0;
+    for (int j = 1; j <= p.m0; ++j) cost.push_back(j + 2.0);  // row-0 build-up
+    for (int r = 1; r <= s->last_fixed_row; ++r) {
+      int rin = int(p.X[r - 1].size()), rout = int(p.X[r].size());
+      R = std::max(rin, rout);
+      // Alg. 1 on one row: the first tensor is absorbed alone (2^(R+1)),
+      // then R-1 pairs (2^(R+2) each), then, when both cuts have R
+      // crossings, the last tensor alone (2^(R+1)).
+      for (int j = 0; j < R - 1; ++j) cost.push_back(R + 2.0);
+      cost.push_back(R + 1.0);
+      if (rin == rout) cost.push_back(R + 1.0);
+    }
+    R = s->m_fix;
+    if (k == 0) {
+      for (int j = R; j >= 1; --j) cost.push_back(j + 1.0);
+    } else {
+      cost.push_back(double(R + k));      // join: 2^(R-k) * 2^k * 2^k
+      cost.push_back(2.0 * k + k + 2.0);  // early region (host)
+      for (int j = R; j > k; --j) cost.push_back(j + 1.0);
+    }
+    s->log2_cost = log2_sum(cost);
+    s->width = std::max(p.h, k >= 1 ? 2 * k : 0);
+  }
+  p.sched[k] = s;
+  *out = s;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 host execution of the plan tables (self-check of the lowering).
+namespace {
+
+void host_apply_op(const SweepOp& op, std::vector<cd>& B, int h, const uint8_t* x) {
+  const size_t dim = size_t(1) << h;
+  int var = 0;
+  if (op.xrow[0] >= 0) var += 2 * x[op.xrow[0]];
+  if (op.xrow[1] >= 0) var += x[op.xrow[1]];
+  const size_t ts = size_t(1) << op.target;
+  for (size_t i = 0; i < dim; ++i) {
+    if (i & ts) continue;
+    if (op.kind == OP_DUP) {
+      B[i | ts] = B[i];
+      continue;
+    }
+    int a = op.control >= 0 ? int((i >> op.control) & 1) : 0;
+    const M2& m = op.mat[var][a];
+    cd b0 = B[i], b1 = B[i | ts];
+    B[i] = m(0, 0) * b0 + m(0, 1) * b1;
+    B[i | ts] = m(1, 0) * b0 + m(1, 1) * b1;
+  }
+}
+
+}  // namespace
+
+int execute_host(Plan& p, int k, int n_batches, const uint8_t* bits, cd* out, std::string* err) {
+  std::shared_ptr<Schedule> s;
+  int rc = get_schedule(p, k, &s, err);
+  if (rc) return rc;
+  const int h = p.h, n = p.n;
+  if (h > 24) return fail(err, kErrDomain, "host execution limited to width 24");
+  const size_t dim = size_t(1) << h;
+  for (int bt = 0; bt < n_batches; ++bt) {
+    const uint8_t* x = bits + (size_t)bt * n;
+    std::vector<cd> B(dim, cd(0));
+    // row 0
+    const int m0 = p.m0;
+    for (size_t i = 0; i < (size_t(1) << m0); ++i) {
+      cd v = p.init_v[i & 1];
+      for (int j = 1; j < m0; ++j) v *= p.init_seg[j - 1](int(i >> j & 1), int(i >> (j - 1) & 1));
+      v *= p.init_f[x[0]][int(i >> (m0 - 1) & 1)];
+      B[i] = v;
+    }
+    for (const auto& op : s->ops) host_apply_op(op, B, h, x);
+    // late: state tensor st[rest][t] with t in the low s bits
+    const int sb = s->s_bits;
+    const int ub = s->join_u_bits;
+    int rest_bits = s->m_fix - ub;
+    std::vector<cd> st((size_t(1) << sb) << rest_bits, cd(0));
+    const size_t sd = size_t(1) << sb;
+    for (size_t rr = 0; rr < (size_t(1) << rest_bits); ++rr) {
+      for (size_t t = 0; t < sd; ++t) {
+        cd acc = 0;
+        if (k == 0) {
+          acc = s->join[t] * B[rr];
+        } else {
+          for (size_t u = 0; u < (size_t(1) << ub); ++u) acc += B[(rr << ub) | u] * s->join[u * sd + t];
+        }
+        st[(rr << sb) | t] = acc;
+      }
+    }
+    cd* o = out + (size_t)bt * (size_t(1) << k);
+    for (const auto& lo : s->late) {
+      const size_t nrest = size_t(1) << rest_bits;
+      if (lo.kind == L_U1) {
+        M2 m;
+        for (int e = 0; e < 4; ++e) m.a[e] = lo.m[e];
+        for (size_t rr = 0; rr < nrest; ++rr) {
+          std::vector<cd> v(st.begin() + rr * sd, st.begin() + (rr + 1) * sd);
+          band_apply_u1(v, sb, lo.a, m);
+          std::copy(v.begin(), v.end(), st.begin() + rr * sd);
+        }
+      } else if (lo.kind == L_G4) {
+        for (size_t rr = 0; rr < nrest; ++rr) {
+          std::vector<cd> v(st.begin() + rr * sd, st.begin() + (rr + 1) * sd);
+          band_apply_g4(v, sb, lo.a, lo.m);
+          std::copy(v.begin(), v.end(), st.begin() + rr * sd);
+        }
+      } else if (lo.kind == L_REMOVE) {
+        M2 C[2];
+        for (int b = 0; b < 2; ++b)
+          for (int e = 0; e < 4; ++e) C[b].a[e] = lo.m[4 * b + e];
+        std::vector<cd> ns((sd << (rest_bits - 1)), cd(0));
+        for (size_t rr = 0; rr < (nrest >> 1); ++rr)
+          for (int u = 0; u < 2; ++u) {
+            std::vector<cd> v(st.begin() + ((rr << 1) | u) * sd, st.begin() + (((rr << 1) | u) + 1) * sd);
+            band_apply_u1(v, sb, 0, C[u]);
+            for (size_t t = 0; t < sd; ++t) ns[rr * sd + t] += v[t];
+          }
+        st.swap(ns);
+        rest_bits--;
+      } else if (lo.kind == L_DOT) {
+        int xv = x[lo.xrow];
+        o[0] = lo.m[2 * xv] * st[0] + lo.m[2 * xv + 1] * st[1];
+      } else if (lo.kind == L_OUT) {
+        for (size_t b = 0; b < sd; ++b) {
+          size_t t = 0;
+          for (int j = 0; j < k; ++j) t |= ((b >> (k - 1 - j)) & 1) << j;
+          o[b] = st[t];
+        }
+      }
+    }
+    if (rest_bits != 0) return fail(err, kErrInvalid, "late program left slots");
+  }
+  return 0;
+}
+
+}  // namespace tnc

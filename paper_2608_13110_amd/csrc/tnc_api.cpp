@@ -1,0 +1,662 @@
+// C ABI and executor of the temporal-boundary contraction (include/tnc.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/tnc.h"
+#include "kernels.hpp"
+#include "late.hpp"
+#include "plan.hpp"
+
+struct tnc_plan_s {
+  std::unique_ptr<tnc::Plan> plan;
+};
+
+namespace tnc {
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_err(hipError_t e, const char* what) {
+  return set_err(TNC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+// Host copies of a schedule's device tables.
+struct PassHost {
+  int phase_off = 0, n_phases = 0;
+  Window w;
+  int R = 5;
+};
+
+struct HostTables {
+  std::vector<DevOp> ops;
+  std::vector<float> mats;
+  std::vector<DevPhase> phases;
+  std::vector<PassHost> passes;
+  std::vector<double2> seg;
+  LatePlan late;
+  std::vector<LateOpDev> prog;
+  uint64_t bytes_B = 0;      // per batch
+  uint64_t bytes_late[2] = {0, 0};
+};
+
+int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
+  const size_t nops = s.ops.size();
+  t->ops.resize(nops);
+  t->mats.assign(nops * 4 * 16, 0.f);
+  for (size_t o = 0; o < nops; ++o) {
+    const SweepOp& op = s.ops[o];
+    for (int var = 0; var < 4; ++var)
+      for (int c = 0; c < 2; ++c)
+        for (int e = 0; e < 4; ++e) {
+          t->mats[(o * 4 + var) * 16 + c * 8 + 2 * e] = (float)op.mat[var][c].a[e].real();
+          t->mats[(o * 4 + var) * 16 + c * 8 + 2 * e + 1] = (float)op.mat[var][c].a[e].imag();
+        }
+  }
+  for (const Pass& ps : s.passes) {
+    PassHost ph;
+    ph.w = ps.w;
+    ph.R = std::min(s.reg_bits, ps.w.tile_bits());
+    ph.phase_off = int(t->phases.size());
+    ph.n_phases = int(ps.phases.size());
+    const int R = ph.R;
+    if (ps.w.tile_bits() - R > 8) {
+      if (err) *err = "pass tile too large for the thread block";
+      return TNC_E_DOMAIN;
+    }
+    if (!(ps.w.lo_bits >= 1 || ps.w.win_lo == 0)) {
+      if (err) *err = "pass tile lacks slot 0";
+      return TNC_E_INVALID;
+    }
+    for (const Phase& pp : ps.phases) {
+      DevPhase dp;
+      std::memset(&dp, 0, sizeof(dp));
+      dp.op_begin = pp.op_begin;
+      dp.op_end = pp.op_end;
+      for (int b = 0; b < 8; ++b) dp.reg[b] = (int8_t)(b < R ? pp.reg[b] : 0);
+      for (int b = 0; b < R; ++b)
+        for (int c = 0; c < b; ++c)
+          if (pp.reg[b] == pp.reg[c] || pp.reg[b] < 0) {
+            if (err) *err = "bad register map";
+            return TNC_E_INVALID;
+          }
+      t->phases.push_back(dp);
+      for (int o = pp.op_begin; o < pp.op_end; ++o) {
+        const SweepOp& op = s.ops[o];
+        DevOp d;
+        std::memset(&d, 0, sizeof(d));
+        d.kind = (int8_t)op.kind;
+        const int lt = ps.w.local(op.target);
+        int treg = -1;
+        for (int b = 0; b < R; ++b)
+          if (pp.reg[b] == lt) treg = b;
+        if (treg < 0 || !ps.w.contains(op.target)) {
+          if (err) *err = "op target not in registers";
+          return TNC_E_INVALID;
+        }
+        d.treg = (int8_t)treg;
+        d.creg = (int8_t)R;
+        d.cloc = -1;
+        if (op.control >= 0) {
+          if (!ps.w.contains(op.control)) {
+            if (err) *err = "op control outside the tile";
+            return TNC_E_INVALID;
+          }
+          const int lc = ps.w.local(op.control);
+          for (int b = 0; b < R; ++b)
+            if (pp.reg[b] == lc) d.creg = (int8_t)b;
+          if (d.creg == R) d.cloc = (int8_t)lc;
+        }
+        d.xrow0 = (int16_t)op.xrow[0];
+        d.xrow1 = (int16_t)op.xrow[1];
+        d.mat = o;
+        t->ops[o] = d;
+      }
+    }
+    t->passes.push_back(ph);
+  }
+  t->seg.resize((size_t)std::max(0, p.m0 - 1) * 4);
+  for (int j = 1; j < p.m0; ++j)
+    for (int e = 0; e < 4; ++e)
+      t->seg[(size_t)(j - 1) * 4 + e] = make_double2(p.init_seg[j - 1].a[e].real(), p.init_seg[j - 1].a[e].imag());
+  int rc = build_late(p, s, &t->late, err);
+  if (rc) return rc;
+  for (const LateOp& lo : s.late) {
+    LateOpDev d;
+    std::memset(&d, 0, sizeof(d));
+    d.kind = lo.kind;
+    d.a = lo.a;
+    d.xrow = lo.xrow;
+    for (size_t e = 0; e < lo.m.size() && e < 16; ++e) d.m[e] = make_double2(lo.m[e].real(), lo.m[e].imag());
+    t->prog.push_back(d);
+  }
+  t->bytes_B = align256((uint64_t)8 << p.h);
+  // late buffers: first output -> buffer 0, ops launch i -> buffer (i+1)&1
+  const LateFirst& F = t->late.first;
+  if (!F.final) t->bytes_late[0] = align256((uint64_t)F.M * F.N * 16);
+  for (size_t i = 0; i < t->late.ops.size(); ++i) {
+    const LateOpsLaunch& ln = t->late.ops[i];
+    if (ln.final) continue;
+    const uint64_t bytes = align256((uint64_t)(ln.rows_in >> ln.j) * (16ull << t->late.s));
+    uint64_t& slot = t->bytes_late[(i + 1) & 1];
+    slot = std::max(slot, bytes);
+  }
+  return 0;
+}
+
+// Device copy of the tables for one (k, device).
+struct DevSched {
+  int device = -1;
+  HostTables host;
+  DevOp* d_ops = nullptr;
+  float* d_mats = nullptr;
+  DevPhase* d_phases = nullptr;
+  double2* d_seg = nullptr;
+  double2* d_J = nullptr;
+  LateOpDev* d_prog = nullptr;
+  ~DevSched() {
+    int prev = 0;
+    if (device >= 0 && hipGetDevice(&prev) == hipSuccess) {
+      (void)hipSetDevice(device);
+      void* ptrs[] = {d_ops, d_mats, d_phases, d_seg, d_J, d_prog};
+      for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+      (void)hipSetDevice(prev);
+    }
+  }
+  uint64_t per_batch() const { return host.bytes_B + host.bytes_late[0] + host.bytes_late[1]; }
+};
+
+struct PlanDevice {
+  std::mutex mu;
+  std::map<std::pair<int, int>, std::shared_ptr<DevSched>> m;
+};
+
+void free_plan_device(void* p) { delete static_cast<PlanDevice*>(p); }
+
+PlanDevice& plan_device(Plan& p) {
+  std::lock_guard<std::mutex> lk(p.mu);
+  if (!p.device) {
+    p.device = new PlanDevice();
+    p.device_free = free_plan_device;
+  }
+  return *static_cast<PlanDevice*>(p.device);
+}
+
+template <typename T>
+int upload(T** dst, const std::vector<T>& src) {
+  if (src.empty()) return 0;
+  hipError_t e = hipMalloc((void**)dst, src.size() * sizeof(T));
+  if (e != hipSuccess) return set_err(TNC_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_err(e, "hipMemcpy");
+  return 0;
+}
+
+int get_dev_sched(Plan& p, int k, std::shared_ptr<DevSched>* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_err(e, "hipGetDevice");
+  PlanDevice& pd = plan_device(p);
+  std::lock_guard<std::mutex> lk(pd.mu);
+  auto it = pd.m.find({k, dev});
+  if (it != pd.m.end()) {
+    *out = it->second;
+    return 0;
+  }
+  std::shared_ptr<Schedule> s;
+  std::string err;
+  int rc = get_schedule(p, k, &s, &err);
+  if (rc) return set_err(rc, err);
+  auto ds = std::make_shared<DevSched>();
+  ds->device = dev;
+  rc = build_tables(p, *s, &ds->host, &err);
+  if (rc) return set_err(rc, err);
+  std::vector<double2> J;
+  for (const cd& z : ds->host.late.first.J) J.push_back(make_double2(z.real(), z.imag()));
+  if ((rc = upload(&ds->d_ops, ds->host.ops)) || (rc = upload(&ds->d_mats, ds->host.mats)) ||
+      (rc = upload(&ds->d_phases, ds->host.phases)) || (rc = upload(&ds->d_seg, ds->host.seg)) ||
+      (rc = upload(&ds->d_J, J)) || (rc = upload(&ds->d_prog, ds->host.prog)))
+    return rc;
+  pd.m[{k, dev}] = ds;
+  *out = ds;
+  return 0;
+}
+
+InitArgs init_args(const Plan& p, const HostTables& t, float2* B, const uint8_t* bits, int nb,
+                   const double2* d_seg) {
+  InitArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.B = B;
+  a.bits = bits;
+  a.seg = d_seg;
+  for (int w = 0; w < 2; ++w) a.v[w] = make_double2(p.init_v[w].real(), p.init_v[w].imag());
+  for (int x = 0; x < 2; ++x)
+    for (int w = 0; w < 2; ++w) a.f[x][w] = make_double2(p.init_f[x][w].real(), p.init_f[x][w].imag());
+  a.m0 = p.m0;
+  a.h = p.h;
+  a.n = p.n;
+  a.n_batches = nb;
+  (void)t;
+  return a;
+}
+
+PassArgs pass_args(const Plan& p, const PassHost& ph, const DevPhase* phases, const DevOp* ops, const float* mats,
+                   float2* B, const uint8_t* bits, int nb) {
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.phases = phases + ph.phase_off;
+  a.ops = ops;
+  a.mats = mats;
+  a.B = B;
+  a.bits = bits;
+  a.n_phases = ph.n_phases;
+  a.n = p.n;
+  a.h = p.h;
+  a.T = ph.w.tile_bits();
+  a.lo_bits = ph.w.lo_bits;
+  a.win_lo = ph.w.win_lo;
+  a.win_len = ph.w.win_len;
+  a.n_tiles = nb << (p.h - a.T);
+  return a;
+}
+
+LateArgs first_args(const Plan& p, const HostTables& t, const void* in, double2* out, long long out_stride,
+                    const double2* J, const uint8_t* bits, int nb) {
+  const LateFirst& F = t.late.first;
+  LateArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = in;
+  a.out = out;
+  a.J = J;
+  a.bits = bits;
+  a.in_batch_stride = 1ll << p.h;
+  a.out_batch_stride = out_stride;
+  a.M = (int)F.M;
+  a.K = F.K;
+  a.N = F.N;
+  a.n_batches = nb;
+  a.xrow = F.xrow;
+  a.n = p.n;
+  return a;
+}
+
+LateOpsArgs ops_args(const Plan& p, const HostTables& t, const LateOpsLaunch& ln, const double2* in, double2* out,
+                     long long out_stride, const LateOpDev* prog, const uint8_t* bits, int nb, int k) {
+  LateOpsArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = in;
+  a.out = out;
+  a.bits = bits;
+  a.prog = prog + ln.op_begin;
+  a.n_prog = ln.op_end - ln.op_begin;
+  a.s = t.late.s;
+  a.j = ln.j;
+  a.in_batch_stride = ln.rows_in << t.late.s;
+  a.out_batch_stride = out_stride;
+  a.rows_out = ln.rows_in >> ln.j;
+  a.n_batches = nb;
+  a.n = p.n;
+  a.k = k;
+  a.final_kind = ln.final ? t.late.final_kind : 0;
+  a.final_xrow = t.late.final_xrow;
+  if (t.late.final_kind == L_DOT)
+    for (int x = 0; x < 2; ++x)
+      for (int w = 0; w < 2; ++w)
+        a.dot[x][w] = make_double2(t.late.dot[2 * x + w].real(), t.late.dot[2 * x + w].imag());
+  return a;
+}
+
+int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k, tnc_c128* d_out, void* ws,
+               uint64_t ws_bytes, hipStream_t stream) {
+  const HostTables& t = ds.host;
+  const uint64_t per = ds.per_batch();
+  const uint64_t fit = ws_bytes / per;
+  if (fit < 1) return set_err(TNC_E_NOMEM, "workspace smaller than one batch");
+  const int chunk = (int)std::min<uint64_t>(fit, (uint64_t)std::min(nb_total, 65535));
+  char* base = static_cast<char*>(ws);
+  for (int b0 = 0; b0 < nb_total; b0 += chunk) {
+    const int nb = std::min(chunk, nb_total - b0);
+    float2* B = reinterpret_cast<float2*>(base);
+    double2* L0 = reinterpret_cast<double2*>(base + t.bytes_B * (uint64_t)nb);
+    double2* L1 = reinterpret_cast<double2*>(base + (t.bytes_B + t.bytes_late[0]) * (uint64_t)nb);
+    const uint8_t* bits = d_bits + (size_t)b0 * p.n;
+    double2* out = reinterpret_cast<double2*>(d_out) + ((size_t)b0 << k);
+    hipError_t e = launch_init(init_args(p, t, B, bits, nb, ds.d_seg), stream);
+    if (e != hipSuccess) return hip_err(e, "init launch");
+    for (const PassHost& ph : t.passes) {
+      e = launch_pass(pass_args(p, ph, ds.d_phases, ds.d_ops, ds.d_mats, B, bits, nb), ph.R, stream);
+      if (e != hipSuccess) return hip_err(e, "pass launch");
+    }
+    const LateFirst& F = t.late.first;
+    double2* fout = F.final ? out : L0;
+    const long long fstride = F.final ? (1ll << k) : (long long)(t.bytes_late[0] / 16);
+    e = launch_late(first_args(p, t, B, fout, fstride, ds.d_J, bits, nb), true, stream);
+    if (e != hipSuccess) return hip_err(e, "late launch");
+    const double2* cur = L0;
+    long long cur_stride = fstride;
+    for (size_t i = 0; i < t.late.ops.size(); ++i) {
+      const LateOpsLaunch& ln = t.late.ops[i];
+      double2* dst = ln.final ? out : ((i + 1) & 1 ? L1 : L0);
+      const long long dstride = ln.final ? (1ll << k) : (long long)(t.bytes_late[(i + 1) & 1] / 16);
+      LateOpsArgs a = ops_args(p, t, ln, cur, dst, dstride, ds.d_prog, bits, nb, k);
+      a.in_batch_stride = cur_stride;
+      e = launch_late_ops(a, stream);
+      if (e != hipSuccess) return hip_err(e, "late-ops launch");
+      cur = dst;
+      cur_stride = dstride;
+    }
+  }
+  return TNC_OK;
+}
+
+// Host emulation of the whole device pipeline with the same tables.
+int emulate(Plan& p, int k, int nb, const uint8_t* bits, cd* out) {
+  std::shared_ptr<Schedule> s;
+  std::string err;
+  int rc = get_schedule(p, k, &s, &err);
+  if (rc) return set_err(rc, err);
+  HostTables t;
+  rc = build_tables(p, *s, &t, &err);
+  if (rc) return set_err(rc, err);
+  if (p.h > 24) return set_err(TNC_E_DOMAIN, "emulation limited to width 24");
+  const size_t dim = size_t(1) << p.h;
+  std::vector<float2> B(dim * nb);
+  // init (same arithmetic as k_init, FP64 product rounded to FP32)
+  for (int b = 0; b < nb; ++b)
+    for (size_t i = 0; i < dim; ++i) {
+      cd v = 0;
+      if (i < (size_t(1) << p.m0)) {
+        v = p.init_v[i & 1];
+        for (int j = 1; j < p.m0; ++j) v *= p.init_seg[j - 1](int(i >> j & 1), int(i >> (j - 1) & 1));
+        v *= p.init_f[bits[(size_t)b * p.n]][int(i >> (p.m0 - 1) & 1)];
+      }
+      B[b * dim + i] = make_float2((float)v.real(), (float)v.imag());
+    }
+  for (const PassHost& ph : t.passes)
+    emulate_pass_host(pass_args(p, ph, t.phases.data(), t.ops.data(), t.mats.data(), B.data(), bits, nb), ph.R);
+  // late (FP64), same tables
+  const LateFirst& F = t.late.first;
+  const int sb = t.late.s;
+  for (int b = 0; b < nb; ++b) {
+    const int var = F.xrow >= 0 ? bits[(size_t)b * p.n + F.xrow] : 0;
+    std::vector<cd> cur((size_t)F.M * F.N);
+    for (long long r = 0; r < F.M; ++r)
+      for (int c = 0; c < F.N; ++c) {
+        cd acc = 0;
+        for (int kk = 0; kk < F.K; ++kk) {
+          const float2 x = B[b * dim + (size_t)r * F.K + kk];
+          acc += cd(x.x, x.y) * F.J[((size_t)var * F.K + kk) * F.N + c];
+        }
+        cur[(size_t)r * F.N + c] = acc;
+      }
+    for (const LateOpsLaunch& ln : t.late.ops) {
+      const long long rows_out = ln.rows_in >> ln.j;
+      std::vector<cd> nxt((size_t)rows_out << sb);
+      for (long long ro = 0; ro < rows_out; ++ro) {
+        std::vector<cd> st(cur.begin() + ((size_t)ro << (ln.j + sb)), cur.begin() + ((size_t)(ro + 1) << (ln.j + sb)));
+        int l = 0;
+        for (int o = ln.op_begin; o < ln.op_end; ++o) {
+          const LateOp& op = s->late[o];
+          const int live = ln.j - l;
+          for (int r = 0; r < (1 << live); ++r) {
+            const int row = r << l;
+            cd* v = st.data() + ((size_t)row << sb);
+            if (op.kind == L_U1) {
+              for (int i = 0; i < (1 << sb); ++i) {
+                if (i >> op.a & 1) continue;
+                const int i1 = i | (1 << op.a);
+                const cd a0 = v[i], a1 = v[i1];
+                v[i] = op.m[0] * a0 + op.m[1] * a1;
+                v[i1] = op.m[2] * a0 + op.m[3] * a1;
+              }
+            } else if (op.kind == L_G4) {
+              for (int i = 0; i < (1 << sb); ++i) {
+                if ((i >> op.a & 1) || (i >> (op.a + 1) & 1)) continue;
+                const int idx[4] = {i, i | (1 << (op.a + 1)), i | (1 << op.a), i | (3 << op.a)};
+                cd x[4], y[4];
+                for (int u = 0; u < 4; ++u) x[u] = v[idx[u]];
+                for (int q = 0; q < 4; ++q) {
+                  y[q] = 0;
+                  for (int u = 0; u < 4; ++u) y[q] += op.m[4 * q + u] * x[u];
+                }
+                for (int u = 0; u < 4; ++u) v[idx[u]] = y[u];
+              }
+            } else if (op.kind == L_REMOVE && (r & 1) == 0) {
+              cd* w = st.data() + ((size_t)(row | (1 << l)) << sb);
+              for (int i = 0; i < (1 << sb); i += 2) {
+                const cd x0 = v[i], x1 = v[i + 1], y0 = w[i], y1 = w[i + 1];
+                v[i] = op.m[0] * x0 + op.m[1] * x1 + op.m[4] * y0 + op.m[5] * y1;
+                v[i + 1] = op.m[2] * x0 + op.m[3] * x1 + op.m[6] * y0 + op.m[7] * y1;
+              }
+            }
+          }
+          if (op.kind == L_REMOVE) ++l;
+        }
+        for (int q = 0; q < (1 << sb); ++q) nxt[((size_t)ro << sb) + q] = st[q];
+      }
+      cur.swap(nxt);
+    }
+    cd* o = out + ((size_t)b << k);
+    if (F.final) {
+      for (int c = 0; c < (1 << k); ++c) o[c] = cur[c];
+    } else if (t.late.final_kind == L_OUT) {
+      for (int bb = 0; bb < (1 << k); ++bb) {
+        int tt = 0;
+        for (int q = 0; q < k; ++q) tt |= ((bb >> (k - 1 - q)) & 1) << q;
+        o[bb] = cur[tt];
+      }
+    } else {
+      const int x = bits[(size_t)b * p.n + t.late.final_xrow];
+      o[0] = t.late.dot[2 * x] * cur[0] + t.late.dot[2 * x + 1] * cur[1];
+    }
+  }
+  return TNC_OK;
+}
+
+Plan* get(tnc_plan_t h) { return h ? h->plan.get() : nullptr; }
+
+}  // namespace
+}  // namespace tnc
+
+using namespace tnc;
+
+extern "C" {
+
+int tnc_plan(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, const tnc_gate2* gates,
+             const tnc_options* opt, tnc_plan_t* out) {
+  if (!out || !one_qubit || (n_gate2 > 0 && !gates) || n_gate2 < 0) return set_err(TNC_E_INVALID, "null argument");
+  *out = nullptr;
+  Options o;
+  if (opt) {
+    if (opt->max_tile_bits) o.max_tile_bits = opt->max_tile_bits;
+    if (opt->reg_bits) o.reg_bits = opt->reg_bits;
+    if (opt->low_bits) o.low_bits = opt->low_bits;
+  }
+  if (o.max_tile_bits < 6 || o.max_tile_bits > 13 || o.reg_bits < 1 || o.reg_bits > 5 || o.low_bits < 1 ||
+      o.low_bits > o.max_tile_bits - 2 || o.max_tile_bits - o.reg_bits > 8)
+    return set_err(TNC_E_INVALID, "tile options out of range");
+  if (n < 2 || d < 2 || (int64_t)n * (d + 1) > (1 << 24)) return set_err(TNC_E_DOMAIN, "need n >= 2, d >= 2");
+  std::vector<cd> one((size_t)(d + 1) * n * 4);
+  for (size_t i = 0; i < one.size(); ++i) one[i] = cd(one_qubit[i].re, one_qubit[i].im);
+  std::vector<std::vector<cd>> mats(n_gate2);
+  std::vector<Gate2In> g(n_gate2);
+  for (int i = 0; i < n_gate2; ++i) {
+    mats[i].resize(16);
+    for (int e = 0; e < 16; ++e) mats[i][e] = cd(gates[i].m[e].re, gates[i].m[e].im);
+    g[i] = Gate2In{gates[i].layer, gates[i].q, gates[i].kind, mats[i].data()};
+  }
+  std::unique_ptr<Plan> p;
+  std::string err;
+  int rc = build_plan(n, d, one.data(), n_gate2, g.data(), o, &p, &err);
+  if (rc) return set_err(rc, err);
+  auto* h = new tnc_plan_s();
+  h->plan = std::move(p);
+  *out = h;
+  return TNC_OK;
+}
+
+int tnc_plan_info(tnc_plan_t plan, int32_t k, tnc_info* info) {
+  Plan* p = get(plan);
+  if (!p || !info) return set_err(TNC_E_INVALID, "null argument");
+  std::shared_ptr<Schedule> s;
+  std::string err;
+  int rc = get_schedule(*p, k, &s, &err);
+  if (rc) return set_err(rc, err);
+  HostTables t;
+  rc = build_tables(*p, *s, &t, &err);
+  if (rc) return set_err(rc, err);
+  std::memset(info, 0, sizeof(*info));
+  info->width = s->width;
+  info->boundary_bits = p->h;
+  info->live_slots_fixed = s->m_fix;
+  info->n_ops = (int32_t)s->ops.size();
+  info->n_passes = (int32_t)s->passes.size();
+  info->n_phases = (int32_t)t.phases.size();
+  info->n_late_launches = 1 + (int32_t)t.late.ops.size();
+  info->fixed_rows = s->last_fixed_row + 1;
+  info->early_layers = k >= 1 ? 2 * k : 0;
+  info->late_layers = k >= 1 ? p->d - 2 * k : 0;
+  info->log2_cost = s->log2_cost;
+  info->workspace_per_batch = t.bytes_B + t.bytes_late[0] + t.bytes_late[1];
+  return TNC_OK;
+}
+
+int tnc_prepare(tnc_plan_t plan, int32_t k) {
+  Plan* p = get(plan);
+  if (!p) return set_err(TNC_E_INVALID, "null plan");
+  std::shared_ptr<DevSched> ds;
+  return get_dev_sched(*p, k, &ds);
+}
+
+int tnc_workspace_bytes(tnc_plan_t plan, int32_t k, int32_t n_batches, int32_t storage, uint64_t* bytes) {
+  Plan* p = get(plan);
+  if (!p || !bytes || n_batches < 0) return set_err(TNC_E_INVALID, "bad argument");
+  if (storage != TNC_STORE_C64) return set_err(TNC_E_INVALID, "unknown storage mode");
+  std::shared_ptr<Schedule> s;
+  std::string err;
+  int rc = get_schedule(*p, k, &s, &err);
+  if (rc) return set_err(rc, err);
+  HostTables t;
+  rc = build_tables(*p, *s, &t, &err);
+  if (rc) return set_err(rc, err);
+  *bytes = (uint64_t)n_batches * (t.bytes_B + t.bytes_late[0] + t.bytes_late[1]);
+  return TNC_OK;
+}
+
+int tnc_amplitudes(tnc_plan_t plan, int32_t n_batches, const uint8_t* d_bits, int32_t k, int32_t storage,
+                   tnc_c128* d_out, void* d_workspace, uint64_t workspace_bytes, void* stream) {
+  Plan* p = get(plan);
+  if (!p || n_batches < 0 || (n_batches > 0 && (!d_bits || !d_out || !d_workspace)))
+    return set_err(TNC_E_INVALID, "bad argument");
+  if (storage != TNC_STORE_C64) return set_err(TNC_E_INVALID, "unknown storage mode");
+  if (n_batches == 0) return TNC_OK;
+  std::shared_ptr<DevSched> ds;
+  int rc = get_dev_sched(*p, k, &ds);
+  if (rc) return rc;
+  return run_device(*p, *ds, n_batches, d_bits, k, d_out, d_workspace, workspace_bytes,
+                    static_cast<hipStream_t>(stream));
+}
+
+int tnc_amplitudes_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, int32_t storage,
+                        tnc_c128* out) {
+  Plan* p = get(plan);
+  if (!p || n_batches < 0 || (n_batches > 0 && (!bits || !out))) return set_err(TNC_E_INVALID, "bad argument");
+  if (n_batches == 0) return TNC_OK;
+  uint64_t ws = 0;
+  int rc = tnc_workspace_bytes(plan, k, n_batches, storage, &ws);
+  if (rc) return rc;
+  uint8_t* d_bits = nullptr;
+  tnc_c128* d_out = nullptr;
+  void* d_ws = nullptr;
+  hipError_t e;
+  auto cleanup = [&]() {
+    if (d_bits) (void)hipFree(d_bits);
+    if (d_out) (void)hipFree(d_out);
+    if (d_ws) (void)hipFree(d_ws);
+  };
+  const size_t nbits = (size_t)n_batches * p->n, nout = (size_t)n_batches << k;
+  if ((e = hipMalloc((void**)&d_bits, nbits)) != hipSuccess || (e = hipMalloc((void**)&d_out, nout * 16)) != hipSuccess ||
+      (e = hipMalloc(&d_ws, ws)) != hipSuccess) {
+    cleanup();
+    return set_err(TNC_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  if ((e = hipMemcpy(d_bits, bits, nbits, hipMemcpyHostToDevice)) != hipSuccess) {
+    cleanup();
+    return hip_err(e, "hipMemcpy");
+  }
+  rc = tnc_amplitudes(plan, n_batches, d_bits, k, storage, d_out, d_ws, ws, nullptr);
+  if (rc == TNC_OK) {
+    if ((e = hipDeviceSynchronize()) != hipSuccess) rc = hip_err(e, "kernel execution");
+    else if ((e = hipMemcpy(out, d_out, nout * 16, hipMemcpyDeviceToHost)) != hipSuccess) rc = hip_err(e, "hipMemcpy");
+  }
+  cleanup();
+  return rc;
+}
+
+int tnc_logxeb(const tnc_c128* d_amp, int32_t n_batches, int32_t k, const int32_t* d_select, int32_t n_qubits,
+               double* d_result, void* stream) {
+  if (!d_amp || !d_result || n_batches <= 0 || k < 0 || k > 30) return set_err(TNC_E_INVALID, "bad argument");
+  hipError_t e = launch_logxeb(reinterpret_cast<const double2*>(d_amp), n_batches, k, d_select, n_qubits, d_result,
+                               static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_err(e, "logxeb launch");
+  return TNC_OK;
+}
+
+void tnc_release(tnc_plan_t plan) {
+  if (!plan) return;
+  Plan* p = plan->plan.get();
+  if (p && p->device && p->device_free) p->device_free(p->device);
+  delete plan;
+}
+
+const char* tnc_strerror(int code) {
+  switch (code) {
+    case TNC_OK: return "ok";
+    case TNC_E_INVALID: return "invalid argument";
+    case TNC_E_DOMAIN: return "outside the supported domain";
+    case TNC_E_RANK: return "entangler operator Schmidt rank above 2";
+    case TNC_E_NOMEM: return "out of memory";
+    case TNC_E_DEVICE: return "device error";
+    default: return "unknown status";
+  }
+}
+
+const char* tnc_last_error(void) { return g_err.c_str(); }
+
+int tnc_debug_execute_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, tnc_c128* out) {
+  Plan* p = get(plan);
+  if (!p || !bits || !out || n_batches < 0) return set_err(TNC_E_INVALID, "bad argument");
+  std::vector<cd> o((size_t)n_batches << k);
+  std::string err;
+  int rc = execute_host(*p, k, n_batches, bits, o.data(), &err);
+  if (rc) return set_err(rc, err);
+  for (size_t i = 0; i < o.size(); ++i) out[i] = tnc_c128{o[i].real(), o[i].imag()};
+  return TNC_OK;
+}
+
+int tnc_debug_emulate_device(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, tnc_c128* out) {
+  Plan* p = get(plan);
+  if (!p || !bits || !out || n_batches < 0) return set_err(TNC_E_INVALID, "bad argument");
+  std::vector<cd> o((size_t)n_batches << k);
+  int rc = emulate(*p, k, n_batches, bits, o.data());
+  if (rc) return rc;
+  for (size_t i = 0; i < o.size(); ++i) out[i] = tnc_c128{o[i].real(), o[i].imag()};
+  return TNC_OK;
+}
+
+}  // extern "C"

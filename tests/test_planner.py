@@ -1,0 +1,140 @@
+"""Planner checks on the CPU: the paper's width, cost and partition claims,
+invariance, error handling, and the lowering itself (the plan's own tables
+executed on the host in FP64, and the device tables run through a host
+emulation of the pass kernel's thread/LDS mapping) against the oracle."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from paper_2608_13110_amd import EXPORTED, TNC_E_DOMAIN, TNC_E_INVALID, TNC_E_RANK, Plan, TncError, lib
+from tests import helpers as H
+from tests.pinlib import tableau
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_library_exports_every_header_symbol():
+    L = lib()
+    syms = H.header_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(EXPORTED) == set(syms)
+
+
+@pytest.mark.parametrize("n", [4, 5, 8, 12])
+def test_width_matches_prop_constructive_memory(n):
+    # Prop. constructive-memory: W = ceil(d/2) for n >= 4, 7 <= d <= 2n;
+    # Prop. batched width: the same for 1 <= k <= floor(d/4).
+    for d in range(7, 2 * n + 1):
+        p = Plan.from_circuit(W.brickwork_circuit(n, d, 1, W.rng_for(301, n, d)))
+        assert p.info(0)["width"] == math.ceil(d / 2)
+        for k in range(1, min(d // 4, n - 1) + 1):
+            assert p.info(k)["width"] == math.ceil(d / 2)
+
+
+def test_cost_point_matches_paper():
+    # Sec. 6.2 / 6.3: (W, log2 C) = (35, 48.22) for the open chi=2 path at n=d=70
+    p = Plan.from_circuit(W.brickwork_circuit(70, 70, 468, W.rng_for(302, 1)))
+    inf = p.info(0)
+    assert inf["width"] == 35
+    assert abs(inf["log2_cost"] - 48.22) < 0.05
+
+
+def test_partition_example_matches_paper():
+    # Sec. 4.3, figure fig:batched-regions: n=d=10, k=2
+    p = Plan.from_circuit(W.brickwork_circuit(10, 10, 4, W.rng_for(303, 1)))
+    inf = p.info(2)
+    assert (inf["fixed_rows"], inf["early_layers"], inf["late_layers"]) == (8, 4, 6)
+
+
+def test_width_and_cost_do_not_depend_on_gate_values():
+    # Abstract / Sec. 1: width and dense scheduled cost are independent of the
+    # one-qubit gate values and of the number and placement of T gates.
+    ref = None
+    for seed, nt in [(1, 0), (2, 30), (3, 300), (4, 700)]:
+        c = W.brickwork_circuit(40, 33, nt, W.rng_for(304, seed))
+        if seed == 4:
+            c = W.with_gate_values(c, W.rng_for(304, 9))
+        sig = [Plan.from_circuit(c).info(k) for k in (0, 3, 8)]
+        if ref is None:
+            ref = sig
+        assert sig == ref
+
+
+def test_rank_and_domain_errors():
+    c = W.brickwork_circuit(6, 6, 0, W.rng_for(305, 1))
+    z = W.rng_for(305, 2).normal(size=(4, 4)) + 1j * W.rng_for(305, 3).normal(size=(4, 4))
+    u = np.linalg.qr(z)[0]
+    bad = list(c.gates)
+    bad[0] = (bad[0][0], bad[0][1], W.GATE_DENSE4, u)
+    with pytest.raises(TncError) as e:
+        Plan(c.n, c.d, c.one_qubit, bad)
+    assert e.value.code == TNC_E_RANK
+    off = list(c.gates) + [(1, 0, W.GATE_CZ, None)] if c.gates[0][1] == 1 else list(c.gates) + [(1, 1, W.GATE_CZ, None)]
+    with pytest.raises(TncError) as e:
+        Plan(c.n, c.d, c.one_qubit, off)
+    assert e.value.code == TNC_E_INVALID
+    p = Plan.from_circuit(c)
+    for k in (-1, 4, 6):
+        with pytest.raises(TncError) as e:
+            p.info(k)
+        assert e.value.code == TNC_E_DOMAIN
+    with pytest.raises(TncError) as e:
+        Plan(3, 1, np.zeros((2, 3, 2, 2)), [])
+    assert e.value.code == TNC_E_DOMAIN
+
+
+CASES = [(2, 2, 1), (2, 5, 0), (3, 2, 0), (3, 7, 1), (4, 4, 0), (5, 6, 1), (6, 7, 0), (7, 8, 1),
+         (8, 9, 0), (9, 12, 1), (10, 15, 0), (12, 12, 1), (13, 20, 0)]
+
+
+@pytest.mark.parametrize("n,d,fp", CASES)
+@pytest.mark.parametrize("dense", [0.0, 0.5])
+def test_host_execution_matches_oracle(n, d, fp, dense):
+    c = H.mixed_circuit(n, d, 100 * n + d, first_parity=fp, dense=dense)
+    p = Plan.from_circuit(c)
+    psi = oracle.statevector(c)
+    bits = W.random_bitstrings(n, 5, W.rng_for(306, n, d))
+    for k in range(0, min(n - 1, d // 2, 8) + 1):
+        ref = oracle.amplitudes(c, bits, k, psi=psi)
+        got = p.debug_execute_host(bits, k)
+        assert np.max(np.abs(got - ref)) < 1e-12, k
+
+
+TILES = [dict(max_tile_bits=6, low_bits=2, reg_bits=3), dict(max_tile_bits=6, low_bits=1, reg_bits=5),
+         dict(max_tile_bits=7, low_bits=3, reg_bits=2), dict(max_tile_bits=8, low_bits=4, reg_bits=4), None]
+
+
+@pytest.mark.parametrize("opts", TILES)
+@pytest.mark.parametrize("n,d,fp", [(10, 20, 0), (11, 21, 1), (12, 24, 1), (9, 19, 0)])
+def test_device_emulation_matches_oracle(opts, n, d, fp):
+    c = H.mixed_circuit(n, d, 7 * n + d, first_parity=fp, dense=0.3)
+    p = Plan.from_circuit(c, opts)
+    psi = oracle.statevector(c)
+    bits = W.random_bitstrings(n, 3, W.rng_for(307, n, d))
+    for k in sorted({0, 1, d // 4, min(n - 1, d // 2, 6)}):
+        ref = oracle.amplitudes(c, bits, k, psi=psi)
+        got = p.debug_emulate_device(bits, k)
+        per, l2 = H.amp_errors(got, ref, n)
+        assert per < H.TOL_C64 and l2 < H.TOL_C64, (k, per, l2)
+
+
+@pytest.mark.parametrize("n,d", [(30, 12), (40, 9), (24, 16)])
+def test_emulation_matches_tableau_at_full_size(n, d):
+    # T-free Clifford circuits at n beyond the state vector: |psi|^2 from the
+    # lowering must equal the stabilizer-tableau probability.
+    c = W.brickwork_circuit(n, d, 0, W.rng_for(308, n, d))
+    _, words = W.clifford_table()
+    tab = tableau.run_clifford(c, words)
+    p = Plan.from_circuit(c, dict(max_tile_bits=6, low_bits=2, reg_bits=3))
+    rng = W.rng_for(308, 1)
+    xs = np.stack([tab.sample(rng) for _ in range(6)] + list(W.random_bitstrings(n, 6, rng)))
+    got = p.debug_emulate_device(xs, 0)[:, 0]
+    for x, a in zip(xs, got):
+        pt = tab.prob(x)
+        assert abs(abs(a) ** 2 - pt) <= 1e-5 * max(pt, 2.0 ** -n)
