@@ -6,7 +6,7 @@
 #include <cstdint>
 
 #if defined(__HIPCC__)
-#define TNC_HD __host__ __device__
+#define TNC_HD __host__ __device__ __attribute__((always_inline))
 #else
 #define TNC_HD
 #endif

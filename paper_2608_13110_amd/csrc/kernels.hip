@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
   }
   __syncthreads();
 
-  float2 v[E];
+  Regs<R> v;
   const uint32_t tmask = (1u << T) - 1u;
   for (int p = 0; p < a.n_phases; ++p) {
     const DevPhase P = a.phases[p];
@@ -138,7 +138,9 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
 #pragma unroll
       for (int b = 0; b < R; ++b)
         if (i & (1 << b)) r |= rm[b];
-      v[i] = *reinterpret_cast<const float2*>(region + (vbase ^ (swz(r) << 3)));
+      const float2 t = *reinterpret_cast<const float2*>(region + (vbase ^ (swz(r) << 3)));
+      v.x[i] = t.x;
+      v.y[i] = t.y;
     }
     run_phase_ops<R>(v, P, a.ops, a.mats, xb, tb);
 #pragma unroll
@@ -147,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
 #pragma unroll
       for (int b = 0; b < R; ++b)
         if (i & (1 << b)) r |= rm[b];
-      *reinterpret_cast<float2*>(region + (vbase ^ (swz(r) << 3))) = v[i];
+      *reinterpret_cast<float2*>(region + (vbase ^ (swz(r) << 3))) = make_float2(v.x[i], v.y[i]);
     }
     __syncthreads();
   }
@@ -222,21 +224,23 @@ static void emulate_pass_r(const PassArgs& a) {
         rmask |= rm[b];
       }
       for (int tt = 0; tt < tpt; ++tt) {
-        float2 v[E];
+        Regs<R> v;
         const uint32_t tb = pdep32((uint32_t)tt, tmask & ~rmask);
         const uint32_t vbase = swz(tb) << 3;
         for (int i = 0; i < E; ++i) {
           uint32_t r = 0;
           for (int b = 0; b < R; ++b)
             if (i & (1 << b)) r |= rm[b];
-          v[i] = *reinterpret_cast<const float2*>(region + (vbase ^ (swz(r) << 3)));
+          const float2 t = *reinterpret_cast<const float2*>(region + (vbase ^ (swz(r) << 3)));
+          v.x[i] = t.x;
+          v.y[i] = t.y;
         }
         run_phase_ops<R>(v, P, a.ops, a.mats, xb, tb);
         for (int i = 0; i < E; ++i) {
           uint32_t r = 0;
           for (int b = 0; b < R; ++b)
             if (i & (1 << b)) r |= rm[b];
-          *reinterpret_cast<float2*>(region + (vbase ^ (swz(r) << 3))) = v[i];
+          *reinterpret_cast<float2*>(region + (vbase ^ (swz(r) << 3))) = make_float2(v.x[i], v.y[i]);
         }
       }
     }

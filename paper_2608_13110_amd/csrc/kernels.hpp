@@ -45,68 +45,84 @@ TNC_HD inline uint32_t pdep32(uint32_t x, uint32_t mask) {
   return r;
 }
 
-// out = K * (b0, b1) with K = [k0 k1; k2 k3] given as 8 floats (re, im).
-TNC_HD inline void cmat2(const float* __restrict__ k, float2& b0, float2& b1) {
-  float2 o0, o1;
-  o0.x = k[0] * b0.x - k[1] * b0.y + k[2] * b1.x - k[3] * b1.y;
-  o0.y = k[0] * b0.y + k[1] * b0.x + k[2] * b1.y + k[3] * b1.x;
-  o1.x = k[4] * b0.x - k[5] * b0.y + k[6] * b1.x - k[7] * b1.y;
-  o1.y = k[4] * b0.y + k[5] * b0.x + k[6] * b1.y + k[7] * b1.x;
-  b0 = o0;
-  b1 = o1;
+// Register-resident complex64 entries of a thread: separate real and
+// imaginary float arrays (keeps every element promotable to a VGPR).
+template <int R>
+struct Regs {
+  float x[1 << R];
+  float y[1 << R];
+};
+
+// (b0, b1) <- K (b0, b1) with K = [k0 k1; k2 k3] given as 8 floats (re, im).
+TNC_HD inline void cmat2(const float* __restrict__ k, float& x0, float& y0, float& x1, float& y1) {
+  const float ox0 = k[0] * x0 - k[1] * y0 + k[2] * x1 - k[3] * y1;
+  const float oy0 = k[0] * y0 + k[1] * x0 + k[2] * y1 + k[3] * x1;
+  const float ox1 = k[4] * x0 - k[5] * y0 + k[6] * x1 - k[7] * y1;
+  const float oy1 = k[4] * y0 + k[5] * x0 + k[6] * y1 + k[7] * x1;
+  x0 = ox0;
+  y0 = oy0;
+  x1 = ox1;
+  y1 = oy1;
 }
 
+// The variants take and return the register set by value: the branches of
+// a dispatch then merge values, never element addresses, so every element
+// stays in a VGPR.
 template <int R, int A, int C>
-TNC_HD inline void op_reg(float2 (&v)[1 << R], const float* __restrict__ m) {
+TNC_HD inline Regs<R> op_reg(Regs<R> v, const float* __restrict__ m) {
 #pragma unroll
   for (int i = 0; i < (1 << R); ++i) {
     if (i & (1 << A)) continue;
-    cmat2(m + 8 * ((i >> C) & 1), v[i], v[i | (1 << A)]);
+    const int j = i | (1 << A);
+    cmat2(m + 8 * ((i >> C) & 1), v.x[i], v.y[i], v.x[j], v.y[j]);
   }
+  return v;
 }
 
 template <int R, int A>
-TNC_HD inline void op_sel(float2 (&v)[1 << R], const float* __restrict__ k) {
+TNC_HD inline Regs<R> op_sel(Regs<R> v, const float* __restrict__ k) {
 #pragma unroll
   for (int i = 0; i < (1 << R); ++i) {
     if (i & (1 << A)) continue;
-    cmat2(k, v[i], v[i | (1 << A)]);
+    const int j = i | (1 << A);
+    cmat2(k, v.x[i], v.y[i], v.x[j], v.y[j]);
   }
+  return v;
 }
 
 template <int R, int A>
-TNC_HD inline void op_dup(float2 (&v)[1 << R]) {
+TNC_HD inline Regs<R> op_dup(Regs<R> v) {
 #pragma unroll
   for (int i = 0; i < (1 << R); ++i) {
     if (i & (1 << A)) continue;
-    v[i | (1 << A)] = v[i];
+    v.x[i | (1 << A)] = v.x[i];
+    v.y[i | (1 << A)] = v.y[i];
   }
+  return v;
 }
 
 template <int R, int A, int C>
 struct RegDispatch {
-  static TNC_HD inline void run(float2 (&v)[1 << R], int a, int c, const float* __restrict__ m) {
+  static TNC_HD inline Regs<R> run(const Regs<R>& v, int a, int c, const float* __restrict__ m) {
     if (a == A && c == C) {
-      if constexpr (A != C) op_reg<R, A, C>(v, m);
-      return;
+      if constexpr (A != C) return op_reg<R, A, C>(v, m);
+      return v;
     }
     if constexpr (C + 1 < R) {
-      RegDispatch<R, A, C + 1>::run(v, a, c, m);
+      return RegDispatch<R, A, C + 1>::run(v, a, c, m);
     } else if constexpr (A + 1 < R) {
-      RegDispatch<R, A + 1, 0>::run(v, a, c, m);
+      return RegDispatch<R, A + 1, 0>::run(v, a, c, m);
     }
+    return v;
   }
 };
 
 template <int R, int A>
 struct SelDispatch {
-  static TNC_HD inline void run(float2 (&v)[1 << R], int a, const float* __restrict__ k, bool dup) {
-    if (a == A) {
-      if (dup) op_dup<R, A>(v);
-      else op_sel<R, A>(v, k);
-      return;
-    }
-    if constexpr (A + 1 < R) SelDispatch<R, A + 1>::run(v, a, k, dup);
+  static TNC_HD inline Regs<R> run(const Regs<R>& v, int a, const float* __restrict__ k, bool dup) {
+    if (a == A) return dup ? op_dup<R, A>(v) : op_sel<R, A>(v, k);
+    if constexpr (A + 1 < R) return SelDispatch<R, A + 1>::run(v, a, k, dup);
+    return v;
   }
 };
 
@@ -114,7 +130,7 @@ struct SelDispatch {
 //   tb: the thread part of the local tile index in this phase.
 //   xb: the output bits of this tile's batch.
 template <int R>
-TNC_HD inline void run_phase_ops(float2 (&v)[1 << R], const DevPhase& P, const DevOp* __restrict__ ops,
+TNC_HD inline void run_phase_ops(Regs<R>& v, const DevPhase& P, const DevOp* __restrict__ ops,
                                  const float* __restrict__ mats, const uint8_t* __restrict__ xb,
                                  uint32_t tb) {
   for (int o = P.op_begin; o < P.op_end; ++o) {
@@ -124,12 +140,12 @@ TNC_HD inline void run_phase_ops(float2 (&v)[1 << R], const DevPhase& P, const D
     if (op.xrow1 >= 0) var += xb[op.xrow1];
     const float* m = mats + ((size_t)op.mat * 4 + var) * 16;
     if (op.kind == 1) {
-      SelDispatch<R, 0>::run(v, op.treg, m, true);
+      v = SelDispatch<R, 0>::run(v, op.treg, m, true);
     } else if (op.creg >= R) {
       const int ctl = op.cloc >= 0 ? int((tb >> op.cloc) & 1u) : 0;
-      SelDispatch<R, 0>::run(v, op.treg, m + 8 * ctl, false);
+      v = SelDispatch<R, 0>::run(v, op.treg, m + 8 * ctl, false);
     } else {
-      RegDispatch<R, 0, 0>::run(v, op.treg, op.creg, m);
+      v = RegDispatch<R, 0, 0>::run(v, op.treg, op.creg, m);
     }
   }
 }

@@ -1,0 +1,205 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerance (complex64 boundary updates, FP64 join and reductions): every
+amplitude within 1e-5 * max(|ref|, 2^(-n/2)); the floor is the typical
+amplitude scale, needed because Clifford circuits have exact zeros.  Where
+no state vector fits (full n = 40 / 70) the GPU is checked by properties that
+hold at any size: a T-free circuit's probabilities equal the stabilizer
+tableau's, and Alg. 1 (k = 0) agrees with Alg. 2 (k > 0) component by
+component.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import helpers as H
+from tests.pinlib import tableau
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need the MI355X"
+    from paper_2608_13110_amd import lib
+    lib()
+    yield
+
+
+def gpu_amps(plan, bits, k, **kw):
+    print(f"  [gpu] n={plan.n} d={plan.d} k={k} batches={len(bits)}", flush=True)
+    d = torch.from_numpy(np.ascontiguousarray(bits, dtype=np.uint8)).cuda()
+    out = plan.amplitudes(d, k, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def assert_close(got, ref, n, tol=H.TOL_C64):
+    per, l2 = H.amp_errors(got, ref, n)
+    assert per < tol, (per, l2)
+
+
+def all_bits(n):
+    x = np.arange(1 << n)
+    return ((x[:, None] >> np.arange(n - 1, -1, -1)[None, :]) & 1).astype(np.uint8)
+
+
+def test_tiny_config_all_amplitudes_k0():
+    from paper_2608_13110_amd import Plan
+    c = W.config_circuit(0)
+    psi = oracle.statevector(c)
+    got = gpu_amps(Plan.from_circuit(c), all_bits(c.n), 0)[:, 0]
+    assert_close(got, psi, c.n)
+
+
+def test_tiny_config_all_amplitudes_k3():
+    from paper_2608_13110_amd import Plan
+    c = W.config_circuit(0)
+    psi = oracle.statevector(c)
+    prefixes = all_bits(c.n - 3)
+    bits = np.concatenate([prefixes, np.zeros((len(prefixes), 3), np.uint8)], axis=1)
+    got = gpu_amps(Plan.from_circuit(c), bits, 3)
+    assert_close(got.reshape(-1), psi, c.n)
+
+
+SMALL = [
+    # n, d, first_parity, dense fraction, k, batches, options
+    (2, 2, 1, 0.0, 0, 3, None),
+    (2, 3, 0, 0.5, 1, 2, None),
+    (3, 3, 1, 0.0, 1, 4, None),
+    (5, 7, 0, 0.5, 1, 1, None),
+    (8, 9, 1, 0.3, 2, 257, None),
+    (9, 12, 0, 0.3, 3, 33, None),
+    (10, 20, 1, 0.3, 5, 9, dict(max_tile_bits=6, low_bits=2, reg_bits=3)),
+    (11, 21, 0, 0.3, 0, 5, dict(max_tile_bits=7, low_bits=3, reg_bits=4)),
+    (12, 24, 1, 0.3, 6, 4, dict(max_tile_bits=8, low_bits=4, reg_bits=2)),
+    (13, 25, 0, 0.0, 8, 3, dict(max_tile_bits=6, low_bits=1, reg_bits=5)),
+    (16, 30, 1, 0.0, 4, 8, None),
+    (14, 29, 0, 0.3, 2, 6, None),
+]
+
+
+@pytest.mark.parametrize("n,d,fp,dense,k,nb,opts", SMALL)
+def test_small_circuits(n, d, fp, dense, k, nb, opts):
+    from paper_2608_13110_amd import Plan
+    c = H.mixed_circuit(n, d, 11 * n + d, first_parity=fp, dense=dense)
+    bits = W.random_bitstrings(n, nb, W.rng_for(401, n, d))
+    ref = oracle.amplitudes(c, bits, k)
+    got = gpu_amps(Plan.from_circuit(c, opts), bits, k)
+    assert_close(got, ref, n)
+
+
+def test_medium_config_restriction():
+    # medium workload (d = 40, w = 20), restricted to 24 qubits, 64 batches, k = 6
+    from paper_2608_13110_amd import Plan
+    c = W.restrict(W.config_circuit(1), 24)
+    bits = W.config_bitstrings(1)[:, :24]
+    ref = oracle.amplitudes(c, bits, 6)
+    got = gpu_amps(Plan.from_circuit(c), bits, 6)
+    assert_close(got, ref, c.n)
+
+
+def test_medium_config_full_alg1_matches_alg2():
+    # n = 40 (no state vector): k = 0 amplitudes equal the k = 6 batch components
+    from paper_2608_13110_amd import Plan
+    c = W.config_circuit(1)
+    p = Plan.from_circuit(c)
+    bits = W.config_bitstrings(1)
+    batch = gpu_amps(p, bits, 6)
+    single = gpu_amps(p, bits, 0)[:, 0]
+    b = (bits[:, -6:].astype(np.int64) * (1 << np.arange(5, -1, -1))).sum(axis=1)
+    comp = batch[np.arange(len(bits)), b]
+    per = np.abs(single - comp) / np.maximum(np.abs(comp), 2.0 ** (-c.n / 2))
+    assert per.max() < 2 * H.TOL_C64
+
+
+def test_precision_config_restriction():
+    # precision workload shape (d = 56, w = 28) restricted to 22 qubits, k = 8
+    from paper_2608_13110_amd import Plan
+    c = W.restrict(W.config_circuit(2), 22)
+    bits = W.config_bitstrings(2)[:3, :22]
+    ref = oracle.amplitudes(c, bits, 8)
+    got = gpu_amps(Plan.from_circuit(c), bits, 8)
+    assert_close(got, ref, c.n)
+
+
+def test_full_width_restriction():
+    # full-width shape (d = 66, w = 33: a 2^33 complex64 boundary tensor)
+    # restricted to 22 qubits, k = 8, the launch configuration of the benchmark
+    from paper_2608_13110_amd import Plan
+    c = W.restrict(W.config_circuit(4), 22)
+    bits = W.config_bitstrings(4)[:1, :22]
+    ref = oracle.amplitudes(c, bits, 8)
+    got = gpu_amps(Plan.from_circuit(c), bits, 8)
+    assert_close(got, ref, c.n)
+
+
+@pytest.mark.parametrize("n,d,k", [(70, 20, 0), (70, 21, 4), (40, 33, 8)])
+def test_full_size_clifford_matches_tableau(n, d, k):
+    from paper_2608_13110_amd import Plan
+    c = W.brickwork_circuit(n, d, 0, W.rng_for(402, n, d))
+    _, words = W.clifford_table()
+    tab = tableau.run_clifford(c, words)
+    rng = W.rng_for(402, 1)
+    bits = np.stack([tab.sample(rng) for _ in range(3)] + list(W.random_bitstrings(n, 2, rng)))
+    got = gpu_amps(Plan.from_circuit(c), bits, k)
+    for row, amps in zip(bits, got):
+        for b in range(0, 1 << k, max(1, (1 << k) // 8)):
+            x = row.copy()
+            for j in range(k):
+                x[n - k + j] = (b >> (k - 1 - j)) & 1
+            pt = tab.prob(x)
+            # |a|^2 has twice the relative error of a: 2 * TOL_C64
+            assert abs(abs(amps[b]) ** 2 - pt) <= 2 * H.TOL_C64 * max(pt, 2.0 ** -n)
+
+
+def test_logxeb_matches_oracle():
+    from paper_2608_13110_amd import Plan, logxeb
+    # random unitary one-qubit gates: no near-zero probabilities, so ln p is
+    # well conditioned (doped-Clifford circuits have exact zeros)
+    c = W.with_gate_values(W.config_circuit(0), W.rng_for(403, 2))
+    bits = W.random_bitstrings(c.n, 40, W.rng_for(403, 1))
+    p = Plan.from_circuit(c)
+    amps = p.amplitudes(torch.from_numpy(bits).cuda(), 3)
+    sel_np = (bits[:, -3:].astype(np.int32) * np.array([4, 2, 1], np.int32)).sum(1).astype(np.int32)
+    res = logxeb(amps, 3, c.n, select=torch.from_numpy(sel_np).cuda()).cpu().numpy()
+    # the FP64 reduction itself, on the same amplitudes
+    g = amps.cpu().numpy()
+    f, se, lo, hi = oracle.logxeb(np.abs(g[np.arange(40), sel_np]) ** 2, c.n)
+    assert np.allclose(res, [f, se, lo, hi, 40], rtol=1e-12, atol=1e-12)
+    # end to end against the oracle's amplitudes (ln p error ~ 2 * TOL_C64)
+    z = oracle.amplitudes(c, bits, 3)
+    f, se, lo, hi = oracle.logxeb(np.abs(z[np.arange(40), sel_np]) ** 2, c.n)
+    assert abs(res[0] - f) < 1e-4 and abs(res[1] - se) < 1e-4
+    # every component of every batch
+    allr = logxeb(amps, 3, c.n).cpu().numpy()
+    f2, se2, _, _ = oracle.logxeb(np.abs(g.reshape(-1)) ** 2, c.n)
+    assert abs(allr[0] - f2) < 1e-12 and allr[4] == 40 * 8
+
+
+def test_workspace_groups_and_nomem():
+    from paper_2608_13110_amd import TNC_E_NOMEM, Plan, TncError
+    c = H.mixed_circuit(12, 22, 5)
+    p = Plan.from_circuit(c)
+    bits = W.random_bitstrings(c.n, 5, W.rng_for(404, 1))
+    full = gpu_amps(p, bits, 3)
+    ws = torch.empty(p.workspace_bytes(3, 2), dtype=torch.uint8, device="cuda")
+    grouped = gpu_amps(p, bits, 3, workspace=ws)
+    assert np.array_equal(full, grouped)
+    small = torch.empty(p.workspace_bytes(3, 1) - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(TncError) as e:
+        gpu_amps(p, bits, 3, workspace=small)
+    assert e.value.code == TNC_E_NOMEM
+
+
+def test_bitwise_deterministic():
+    from paper_2608_13110_amd import Plan
+    c = H.mixed_circuit(18, 34, 6)
+    p = Plan.from_circuit(c)
+    bits = W.random_bitstrings(c.n, 4, W.rng_for(405, 1))
+    a = gpu_amps(p, bits, 4)
+    b = gpu_amps(p, bits, 4)
+    assert np.array_equal(a, b)
