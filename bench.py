@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark of the temporal-boundary amplitude engine on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload full_width|precision]
+
+A step is one pass of the whole hot path (row-0 build-up, the fixed sweep,
+the join and the late phase) over one amplitude batch of the workload,
+inputs resident in HBM.  Default workload: the one-GPU full-width shape
+(n = 70, d = 66, w = 33: a 2^33-entry complex64 boundary tensor, 468 T gates,
+k = 8 open legs -> 256 amplitudes per batch, 8 seeded bitstring batches used
+round robin).  The precision shape (n = 70, d = 56, w = 28, 400 T, 16 batches)
+is measured beside it.  Prints one JSON line.
+
+`roofline` is for the dominant kernel (the sweep pass): algorithmic bytes per
+launch (read + write of the 2^h complex64 boundary tensor) over its average
+duration measured with HIP events on its launch stream; `traffic` is the
+counter-based HBM bytes per launch recorded in profiles/ for the current
+kernel source (null when absent or stale).  `cpu_baseline` times the oracle
+(FP64 state vector) on a bounded restriction of the same circuit.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+FP32_VALU_PEAK_TFLOPS = 78.6    # non-packed FP32 (256 CU x 64 lanes x 2 x 2.4 GHz)
+METRIC = "amplitudes/s and boundary-tensor HBM GB/s (% of peak) at w=28/33; p99 latency"
+
+WORKLOADS = {
+    "full_width": dict(cid=4, k=8, desc="full_width n=70 d=66 w=33 T=468 k=8 (2^33 c64 boundary), 1 batch/step"),
+    "precision": dict(cid=2, k=8, desc="precision n=70 d=56 w=28 T=400 k=8 (2^28 c64 boundary), 1 batch/step"),
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp", "device_tables.hpp"):
+        with open(os.path.join(ROOT, "paper_2608_13110_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload: str):
+    """HBM bytes per pass launch from the committed counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_pass_{workload}_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[i]
+
+
+def run_workload(name, steps, warmup, torch, W, Plan, profile_begin, profile_end):
+    spec = WORKLOADS[name]
+    k = spec["k"]
+    circ = W.config_circuit(spec["cid"])
+    bits_all = W.config_bitstrings(spec["cid"])
+    t0 = time.time()
+    plan = Plan.from_circuit(circ)
+    plan.prepare(k)
+    prep_s = time.time() - t0
+    info = plan.info(k)
+    dev_bits = torch.from_numpy(bits_all).cuda()
+    out = torch.empty((len(bits_all), 1 << k), dtype=torch.complex128, device="cuda")
+    ws = torch.empty(plan.workspace_bytes(k, 1), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(i):
+        j = i % len(bits_all)
+        plan.amplitudes(dev_bits[j:j + 1], k, out=out[j:j + 1], workspace=ws, stream=stream)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for i in range(steps):
+        evs[i][0].record(stream)
+        step(warmup + i)
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    prof = profile_end()
+    lat_ms = [a.elapsed_time(b) for a, b in evs]
+    amps = steps * (1 << k)
+    pass_gbs = prof["pass_bytes"] / (prof["pass_ms"] / 1e3) / 1e9 if prof["pass_ms"] > 0 else 0.0
+    h = info["boundary_bits"]
+    # algorithmic FLOPs of the sweep: every update is a complex 2x2 on each
+    # pair of entries, 14 real flops per entry
+    sweep_flops = info["n_ops"] * 14.0 * (1 << h) * steps
+    return dict(
+        workload=spec["desc"], k=k, h=h, steps=steps, wall_s=wall, prep_s=prep_s,
+        amplitudes_per_s=amps / wall, ms_per_step=1e3 * wall / steps,
+        latency_ms_p50=pct(lat_ms, 50), latency_ms_p99=pct(lat_ms, 99),
+        pass_launches=prof["pass_launches"], pass_ms=prof["pass_ms"], late_ms=prof["late_ms"],
+        init_ms=prof["init_ms"], pass_gbs=pass_gbs, pass_bytes_per_launch=prof["pass_bytes"] / max(1, prof["pass_launches"]),
+        pass_avg_ms=prof["pass_ms"] / max(1, prof["pass_launches"]),
+        sweep_tflops=sweep_flops / (prof["pass_ms"] / 1e3) / 1e12 if prof["pass_ms"] > 0 else 0.0,
+        n_passes=info["n_passes"], n_ops=info["n_ops"], log2_cost=info["log2_cost"],
+    )
+
+
+def cpu_baseline(W):
+    """The oracle on a bounded restriction of the full-width circuit."""
+    import numpy as np
+    import oracle
+    n_r = 26
+    circ = W.restrict(W.config_circuit(4), n_r)
+    bits = W.config_bitstrings(4)[:, :n_r]
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    t0 = time.time()
+    psi = oracle.statevector(circ)
+    z = oracle.amplitudes(circ, bits, 8, psi=psi)
+    dt = time.time() - t0
+    assert np.isfinite(z).all()
+    return {"value": len(bits) * 256 / dt, "unit": "amplitudes/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 state vector of the full-width circuit restricted to qubits 0..{n_r - 1} "
+                      f"(n={n_r}, d=66, all 67 one-qubit layers), 8 batches x 256 requested amplitudes; "
+                      f"{dt:.1f} s; n=70 itself does not fit a state vector"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="full_width")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the contraction is "
+              f"not sharded in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    from paper_2608_13110_amd import Plan, profile_begin, profile_end
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    main_r = run_workload(args.workload, args.steps, args.warmup, torch, W, Plan, profile_begin, profile_end)
+    torch.cuda.empty_cache()
+    secondary = None
+    if not args.no_secondary:
+        other = "precision" if args.workload == "full_width" else "full_width"
+        steps2 = 16 if other == "precision" else 2
+        secondary = run_workload(other, steps2, 1, torch, W, Plan, profile_begin, profile_end)
+        torch.cuda.empty_cache()
+    traffic = recorded_traffic(args.workload)
+    roofline = {
+        "bound": "hbm", "achieved": round(main_r["pass_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(main_r["pass_gbs"] / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "kernel": "k_pass", "bytes_per_launch": main_r["pass_bytes_per_launch"],
+        "avg_launch_ms": round(main_r["pass_avg_ms"], 4),
+        "alu": {"achieved_tflops": round(main_r["sweep_tflops"], 2), "peak_tflops": FP32_VALU_PEAK_TFLOPS,
+                "frac": round(main_r["sweep_tflops"] / FP32_VALU_PEAK_TFLOPS, 4)},
+    }
+    line = {
+        "metric": METRIC, "value": round(main_r["amplitudes_per_s"], 3), "unit": "amplitudes/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(main_r["ms_per_step"], 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": main_r["workload"], "batch_amplitudes": 1 << main_r["k"],
+                   "boundary_bits": main_r["h"], "passes": main_r["n_passes"], "updates": main_r["n_ops"],
+                   "log2_cost": round(main_r["log2_cost"], 3)},
+        "hbm_gbs": round(main_r["pass_gbs"], 1), "hbm_frac": roofline["frac"],
+        "latency_ms_p50": main_r["latency_ms_p50"], "latency_ms_p99": main_r["latency_ms_p99"],
+        "kernel_ms": {"pass": round(main_r["pass_ms"], 2), "late": round(main_r["late_ms"], 2),
+                      "init": round(main_r["init_ms"], 2)},
+        "roofline": roofline,
+    }
+    if secondary is not None:
+        line["secondary"] = {k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in secondary.items()
+                             if k2 in ("workload", "amplitudes_per_s", "pass_gbs", "latency_ms_p50",
+                                       "latency_ms_p99", "ms_per_step", "steps", "pass_avg_ms")}
+        line["secondary"]["hbm_frac"] = round(secondary["pass_gbs"] / HBM_PEAK_GBS, 4)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(W)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

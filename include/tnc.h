@@ -147,6 +147,25 @@ int tnc_amplitudes_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits,
 int tnc_logxeb(const tnc_c128* d_amp, int32_t n_batches, int32_t k, const int32_t* d_select, int32_t n_qubits,
                double* d_result, void* stream);
 
+/*
+ * Kernel timing with HIP events recorded on the launch stream around every
+ * launch of tnc_amplitudes while profiling is on (process-wide).
+ * tnc_profile_end waits for the recorded events and returns the summed
+ * durations per kernel class (row-0 build-up, sweep passes, late phase).
+ */
+typedef struct {
+  double init_ms;
+  double pass_ms;
+  double late_ms;
+  int64_t init_launches;
+  int64_t pass_launches;
+  int64_t late_launches;
+  double pass_bytes;  /* algorithmic bytes of the passes: 2 * 2^h * 8 per batch and pass */
+} tnc_profile;
+
+int tnc_profile_begin(void);
+int tnc_profile_end(tnc_profile* out);
+
 /* Free a plan and its device tables.  NULL is ignored. */
 void tnc_release(tnc_plan_t plan);
 

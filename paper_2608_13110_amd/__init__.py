@@ -34,7 +34,7 @@ STORE_C64 = 0
 EXPORTED = [
     "tnc_plan", "tnc_plan_info", "tnc_prepare", "tnc_workspace_bytes", "tnc_amplitudes",
     "tnc_amplitudes_host", "tnc_logxeb", "tnc_release", "tnc_strerror", "tnc_last_error",
-    "tnc_debug_execute_host", "tnc_debug_emulate_device",
+    "tnc_debug_execute_host", "tnc_debug_emulate_device", "tnc_profile_begin", "tnc_profile_end",
 ]
 
 
@@ -70,6 +70,15 @@ class Info(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("init_ms", ctypes.c_double), ("pass_ms", ctypes.c_double), ("late_ms", ctypes.c_double),
+                ("init_launches", ctypes.c_int64), ("pass_launches", ctypes.c_int64),
+                ("late_launches", ctypes.c_int64), ("pass_bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -97,6 +106,8 @@ def lib() -> ctypes.CDLL:
     L.tnc_last_error.restype = ctypes.c_char_p
     L.tnc_debug_execute_host.argtypes = [vp, i32, vp, i32, vp]
     L.tnc_debug_emulate_device.argtypes = [vp, i32, vp, i32, vp]
+    L.tnc_profile_begin.argtypes = []
+    L.tnc_profile_end.argtypes = [ctypes.POINTER(Profile)]
     for name in EXPORTED:
         if name not in ("tnc_release", "tnc_strerror", "tnc_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -219,6 +230,18 @@ class Plan:
         out = np.empty((bits.shape[0], 1 << k), dtype=np.complex128)
         _check(lib().tnc_debug_emulate_device(self._h, bits.shape[0], bits.ctypes.data, int(k), out.ctypes.data))
         return out
+
+
+def profile_begin():
+    """Start recording HIP events around every kernel launch (process-wide)."""
+    _check(lib().tnc_profile_begin())
+
+
+def profile_end() -> dict:
+    """Stop recording; wait for the events and return summed kernel times."""
+    pr = Profile()
+    _check(lib().tnc_profile_end(ctypes.byref(pr)))
+    return pr.as_dict()
 
 
 def logxeb(amps, k: int, n_qubits: int, select=None, stream=None):

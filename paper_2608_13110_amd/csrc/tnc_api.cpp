@@ -237,6 +237,42 @@ int get_dev_sched(Plan& p, int k, std::shared_ptr<DevSched>* out) {
   return 0;
 }
 
+// Process-wide event timing of kernel launches (tnc_profile_*).
+struct Profiler {
+  std::mutex mu;
+  bool active = false;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Rec> recs;
+};
+Profiler g_prof;
+
+// Records an event pair around `launch` when profiling is on.
+template <typename F>
+hipError_t timed(int cls, double bytes, hipStream_t s, F&& launch) {
+  bool on;
+  {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    on = g_prof.active;
+  }
+  if (!on) return launch();
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = hipEventRecord(a, s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, s);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.recs.push_back({cls, a, b, bytes});
+  return hipSuccess;
+}
+
 InitArgs init_args(const Plan& p, const HostTables& t, float2* B, const uint8_t* bits, int nb,
                    const double2* d_seg) {
   InitArgs a;
@@ -336,16 +372,19 @@ int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k
     double2* L1 = reinterpret_cast<double2*>(base + (t.bytes_B + t.bytes_late[0]) * (uint64_t)nb);
     const uint8_t* bits = d_bits + (size_t)b0 * p.n;
     double2* out = reinterpret_cast<double2*>(d_out) + ((size_t)b0 << k);
-    hipError_t e = launch_init(init_args(p, t, B, bits, nb, ds.d_seg), stream);
+    hipError_t e = timed(0, 0.0, stream, [&] { return launch_init(init_args(p, t, B, bits, nb, ds.d_seg), stream); });
     if (e != hipSuccess) return hip_err(e, "init launch");
+    const double pass_bytes = 2.0 * 8.0 * (double)(1ull << p.h) * nb;
     for (const PassHost& ph : t.passes) {
-      e = launch_pass(pass_args(p, ph, ds.d_phases, ds.d_ops, ds.d_mats, B, bits, nb), ph.R, stream);
+      e = timed(1, pass_bytes, stream, [&] {
+        return launch_pass(pass_args(p, ph, ds.d_phases, ds.d_ops, ds.d_mats, B, bits, nb), ph.R, stream);
+      });
       if (e != hipSuccess) return hip_err(e, "pass launch");
     }
     const LateFirst& F = t.late.first;
     double2* fout = F.final ? out : L0;
     const long long fstride = F.final ? (1ll << k) : (long long)(t.bytes_late[0] / 16);
-    e = launch_late(first_args(p, t, B, fout, fstride, ds.d_J, bits, nb), true, stream);
+    e = timed(2, 0.0, stream, [&] { return launch_late(first_args(p, t, B, fout, fstride, ds.d_J, bits, nb), true, stream); });
     if (e != hipSuccess) return hip_err(e, "late launch");
     const double2* cur = L0;
     long long cur_stride = fstride;
@@ -355,7 +394,7 @@ int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k
       const long long dstride = ln.final ? (1ll << k) : (long long)(t.bytes_late[(i + 1) & 1] / 16);
       LateOpsArgs a = ops_args(p, t, ln, cur, dst, dstride, ds.d_prog, bits, nb, k);
       a.in_batch_stride = cur_stride;
-      e = launch_late_ops(a, stream);
+      e = timed(2, 0.0, stream, [&] { return launch_late_ops(a, stream); });
       if (e != hipSuccess) return hip_err(e, "late-ops launch");
       cur = dst;
       cur_stride = dstride;
@@ -615,6 +654,41 @@ int tnc_logxeb(const tnc_c128* d_amp, int32_t n_batches, int32_t k, const int32_
                                static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_err(e, "logxeb launch");
   return TNC_OK;
+}
+
+int tnc_profile_begin(void) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  for (auto& r : g_prof.recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof.recs.clear();
+  g_prof.active = true;
+  return TNC_OK;
+}
+
+int tnc_profile_end(tnc_profile* out) {
+  if (!out) return set_err(TNC_E_INVALID, "null argument");
+  std::vector<Profiler::Rec> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.active = false;
+    recs.swap(g_prof.recs);
+  }
+  std::memset(out, 0, sizeof(*out));
+  int rc = TNC_OK;
+  for (auto& r : recs) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess && rc == TNC_OK) rc = hip_err(e, "event timing");
+    if (r.cls == 0) out->init_ms += ms, out->init_launches++;
+    if (r.cls == 1) out->pass_ms += ms, out->pass_launches++, out->pass_bytes += r.bytes;
+    if (r.cls == 2) out->late_ms += ms, out->late_launches++;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  return rc;
 }
 
 void tnc_release(tnc_plan_t plan) {
