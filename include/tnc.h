@@ -69,9 +69,15 @@ typedef struct {
 /* Tiling options of the pass kernels; zero fields take the defaults. */
 typedef struct {
   int32_t max_tile_bits; /* entries per pass tile = 2^max_tile_bits (default 13, 6..13) */
-  int32_t reg_bits;      /* entries per thread = 2^reg_bits (default 5, 1..5) */
+  int32_t reg_bits;      /* entries per thread = 2^reg_bits (default 5, 1..5); 256 threads
+                            per tile; max_tile_bits - reg_bits = 9 (512 threads) only with
+                            pipeline = 1 and math = 0 */
   int32_t low_bits;      /* contiguous low slots in every non-bottom tile (default 4) */
-  int32_t reserved;
+  int32_t math;          /* 0: vector-ALU updates (default); 1: matrix-core updates
+                            (v_mfma_f32_4x4x1_16b_f32) where a block holds one tile */
+  int32_t pipeline;      /* 0: one tile per block (default); 1: persistent blocks that prefetch
+                            the next tile into LDS while updating the current one */
+  int32_t reserved[3];
 } tnc_options;
 
 typedef struct {

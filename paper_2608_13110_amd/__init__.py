@@ -55,7 +55,8 @@ class Gate2(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("max_tile_bits", ctypes.c_int32), ("reg_bits", ctypes.c_int32),
-                ("low_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("low_bits", ctypes.c_int32), ("math", ctypes.c_int32),
+                ("pipeline", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Info(ctypes.Structure):
@@ -147,7 +148,8 @@ class Plan:
         opt = None
         if options:
             opt = Options(int(options.get("max_tile_bits", 0)), int(options.get("reg_bits", 0)),
-                          int(options.get("low_bits", 0)), 0)
+                          int(options.get("low_bits", 0)), int(options.get("math", 0)),
+                          int(options.get("pipeline", 0)))
         h = ctypes.c_void_p()
         self._one = one
         _check(L.tnc_plan(self.n, self.d, one.ctypes.data, len(gates), ctypes.addressof(garr),

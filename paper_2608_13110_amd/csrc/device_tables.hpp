@@ -13,41 +13,45 @@
 
 namespace tnc {
 
-// One boundary-tensor update inside a pass (16 bytes).
-//   kind 0 (CU): pairs along register bit `treg`; the 2x2 is chosen by the
-//                control value: register bit `creg` (0..R-1), or, when
-//                creg == R, the tile bit `cloc` of the thread part (cloc < 0:
-//                no control, value 0).
-//   kind 1 (DUP): the register half with bit `treg` = 1 is overwritten by
-//                the half with bit `treg` = 0.
-// The matrices live at mats[(mat*4 + var)*16 .. +16): [ctl][m00 m01 m10 m11]
-// as (re, im) float pairs, var = 2*x[xrow0] + x[xrow1].
+// One boundary-tensor update inside a pass (16 bytes).  Within a register
+// phase, op b acts on the pairs along register bit b; ops b >= 1 are
+// controlled by register bit b-1, op 0 by the tile bit `cloc` of the thread
+// part (cloc < 0: no control), or op 0 is the phase's DUP.
+// Matrices: mats[(mat*4 + var)*16 ..+16): [ctl][k00 k01 k10 k11 as (re, im)],
+// var = 2*x[xrow0] + x[xrow1] (an absent row reads as 0).
 struct DevOp {
-  int8_t kind;
-  int8_t treg;
-  int8_t creg;
-  int8_t cloc;
   int16_t xrow0;
   int16_t xrow1;
+  int8_t cloc;
+  int8_t pad0[3];
   int32_t mat;
-  int32_t pad;
+  int32_t pad1;
 };
 static_assert(sizeof(DevOp) == 16, "DevOp layout");
 
-// A register phase of a pass: ops [op_begin, op_end) run with local tile
+// A register phase: n_ops consecutive ops from op_begin, run with local tile
 // bits reg[0..R-1] held in registers (register bit b <-> local bit reg[b]).
+// first_dup: op 0 copies the register half with bit 0 clear onto the half
+// with bit 0 set (the top-slot expand of odd depth).
 struct DevPhase {
   int32_t op_begin;
-  int32_t op_end;
+  int8_t n_ops;
+  int8_t first_dup;
   int8_t reg[8];
+  int16_t pad;
 };
 static_assert(sizeof(DevPhase) == 16, "DevPhase layout");
 
 // Launch parameters of one pass (a kernel argument).
+//   mats:  per op [var 4][ctl 2][k00 k01 k10 k11 as (re, im)]  (16 floats / var)
+//   mrows: per op [var 4][ctl 2][row 4][4]: the real 4x4 form of the same
+//          2x2, acting on (re b0, im b0, re b1, im b1); row r feeds the
+//          matrix-core update's A operand of lane r (mod 4)
 struct PassArgs {
   const DevPhase* phases;
   const DevOp* ops;
   const float* mats;
+  const float4* mrows;
   float2* B;             // boundary tensors, batch stride 2^h entries
   const uint8_t* bits;   // output bits, batch stride n
   int n_phases;
@@ -56,6 +60,10 @@ struct PassArgs {
   int T;                 // tile bits
   int lo_bits, win_lo, win_len;
   int n_tiles;           // batches << (h - T)
+  int mfma;              // register-controlled updates on the matrix cores
+  int pipeline;          // persistent blocks prefetching the next tile
+  int op_begin;          // this pass's ops: [op_begin, op_begin + n_ops)
+  int n_ops;
 };
 
 // Launch parameters of a late-phase folded contraction:

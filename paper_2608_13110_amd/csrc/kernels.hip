@@ -8,6 +8,7 @@
 //  k_logxeb FP64 log-XEB reduction
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <vector>
 
@@ -89,7 +90,7 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s) {
 //   slots as register bits), the phase's updates in registers, registers ->
 //   LDS,
 //   LDS -> HBM, in place.
-template <int R, bool MULTI>
+template <int R, bool MULTI, bool MF>
 __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
   extern __shared__ float2 lds[];
   constexpr int E = 1 << R;
@@ -106,7 +107,6 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
   const unsigned long long blk = active ? ((unsigned long long)tile & ((1ull << tbits) - 1ull)) : 0ull;
   float2* __restrict__ Bt = a.B + (batch << a.h) + block_offset(blk, a.lo_bits, a.win_lo, a.win_len);
   char* region = reinterpret_cast<char*>(lds) + ((size_t)tile_in_block << (T + 3));
-  const uint8_t* xb = a.bits + batch * a.n;
   const int tpt = 1 << TB;
 
   if (active) {
@@ -119,38 +119,19 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
   }
   __syncthreads();
 
-  Regs<R> v;
   const uint32_t tmask = (1u << T) - 1u;
+  PhaseCtx<R, MF> ctx;
+  ctx.ops = (const TNC_TBL DevOp*)a.ops;
+  ctx.mats = (const TNC_TBL float*)a.mats;
+  ctx.mrows = a.mrows;
+  ctx.bits = a.bits;
+  ctx.xpos = (size_t)batch * a.n;
+  ctx.tb = 0;
+  ctx.lane = tid & 63;
+  ctx.uniform = !MULTI;
   for (int p = 0; p < a.n_phases; ++p) {
-    const DevPhase P = a.phases[p];
-    uint32_t rm[R];
-    uint32_t rmask = 0;
-#pragma unroll
-    for (int b = 0; b < R; ++b) {
-      rm[b] = 1u << P.reg[b];
-      rmask |= rm[b];
-    }
-    const uint32_t tb = pdep32(tt, tmask & ~rmask);
-    const uint32_t vbase = swz(tb) << 3;
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      uint32_t r = 0;
-#pragma unroll
-      for (int b = 0; b < R; ++b)
-        if (i & (1 << b)) r |= rm[b];
-      const float2 t = *reinterpret_cast<const float2*>(region + (vbase ^ (swz(r) << 3)));
-      v.x[i] = t.x;
-      v.y[i] = t.y;
-    }
-    run_phase_ops<R>(v, P, a.ops, a.mats, xb, tb);
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      uint32_t r = 0;
-#pragma unroll
-      for (int b = 0; b < R; ++b)
-        if (i & (1 << b)) r |= rm[b];
-      *reinterpret_cast<float2*>(region + (vbase ^ (swz(r) << 3))) = make_float2(v.x[i], v.y[i]);
-    }
+    const DevPhase P = ((const TNC_TBL DevPhase*)a.phases)[p];
+    phase_dispatch<R, MF>(region, P, ctx, tt, tmask);
     __syncthreads();
   }
 
@@ -164,18 +145,242 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
   }
 }
 
+// Persistent, software-pipelined form of the pass for one 2^T-entry tile
+// per 256-thread block (T - R = 8): each block walks tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ...; the next tile's HBM loads are issued right
+// after the current tile has been staged in LDS, so they are in flight while
+// the current tile's register phases run.
+template <int R, bool MF>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pass_pipe(PassArgs a) {
+  extern __shared__ float2 lds[];
+  constexpr int E = 1 << R;
+  constexpr int HALF = E / 2;
+  const int T = a.T;
+  const int tid = threadIdx.x;
+  const uint32_t tt = (uint32_t)tid;
+  const int tbits = a.h - T;
+  char* region = reinterpret_cast<char*>(lds);
+  const uint32_t tmask = (1u << T) - 1u;
+  auto tile_base = [&](long long tile) -> float2* {
+    const long long batch = tile >> tbits;
+    const unsigned long long blk = (unsigned long long)tile & ((1ull << tbits) - 1ull);
+    return a.B + (batch << a.h) + block_offset(blk, a.lo_bits, a.win_lo, a.win_len);
+  };
+  // prefetch buffer as plain floats (arrays of HIP vector types can be kept
+  // out of registers)
+  float p0[HALF], p1[HALF], p2[HALF], p3[HALF];
+  auto prefetch = [&](long long t) {
+    const float2* src = tile_base(t);
+#pragma unroll
+    for (int it = 0; it < HALF; ++it) {
+      const uint32_t i = (uint32_t)(it * kBlock + tid) * 2u;
+      const float4 q = *reinterpret_cast<const float4*>(src + tile_offset(i, a.lo_bits, a.win_lo));
+      p0[it] = q.x;
+      p1[it] = q.y;
+      p2[it] = q.z;
+      p3[it] = q.w;
+    }
+  };
+  long long tile = blockIdx.x;
+  if (tile < a.n_tiles) prefetch(tile);
+  for (; tile < a.n_tiles; tile += gridDim.x) {
+    const long long batch = tile >> tbits;
+#pragma unroll
+    for (int it = 0; it < HALF; ++it) {
+      const uint32_t i = (uint32_t)(it * kBlock + tid) * 2u;
+      *reinterpret_cast<float4*>(region + ((size_t)swz(i) << 3)) = make_float4(p0[it], p1[it], p2[it], p3[it]);
+    }
+    __syncthreads();
+    const long long next = tile + gridDim.x;
+    if (next < a.n_tiles) prefetch(next);
+    PhaseCtx<R, MF> ctx;
+    ctx.ops = (const TNC_TBL DevOp*)a.ops;
+    ctx.mats = (const TNC_TBL float*)a.mats;
+    ctx.mrows = a.mrows;
+    ctx.bits = a.bits;
+    ctx.xpos = (size_t)batch * a.n;
+    ctx.tb = 0;
+    ctx.lane = tid & 63;
+    ctx.uniform = true;
+    for (int p = 0; p < a.n_phases; ++p) {
+      const DevPhase P = ((const TNC_TBL DevPhase*)a.phases)[p];
+      phase_dispatch<R, MF>(region, P, ctx, tt, tmask);
+      __syncthreads();
+    }
+    float2* dst = tile_base(tile);
+#pragma unroll
+    for (int it = 0; it < HALF; ++it) {
+      const uint32_t i = (uint32_t)(it * kBlock + tid) * 2u;
+      const float4 val = *reinterpret_cast<const float4*>(region + ((size_t)swz(i) << 3));
+      *reinterpret_cast<float4*>(dst + tile_offset(i, a.lo_bits, a.win_lo)) = val;
+    }
+    __syncthreads();
+  }
+}
+
+// Waits for outstanding vector-memory operations only (vmcnt <= n; gfx9
+// encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at
+// their maxima), and the LDS-only wait used before raw barriers.
+#define TNC_WAIT_VMCNT0() __builtin_amdgcn_s_waitcnt(0x0F70)
+// vmcnt <= n for n < 16 (vector-memory operations retire in issue order)
+#define TNC_WAIT_VMCNT(n) __builtin_amdgcn_s_waitcnt(0x0F70 | ((n) & 15))
+#define TNC_WAIT_LGKM0() __builtin_amdgcn_s_waitcnt(0xC07F)
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Persistent pass with double-buffered LDS tiles: the next tile is fetched
+// by direct global->LDS loads (global_load_lds_dwordx4, no VGPRs) while the
+// current tile's register phases run.  Slot pair p of a buffer holds tile
+// entries swz(p), swz(p)+1 (swz is an involution that keeps pairs), so the
+// register phases use the same placement as the other pass kernels.  Phase
+// barriers wait for LDS only, leaving the prefetch in flight.
+// One block per CU (two 2^T-entry LDS tiles): 4 or 8 waves per CU.
+template <int R, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT / 256))) void k_pass_dma(PassArgs a) {
+  constexpr int E = 1 << R;
+  constexpr int HALF = E / 2;
+  constexpr int T = R + (NT == 512 ? 9 : 8);
+  // two statically distinct buffers: the compiler can see that the phases
+  // never read the buffer the DMA is writing, so it adds no memory waits
+  __shared__ float2 ping[1 << T];
+  __shared__ float2 pong[1 << T];
+  const int tid = threadIdx.x;
+  const uint32_t tt = (uint32_t)tid;
+  const int tbits = a.h - T;
+  constexpr uint32_t tmask = (1u << T) - 1u;
+  const int wave = tid >> 6;
+  auto tile_base = [&](long long tile) -> float2* {
+    const long long batch = tile >> tbits;
+    const unsigned long long blk = (unsigned long long)tile & ((1ull << tbits) - 1ull);
+    return a.B + (batch << a.h) + block_offset(blk, a.lo_bits, a.win_lo, a.win_len);
+  };
+  auto fetch = [&](long long tile, float2* dst) {
+    const float2* src = tile_base(tile);
+#pragma unroll
+    for (int it = 0; it < HALF; ++it) {
+      const uint32_t p = (uint32_t)(it * NT + tid) * 2u;
+      const float2* g = src + tile_offset(swz(p), a.lo_bits, a.win_lo);
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(g),
+                                       (lds_void_t*)(reinterpret_cast<char*>(dst) + ((size_t)(it * NT + wave * 64) << 4)),
+                                       16, 0, 0);
+    }
+  };
+  // one tile: wait for its prefetch, start the next tile's, run the phases,
+  // store
+  auto process = [&](long long tile, float2* cur, float2* nxt) {
+    const long long batch = tile >> tbits;
+    // this tile's prefetch was issued before the previous tile's HALF
+    // stores, and vector-memory operations retire in issue order
+    TNC_WAIT_VMCNT(HALF);
+    TNC_WAIT_LGKM0();
+    __builtin_amdgcn_s_barrier();
+    const long long next = tile + gridDim.x;
+    if (next < a.n_tiles) fetch(next, nxt);
+    char* region = reinterpret_cast<char*>(cur);
+    PhaseCtx<R, false> ctx;
+    ctx.ops = (const TNC_TBL DevOp*)a.ops;
+    ctx.mats = (const TNC_TBL float*)a.mats;
+    ctx.mrows = nullptr;
+    ctx.bits = a.bits;
+    ctx.xpos = (size_t)batch * a.n;
+    ctx.tb = 0;
+    ctx.lane = tid & 63;
+    ctx.uniform = true;
+    for (int p = 0; p < a.n_phases; ++p) {
+      const DevPhase P = ((const TNC_TBL DevPhase*)a.phases)[p];
+      phase_dispatch<R, false>(region, P, ctx, tt, tmask);
+      TNC_WAIT_LGKM0();
+      __builtin_amdgcn_s_barrier();
+    }
+    float2* dst = tile_base(tile);
+#pragma unroll
+    for (int it = 0; it < HALF; ++it) {
+      const uint32_t i = (uint32_t)(it * NT + tid) * 2u;
+      const float4 val = *reinterpret_cast<const float4*>(region + ((size_t)swz(i) << 3));
+      *reinterpret_cast<float4*>(dst + tile_offset(i, a.lo_bits, a.win_lo)) = val;
+    }
+  };
+  long long tile = blockIdx.x;
+  if (tile >= a.n_tiles) return;
+  fetch(tile, ping);
+  // the first tile has no stores queued behind its loads: wait for all
+  TNC_WAIT_VMCNT0();
+  for (;;) {
+    process(tile, ping, pong);
+    tile += gridDim.x;
+    if (tile >= a.n_tiles) break;
+    process(tile, pong, ping);
+    tile += gridDim.x;
+    if (tile >= a.n_tiles) break;
+  }
+}
+
+static int pipe_blocks_per_cu(const void* fn, size_t lds) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kBlock, lds) != hipSuccess || blocks < 1) blocks = 1;
+  return blocks;
+}
+
+static int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+template <int R, int NT>
+static hipError_t launch_pass_dma(const PassArgs& a, hipStream_t s) {
+  static int bpc = 0;
+  if (bpc == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, reinterpret_cast<const void*>(&k_pass_dma<R, NT>), NT, 0) !=
+            hipSuccess ||
+        bpc < 1)
+      bpc = 1;
+  }
+  const long long grid = std::min<long long>(a.n_tiles, (long long)bpc * device_cus());
+  hipLaunchKernelGGL((k_pass_dma<R, NT>), dim3((unsigned)grid), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
 template <int R>
 static hipError_t launch_pass_r(const PassArgs& a, hipStream_t s) {
   const int TB = a.T - R;
+  const bool dma_ok = a.pipeline && !a.mfma;
+  if constexpr (R >= 4) {
+    if (dma_ok && TB == 8) return launch_pass_dma<R, 256>(a, s);
+  }
+  if constexpr (R == 4) {
+    if (dma_ok && TB == 9) return launch_pass_dma<R, 512>(a, s);
+  }
   if (TB < 0 || TB > 8) return hipErrorInvalidValue;
   const bool multi = TB < 8;
   const int tiles_per_block = multi ? (kBlock >> TB) : 1;
   const long long blocks = ((long long)a.n_tiles + tiles_per_block - 1) / tiles_per_block;
   const size_t lds = (size_t)kBlock * (1 << R) * sizeof(float2);
+  // matrix-core updates need the four lanes of an MFMA block in one tile
+  const bool mf = a.mfma && TB >= 2 && a.mrows != nullptr;
+  if (!multi && a.pipeline && mf) {
+    const void* fn = mf ? reinterpret_cast<const void*>(&k_pass_pipe<R, true>)
+                        : reinterpret_cast<const void*>(&k_pass_pipe<R, false>);
+    static int per_cu[2][8] = {{0}};
+    int& bpc = per_cu[mf ? 1 : 0][R];
+    if (bpc == 0) bpc = pipe_blocks_per_cu(fn, lds);
+    const long long resident = (long long)bpc * device_cus();
+    const long long grid = std::min<long long>(a.n_tiles, resident);
+    if (mf) hipLaunchKernelGGL((k_pass_pipe<R, true>), dim3((unsigned)grid), dim3(kBlock), lds, s, a);
+    else hipLaunchKernelGGL((k_pass_pipe<R, false>), dim3((unsigned)grid), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+  }
   if (multi) {
-    hipLaunchKernelGGL((k_pass<R, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    if (mf) hipLaunchKernelGGL((k_pass<R, true, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    else hipLaunchKernelGGL((k_pass<R, true, false>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
   } else {
-    hipLaunchKernelGGL((k_pass<R, false>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    if (mf) hipLaunchKernelGGL((k_pass<R, false, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    else hipLaunchKernelGGL((k_pass<R, false, false>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
   }
   return hipGetLastError();
 }
@@ -200,13 +405,11 @@ static void emulate_pass_r(const PassArgs& a) {
   const int tbits = a.h - T;
   std::vector<float2> lds((size_t)1 << T);
   char* region = reinterpret_cast<char*>(lds.data());
-  std::vector<float2> regs((size_t)tpt * E);
   const uint32_t tmask = (1u << T) - 1u;
   for (long long tile = 0; tile < a.n_tiles; ++tile) {
     const long long batch = tile >> tbits;
     const unsigned long long blk = (unsigned long long)tile & ((1ull << tbits) - 1ull);
     float2* Bt = a.B + (batch << a.h) + block_offset(blk, a.lo_bits, a.win_lo, a.win_len);
-    const uint8_t* xb = a.bits + batch * a.n;
     for (int tt = 0; tt < tpt; ++tt)
       for (int it = 0; it < E / 2; ++it) {
         const uint32_t i = (uint32_t)(it * tpt + tt) * 2u;
@@ -215,34 +418,18 @@ static void emulate_pass_r(const PassArgs& a) {
         dst[0] = src[0];
         dst[1] = src[1];
       }
+    PhaseCtx<R, false> ctx;
+    ctx.ops = (const TNC_TBL DevOp*)a.ops;
+    ctx.mats = (const TNC_TBL float*)a.mats;
+    ctx.mrows = a.mrows;
+    ctx.bits = a.bits;
+    ctx.xpos = (size_t)batch * a.n;
+    ctx.tb = 0;
+    ctx.lane = 0;
+    ctx.uniform = false;
     for (int p = 0; p < a.n_phases; ++p) {
-      const DevPhase P = a.phases[p];
-      uint32_t rm[R];
-      uint32_t rmask = 0;
-      for (int b = 0; b < R; ++b) {
-        rm[b] = 1u << P.reg[b];
-        rmask |= rm[b];
-      }
-      for (int tt = 0; tt < tpt; ++tt) {
-        Regs<R> v;
-        const uint32_t tb = pdep32((uint32_t)tt, tmask & ~rmask);
-        const uint32_t vbase = swz(tb) << 3;
-        for (int i = 0; i < E; ++i) {
-          uint32_t r = 0;
-          for (int b = 0; b < R; ++b)
-            if (i & (1 << b)) r |= rm[b];
-          const float2 t = *reinterpret_cast<const float2*>(region + (vbase ^ (swz(r) << 3)));
-          v.x[i] = t.x;
-          v.y[i] = t.y;
-        }
-        run_phase_ops<R>(v, P, a.ops, a.mats, xb, tb);
-        for (int i = 0; i < E; ++i) {
-          uint32_t r = 0;
-          for (int b = 0; b < R; ++b)
-            if (i & (1 << b)) r |= rm[b];
-          *reinterpret_cast<float2*>(region + (vbase ^ (swz(r) << 3))) = make_float2(v.x[i], v.y[i]);
-        }
-      }
+      const DevPhase P = ((const TNC_TBL DevPhase*)a.phases)[p];
+      for (int tt = 0; tt < tpt; ++tt) phase_dispatch<R, false>(region, P, ctx, (uint32_t)tt, tmask);
     }
     for (int tt = 0; tt < tpt; ++tt)
       for (int it = 0; it < E / 2; ++it) {

@@ -45,6 +45,16 @@ TNC_HD inline uint32_t pdep32(uint32_t x, uint32_t mask) {
   return r;
 }
 
+// The pass tables (phases, ops, matrices) are read through the constant
+// address space on the device: wave-uniform reads become scalar loads, which
+// are counted apart from vector memory, so reading them never waits for
+// vector loads in flight (such as the prefetch of the next tile).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define TNC_TBL __attribute__((address_space(4)))
+#else
+#define TNC_TBL
+#endif
+
 // Register-resident complex64 entries of a thread: separate real and
 // imaginary float arrays (keeps every element promotable to a VGPR).
 template <int R>
@@ -54,7 +64,8 @@ struct Regs {
 };
 
 // (b0, b1) <- K (b0, b1) with K = [k0 k1; k2 k3] given as 8 floats (re, im).
-TNC_HD inline void cmat2(const float* __restrict__ k, float& x0, float& y0, float& x1, float& y1) {
+template <class P>
+TNC_HD inline void cmat2(P k, float& x0, float& y0, float& x1, float& y1) {
   const float ox0 = k[0] * x0 - k[1] * y0 + k[2] * x1 - k[3] * y1;
   const float oy0 = k[0] * y0 + k[1] * x0 + k[2] * y1 + k[3] * x1;
   const float ox1 = k[4] * x0 - k[5] * y0 + k[6] * x1 - k[7] * y1;
@@ -69,7 +80,7 @@ TNC_HD inline void cmat2(const float* __restrict__ k, float& x0, float& y0, floa
 // a dispatch then merge values, never element addresses, so every element
 // stays in a VGPR.
 template <int R, int A, int C>
-TNC_HD inline Regs<R> op_reg(Regs<R> v, const float* __restrict__ m) {
+TNC_HD inline Regs<R> op_reg(Regs<R> v, const TNC_TBL float* __restrict__ m) {
 #pragma unroll
   for (int i = 0; i < (1 << R); ++i) {
     if (i & (1 << A)) continue;
@@ -79,8 +90,8 @@ TNC_HD inline Regs<R> op_reg(Regs<R> v, const float* __restrict__ m) {
   return v;
 }
 
-template <int R, int A>
-TNC_HD inline Regs<R> op_sel(Regs<R> v, const float* __restrict__ k) {
+template <int R, int A, class P>
+TNC_HD inline Regs<R> op_sel(Regs<R> v, P k) {
 #pragma unroll
   for (int i = 0; i < (1 << R); ++i) {
     if (i & (1 << A)) continue;
@@ -101,52 +112,185 @@ TNC_HD inline Regs<R> op_dup(Regs<R> v) {
   return v;
 }
 
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef float tnc_floatx4 __attribute__((ext_vector_type(4)));
+
+// Matrix-core form of op_reg: v_mfma_f32_4x4x1_16b_f32 computes, for each
+// block of 4 lanes, D[i][j] += A[i] * B[j] with A from lane 4b+i and B from
+// lane 4b+j.  With A = row (lane % 4) of the real 4x4 M and B = one real
+// component of the lane's own pair, four accumulating steps leave M x in the
+// lane's four accumulators: every lane transforms its own pair, no padding.
+// All four lanes of a block must use the same M (same tile, same control).
 template <int R, int A, int C>
-struct RegDispatch {
-  static TNC_HD inline Regs<R> run(const Regs<R>& v, int a, int c, const float* __restrict__ m) {
-    if (a == A && c == C) {
-      if constexpr (A != C) return op_reg<R, A, C>(v, m);
-      return v;
-    }
-    if constexpr (C + 1 < R) {
-      return RegDispatch<R, A, C + 1>::run(v, a, c, m);
-    } else if constexpr (A + 1 < R) {
-      return RegDispatch<R, A + 1, 0>::run(v, a, c, m);
-    }
-    return v;
+__device__ __attribute__((always_inline)) inline Regs<R> op_reg_mfma(Regs<R> v, const float4 r0, const float4 r1) {
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    if (i & (1 << A)) continue;
+    const int j = i | (1 << A);
+    const float4 r = ((i >> C) & 1) ? r1 : r0;
+    tnc_floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(r.x, v.x[i], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(r.y, v.y[i], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(r.z, v.x[j], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(r.w, v.y[j], acc, 0, 0, 0);
+    v.x[i] = acc[0];
+    v.y[i] = acc[1];
+    v.x[j] = acc[2];
+    v.y[j] = acc[3];
   }
+  return v;
+}
+
+#endif
+
+template <int R, bool MF>
+struct PhaseCtx {
+  const TNC_TBL DevOp* __restrict__ ops;
+  const TNC_TBL float* __restrict__ mats;
+  const float4* __restrict__ mrows;
+  const uint8_t* bits;  // output bits, one byte per qubit per batch
+  size_t xpos;          // byte offset of this tile's batch in `bits`
+  uint32_t tb;
+  int lane;
+  bool uniform;
 };
 
-template <int R, int A>
-struct SelDispatch {
-  static TNC_HD inline Regs<R> run(const Regs<R>& v, int a, const float* __restrict__ k, bool dup) {
-    if (a == A) return dup ? op_dup<R, A>(v) : op_sel<R, A>(v, k);
-    if constexpr (A + 1 < R) return SelDispatch<R, A + 1>::run(v, a, k, dup);
-    return v;
-  }
-};
+// Output bit at byte `pos` of the bit array.  On the device the byte is cut
+// from the aligned 32-bit word that holds it, read through the constant
+// address space: one scalar load when `pos` is wave-uniform.  The word never
+// crosses a 4-byte boundary, so it stays inside the page of the byte.
+TNC_HD inline int out_bit(const uint8_t* bits, size_t pos) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const uintptr_t addr = reinterpret_cast<uintptr_t>(bits) + pos;
+  const uint32_t w = *(const TNC_TBL uint32_t*)(addr & ~(uintptr_t)3);
+  return int((w >> (8 * (addr & 3))) & 1u);
+#else
+  return bits[pos] & 1;
+#endif
+}
 
-// Apply the ops of one phase to a thread's registers.
-//   tb: the thread part of the local tile index in this phase.
-//   xb: the output bits of this tile's batch.
-template <int R>
-TNC_HD inline void run_phase_ops(Regs<R>& v, const DevPhase& P, const DevOp* __restrict__ ops,
-                                 const float* __restrict__ mats, const uint8_t* __restrict__ xb,
-                                 uint32_t tb) {
-  for (int o = P.op_begin; o < P.op_end; ++o) {
-    const DevOp op = ops[o];
-    int var = 0;
-    if (op.xrow0 >= 0) var += 2 * xb[op.xrow0];
-    if (op.xrow1 >= 0) var += xb[op.xrow1];
-    const float* m = mats + ((size_t)op.mat * 4 + var) * 16;
-    if (op.kind == 1) {
-      v = SelDispatch<R, 0>::run(v, op.treg, m, true);
-    } else if (op.creg >= R) {
-      const int ctl = op.cloc >= 0 ? int((tb >> op.cloc) & 1u) : 0;
-      v = SelDispatch<R, 0>::run(v, op.treg, m + 8 * ctl, false);
+// Variant index of an op from its batch's output bits.  With one tile per
+// block the index is wave-uniform, so the bit reads and the matrix loads
+// that follow are scalar.
+template <int R, bool MF>
+TNC_HD inline int op_variant(const DevOp& op, const PhaseCtx<R, MF>& c) {
+  int var = 0;
+  if (op.xrow0 >= 0) var += 2 * out_bit(c.bits, c.xpos + op.xrow0);
+  if (op.xrow1 >= 0) var += out_bit(c.bits, c.xpos + op.xrow1);
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (c.uniform) var = __builtin_amdgcn_readfirstlane(var);
+#endif
+  return var;
+}
+
+// A value read at a wave-uniform address (valid only where the address is
+// the same for every lane of the wave).  Selecting between two such values
+// per lane must not be turned into a load from a per-lane address (a vector
+// load); pinning each value to the wave keeps both loads scalar.
+TNC_HD inline float uniform_value(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+#else
+  return x;
+#endif
+}
+
+// Ops 1..N-1 of a canonical phase: op b on register bit b controlled by b-1.
+template <int R, int B, int N, bool MF>
+TNC_HD inline Regs<R> stair_rest(Regs<R> v, const PhaseCtx<R, MF>& c, int op_begin) {
+  if constexpr (B < N) {
+    const DevOp op = c.ops[op_begin + B];
+    const int var = op_variant(op, c);
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (MF) {
+      const float4* rows = c.mrows + ((size_t)op.mat * 4 + var) * 8;
+      v = op_reg_mfma<R, B, B - 1>(v, rows[c.lane & 3], rows[4 + (c.lane & 3)]);
+      return stair_rest<R, B + 1, N, MF>(v, c, op_begin);
+    }
+#endif
+    v = op_reg<R, B, B - 1>(v, c.mats + ((size_t)op.mat * 4 + var) * 16);
+    return stair_rest<R, B + 1, N, MF>(v, c, op_begin);
+  }
+  return v;
+}
+
+// A whole canonical phase of N ops on a thread's registers.
+template <int R, int N, bool MF>
+TNC_HD inline Regs<R> stair(Regs<R> v, const DevPhase& P, const PhaseCtx<R, MF>& c) {
+  if (P.first_dup) {
+    v = op_dup<R, 0>(v);
+  } else {
+    const DevOp op = c.ops[P.op_begin];
+    const int var = op_variant(op, c);
+    const TNC_TBL float* m = c.mats + ((size_t)op.mat * 4 + var) * 16;
+    if (op.cloc < 0) {
+      v = op_sel<R, 0>(v, m);
     } else {
-      v = RegDispatch<R, 0, 0>::run(v, op.treg, op.creg, m);
+      const bool hi = (c.tb >> op.cloc) & 1u;
+      if (c.uniform) {
+        // thread-controlled: pick the values per thread from the
+        // wave-uniform pair of matrices (a per-thread address would need
+        // vector loads)
+        float k[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) k[e] = hi ? uniform_value(m[8 + e]) : uniform_value(m[e]);
+        v = op_sel<R, 0>(v, static_cast<const float*>(k));
+      } else {
+        v = op_sel<R, 0>(v, m + 8 * int(hi));
+      }
     }
+  }
+  return stair_rest<R, 1, N, MF>(v, c, P.op_begin);
+}
+
+// One register phase: LDS -> registers (phase layout), the phase's ops,
+// registers -> LDS.  Each thread writes back exactly the entries it read.
+template <int R, int N, bool MF>
+TNC_HD inline void phase_exec(char* region, const DevPhase& P, const PhaseCtx<R, MF>& c0, uint32_t tt,
+                              uint32_t tmask) {
+  constexpr int E = 1 << R;
+  uint32_t rm[R];
+  uint32_t rmask = 0;
+#pragma unroll
+  for (int b = 0; b < R; ++b) {
+    rm[b] = 1u << P.reg[b];
+    rmask |= rm[b];
+  }
+  PhaseCtx<R, MF> c = c0;
+  c.tb = pdep32(tt, tmask & ~rmask);
+  const uint32_t vbase = swz(c.tb) << 3;
+  Regs<R> v;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < R; ++b)
+      if (i & (1 << b)) r |= rm[b];
+    const float2 t = *reinterpret_cast<const float2*>(region + (vbase ^ (swz(r) << 3)));
+    v.x[i] = t.x;
+    v.y[i] = t.y;
+  }
+  v = stair<R, N, MF>(v, P, c);
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < R; ++b)
+      if (i & (1 << b)) r |= rm[b];
+    *reinterpret_cast<float2*>(region + (vbase ^ (swz(r) << 3))) = make_float2(v.x[i], v.y[i]);
+  }
+}
+
+template <int R, bool MF>
+TNC_HD inline void phase_dispatch(char* region, const DevPhase& P, const PhaseCtx<R, MF>& c, uint32_t tt,
+                                  uint32_t tmask) {
+  switch (P.n_ops) {
+    case 1: phase_exec<R, 1, MF>(region, P, c, tt, tmask); break;
+    case 2: if constexpr (R >= 2) phase_exec<R, 2, MF>(region, P, c, tt, tmask); break;
+    case 3: if constexpr (R >= 3) phase_exec<R, 3, MF>(region, P, c, tt, tmask); break;
+    case 4: if constexpr (R >= 4) phase_exec<R, 4, MF>(region, P, c, tt, tmask); break;
+    case 5: if constexpr (R >= 5) phase_exec<R, 5, MF>(region, P, c, tt, tmask); break;
+    default: break;
   }
 }
 

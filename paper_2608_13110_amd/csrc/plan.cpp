@@ -560,39 +560,42 @@ bool op_fits(const SweepOp& op, const Window& w) {
   return true;
 }
 
+// Register phases in canonical staircase form: op b of a phase targets
+// register bit b and, for b >= 1, is controlled by register bit b-1; op 0 is
+// either a DUP or an update whose control is not a register bit (or absent).
+// Every row of the sweep is such a staircase; turns start a new phase.
 void plan_phases(Pass& ps, const std::vector<SweepOp>& ops, int R) {
   const int T = ps.w.tile_bits();
-  const int Reff = std::min(R, T);
+  const int Reff = pass_reg_bits(R, T);
   int i = ps.op_begin;
   while (i < ps.op_end) {
     Phase ph;
     ph.op_begin = i;
-    std::vector<int> tg;  // local target bits, in first-use order
-    int j = i;
-    for (; j < ps.op_end; ++j) {
-      int t = ps.w.local(ops[j].target);
-      bool have = std::find(tg.begin(), tg.end(), t) != tg.end();
-      if (!have && int(tg.size()) == Reff) break;
-      if (!have) tg.push_back(t);
+    std::vector<int> regs = {ps.w.local(ops[i].target)};
+    const int ctl0 = ops[i].kind == OP_CU && ops[i].control >= 0 ? ps.w.local(ops[i].control) : -1;
+    int j = i + 1;
+    for (; j < ps.op_end && int(regs.size()) < Reff; ++j) {
+      const SweepOp& op = ops[j];
+      const int t = ps.w.local(op.target);
+      if (op.kind != OP_CU || op.control < 0) break;
+      if (ps.w.local(op.control) != regs.back()) break;
+      if (std::find(regs.begin(), regs.end(), t) != regs.end() || t == ctl0) break;
+      regs.push_back(t);
     }
     ph.op_end = j;
-    // pad: controls of the phase's ops first, then nearest unused bits
-    std::vector<int> regs = tg;
-    for (int q = ph.op_begin; q < ph.op_end && int(regs.size()) < Reff; ++q) {
-      if (ops[q].control < 0) continue;
-      int c = ps.w.local(ops[q].control);
-      if (std::find(regs.begin(), regs.end(), c) == regs.end()) regs.push_back(c);
-    }
+    // pad with bits next to the targets, never op 0's control
+    auto usable = [&](int c) {
+      return c >= 0 && c < T && c != ctl0 && std::find(regs.begin(), regs.end(), c) == regs.end();
+    };
     for (int dist = 1; int(regs.size()) < Reff && dist <= T; ++dist)
       for (int base : std::vector<int>(regs)) {
         for (int c : {base + dist, base - dist}) {
           if (int(regs.size()) >= Reff) break;
-          if (c < 0 || c >= T) continue;
-          if (std::find(regs.begin(), regs.end(), c) == regs.end()) regs.push_back(c);
+          if (usable(c)) regs.push_back(c);
         }
       }
     for (int c = 0; int(regs.size()) < Reff && c < T; ++c)
-      if (std::find(regs.begin(), regs.end(), c) == regs.end()) regs.push_back(c);
+      if (usable(c)) regs.push_back(c);
     for (int q = 0; q < kMaxReg; ++q) ph.reg[q] = q < int(regs.size()) ? regs[q] : -1;
     ps.phases.push_back(ph);
     i = j;

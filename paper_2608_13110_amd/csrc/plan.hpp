@@ -97,6 +97,10 @@ struct Window {
 
 constexpr int kMaxReg = 8;
 
+// Register bits of a pass with 2^T-entry tiles: at most R, and at least one
+// bit left for the thread part so that op 0's control is never a register.
+inline int pass_reg_bits(int R, int T) { return T <= 1 ? 1 : (R < T - 1 ? R : T - 1); }
+
 struct Phase {
   int op_begin = 0, op_end = 0;
   int reg[kMaxReg] = {0};  // local tile bits held in registers, in register-bit order
@@ -112,6 +116,8 @@ struct Options {
   int max_tile_bits = 13;   // tile of one pass: 2^max_tile_bits entries
   int reg_bits = 5;         // entries per thread = 2^reg_bits
   int low_bits = 4;         // contiguous low slots kept in every non-bottom tile
+  int math = 0;             // 0: vector ALU updates; 1: register-controlled updates on the matrix cores
+  int pipeline = 0;         // 1: persistent, prefetching pass blocks where a block holds one tile
 };
 
 // Everything that depends on k (the number of open output legs).

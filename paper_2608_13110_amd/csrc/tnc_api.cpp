@@ -38,6 +38,7 @@ uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 // Host copies of a schedule's device tables.
 struct PassHost {
   int phase_off = 0, n_phases = 0;
+  int op_begin = 0, op_end = 0;
   Window w;
   int R = 5;
 };
@@ -45,6 +46,7 @@ struct PassHost {
 struct HostTables {
   std::vector<DevOp> ops;
   std::vector<float> mats;
+  std::vector<float4> mrows;
   std::vector<DevPhase> phases;
   std::vector<PassHost> passes;
   std::vector<double2> seg;
@@ -58,68 +60,77 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
   const size_t nops = s.ops.size();
   t->ops.resize(nops);
   t->mats.assign(nops * 4 * 16, 0.f);
+  t->mrows.assign(nops * 4 * 8, make_float4(0.f, 0.f, 0.f, 0.f));
   for (size_t o = 0; o < nops; ++o) {
     const SweepOp& op = s.ops[o];
     for (int var = 0; var < 4; ++var)
-      for (int c = 0; c < 2; ++c)
+      for (int c = 0; c < 2; ++c) {
+        const M2& K = op.mat[var][c];
         for (int e = 0; e < 4; ++e) {
-          t->mats[(o * 4 + var) * 16 + c * 8 + 2 * e] = (float)op.mat[var][c].a[e].real();
-          t->mats[(o * 4 + var) * 16 + c * 8 + 2 * e + 1] = (float)op.mat[var][c].a[e].imag();
+          t->mats[(o * 4 + var) * 16 + c * 8 + 2 * e] = (float)K.a[e].real();
+          t->mats[(o * 4 + var) * 16 + c * 8 + 2 * e + 1] = (float)K.a[e].imag();
         }
+        // real form on (re b0, im b0, re b1, im b1): rows (re o0, im o0, re o1, im o1)
+        for (int r = 0; r < 2; ++r) {
+          const cd k0 = K(r, 0), k1 = K(r, 1);
+          t->mrows[((o * 4 + var) * 2 + c) * 4 + 2 * r] =
+              make_float4((float)k0.real(), (float)-k0.imag(), (float)k1.real(), (float)-k1.imag());
+          t->mrows[((o * 4 + var) * 2 + c) * 4 + 2 * r + 1] =
+              make_float4((float)k0.imag(), (float)k0.real(), (float)k1.imag(), (float)k1.real());
+        }
+      }
   }
   for (const Pass& ps : s.passes) {
     PassHost ph;
     ph.w = ps.w;
-    ph.R = std::min(s.reg_bits, ps.w.tile_bits());
+    ph.R = pass_reg_bits(s.reg_bits, ps.w.tile_bits());
     ph.phase_off = int(t->phases.size());
     ph.n_phases = int(ps.phases.size());
+    ph.op_begin = ps.op_begin;
+    ph.op_end = ps.op_end;
     const int R = ph.R;
-    if (ps.w.tile_bits() - R > 8) {
-      if (err) *err = "pass tile too large for the thread block";
-      return TNC_E_DOMAIN;
-    }
-    if (!(ps.w.lo_bits >= 1 || ps.w.win_lo == 0)) {
-      if (err) *err = "pass tile lacks slot 0";
+    auto fail_t = [&](const char* m) {
+      if (err) *err = m;
       return TNC_E_INVALID;
-    }
+    };
+    // 256 threads per tile (T - R = 8), or 512 with the prefetching kernel
+    if (ps.w.tile_bits() - R > (p.opt.pipeline && p.opt.math == 0 ? 9 : 8))
+      return fail_t("pass tile too large for the thread block");
+    if (!(ps.w.lo_bits >= 1 || ps.w.win_lo == 0)) return fail_t("pass tile lacks slot 0");
     for (const Phase& pp : ps.phases) {
+      const int nops = pp.op_end - pp.op_begin;
+      if (nops < 1 || nops > R) return fail_t("phase size out of range");
       DevPhase dp;
       std::memset(&dp, 0, sizeof(dp));
       dp.op_begin = pp.op_begin;
-      dp.op_end = pp.op_end;
-      for (int b = 0; b < 8; ++b) dp.reg[b] = (int8_t)(b < R ? pp.reg[b] : 0);
-      for (int b = 0; b < R; ++b)
+      dp.n_ops = (int8_t)nops;
+      dp.first_dup = s.ops[pp.op_begin].kind == OP_DUP ? 1 : 0;
+      for (int b = 0; b < R; ++b) {
+        if (pp.reg[b] < 0 || pp.reg[b] >= ps.w.tile_bits()) return fail_t("bad register map");
         for (int c = 0; c < b; ++c)
-          if (pp.reg[b] == pp.reg[c] || pp.reg[b] < 0) {
-            if (err) *err = "bad register map";
-            return TNC_E_INVALID;
-          }
+          if (pp.reg[b] == pp.reg[c]) return fail_t("bad register map");
+        dp.reg[b] = (int8_t)pp.reg[b];
+      }
       t->phases.push_back(dp);
-      for (int o = pp.op_begin; o < pp.op_end; ++o) {
+      for (int b = 0; b < nops; ++b) {
+        const int o = pp.op_begin + b;
         const SweepOp& op = s.ops[o];
+        if (!ps.w.contains(op.target) || ps.w.local(op.target) != pp.reg[b]) return fail_t("op target not canonical");
         DevOp d;
         std::memset(&d, 0, sizeof(d));
-        d.kind = (int8_t)op.kind;
-        const int lt = ps.w.local(op.target);
-        int treg = -1;
-        for (int b = 0; b < R; ++b)
-          if (pp.reg[b] == lt) treg = b;
-        if (treg < 0 || !ps.w.contains(op.target)) {
-          if (err) *err = "op target not in registers";
-          return TNC_E_INVALID;
-        }
-        d.treg = (int8_t)treg;
-        d.creg = (int8_t)R;
         d.cloc = -1;
-        if (op.control >= 0) {
-          if (!ps.w.contains(op.control)) {
-            if (err) *err = "op control outside the tile";
-            return TNC_E_INVALID;
+        if (b == 0) {
+          if (op.kind == OP_CU && op.control >= 0) {
+            if (!ps.w.contains(op.control)) return fail_t("op control outside the tile");
+            const int lc = ps.w.local(op.control);
+            for (int q = 0; q < R; ++q)
+              if (pp.reg[q] == lc) return fail_t("first op control held in registers");
+            d.cloc = (int8_t)lc;
           }
-          const int lc = ps.w.local(op.control);
-          for (int b = 0; b < R; ++b)
-            if (pp.reg[b] == lc) d.creg = (int8_t)b;
-          if (d.creg == R) d.cloc = (int8_t)lc;
+        } else {
+          if (op.kind != OP_CU || op.control < 0 || !ps.w.contains(op.control) ||
+              ps.w.local(op.control) != pp.reg[b - 1])
+            return fail_t("op control not canonical");
         }
         d.xrow0 = (int16_t)op.xrow[0];
         d.xrow1 = (int16_t)op.xrow[1];
@@ -164,6 +175,7 @@ struct DevSched {
   HostTables host;
   DevOp* d_ops = nullptr;
   float* d_mats = nullptr;
+  float4* d_mrows = nullptr;
   DevPhase* d_phases = nullptr;
   double2* d_seg = nullptr;
   double2* d_J = nullptr;
@@ -172,7 +184,7 @@ struct DevSched {
     int prev = 0;
     if (device >= 0 && hipGetDevice(&prev) == hipSuccess) {
       (void)hipSetDevice(device);
-      void* ptrs[] = {d_ops, d_mats, d_phases, d_seg, d_J, d_prog};
+      void* ptrs[] = {d_ops, d_mats, d_mrows, d_phases, d_seg, d_J, d_prog};
       for (void* q : ptrs)
         if (q) (void)hipFree(q);
       (void)hipSetDevice(prev);
@@ -229,6 +241,7 @@ int get_dev_sched(Plan& p, int k, std::shared_ptr<DevSched>* out) {
   std::vector<double2> J;
   for (const cd& z : ds->host.late.first.J) J.push_back(make_double2(z.real(), z.imag()));
   if ((rc = upload(&ds->d_ops, ds->host.ops)) || (rc = upload(&ds->d_mats, ds->host.mats)) ||
+      (rc = upload(&ds->d_mrows, ds->host.mrows)) ||
       (rc = upload(&ds->d_phases, ds->host.phases)) || (rc = upload(&ds->d_seg, ds->host.seg)) ||
       (rc = upload(&ds->d_J, J)) || (rc = upload(&ds->d_prog, ds->host.prog)))
     return rc;
@@ -292,12 +305,17 @@ InitArgs init_args(const Plan& p, const HostTables& t, float2* B, const uint8_t*
 }
 
 PassArgs pass_args(const Plan& p, const PassHost& ph, const DevPhase* phases, const DevOp* ops, const float* mats,
-                   float2* B, const uint8_t* bits, int nb) {
+                   const float4* mrows, float2* B, const uint8_t* bits, int nb) {
   PassArgs a;
   std::memset(&a, 0, sizeof(a));
   a.phases = phases + ph.phase_off;
   a.ops = ops;
   a.mats = mats;
+  a.mrows = mrows;
+  a.mfma = p.opt.math == 1 ? 1 : 0;
+  a.pipeline = p.opt.pipeline;
+  a.op_begin = ph.op_begin;
+  a.n_ops = ph.op_end - ph.op_begin;
   a.B = B;
   a.bits = bits;
   a.n_phases = ph.n_phases;
@@ -377,7 +395,7 @@ int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k
     const double pass_bytes = 2.0 * 8.0 * (double)(1ull << p.h) * nb;
     for (const PassHost& ph : t.passes) {
       e = timed(1, pass_bytes, stream, [&] {
-        return launch_pass(pass_args(p, ph, ds.d_phases, ds.d_ops, ds.d_mats, B, bits, nb), ph.R, stream);
+        return launch_pass(pass_args(p, ph, ds.d_phases, ds.d_ops, ds.d_mats, ds.d_mrows, B, bits, nb), ph.R, stream);
       });
       if (e != hipSuccess) return hip_err(e, "pass launch");
     }
@@ -427,7 +445,8 @@ int emulate(Plan& p, int k, int nb, const uint8_t* bits, cd* out) {
       B[b * dim + i] = make_float2((float)v.real(), (float)v.imag());
     }
   for (const PassHost& ph : t.passes)
-    emulate_pass_host(pass_args(p, ph, t.phases.data(), t.ops.data(), t.mats.data(), B.data(), bits, nb), ph.R);
+    emulate_pass_host(pass_args(p, ph, t.phases.data(), t.ops.data(), t.mats.data(), t.mrows.data(), B.data(), bits, nb),
+                      ph.R);
   // late (FP64), same tables
   const LateFirst& F = t.late.first;
   const int sb = t.late.s;
@@ -525,9 +544,12 @@ int tnc_plan(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, c
     if (opt->max_tile_bits) o.max_tile_bits = opt->max_tile_bits;
     if (opt->reg_bits) o.reg_bits = opt->reg_bits;
     if (opt->low_bits) o.low_bits = opt->low_bits;
+    o.math = opt->math;
+    o.pipeline = opt->pipeline;
   }
   if (o.max_tile_bits < 6 || o.max_tile_bits > 13 || o.reg_bits < 1 || o.reg_bits > 5 || o.low_bits < 1 ||
-      o.low_bits > o.max_tile_bits - 2 || o.max_tile_bits - o.reg_bits > 8)
+      o.low_bits > o.max_tile_bits - 2 || o.math < 0 || o.math > 1 || o.pipeline < 0 || o.pipeline > 1 ||
+      o.max_tile_bits - o.reg_bits > (o.pipeline && o.math == 0 ? 9 : 8))
     return set_err(TNC_E_INVALID, "tile options out of range");
   if (n < 2 || d < 2 || (int64_t)n * (d + 1) > (1 << 24)) return set_err(TNC_E_DOMAIN, "need n >= 2, d >= 2");
   std::vector<cd> one((size_t)(d + 1) * n * 4);

@@ -79,6 +79,12 @@ SMALL = [
     (13, 25, 0, 0.0, 8, 3, dict(max_tile_bits=6, low_bits=1, reg_bits=5)),
     (16, 30, 1, 0.0, 4, 8, None),
     (14, 29, 0, 0.3, 2, 6, None),
+    (16, 30, 1, 0.3, 4, 8, dict(math=1)),
+    (12, 24, 0, 0.3, 6, 4, dict(max_tile_bits=8, low_bits=4, reg_bits=4, math=1)),
+    # persistent prefetching pass blocks: 256 threads x 32, 512 x 16, 256 x 16
+    (16, 30, 1, 0.3, 4, 8, dict(pipeline=1)),
+    (16, 30, 0, 0.3, 3, 8, dict(pipeline=1, reg_bits=4)),
+    (16, 31, 1, 0.3, 2, 8, dict(pipeline=1, reg_bits=4, max_tile_bits=12)),
 ]
 
 
@@ -92,13 +98,16 @@ def test_small_circuits(n, d, fp, dense, k, nb, opts):
     assert_close(got, ref, n)
 
 
-def test_medium_config_restriction():
-    # medium workload (d = 40, w = 20), restricted to 24 qubits, 64 batches, k = 6
+@pytest.mark.parametrize("opts", [None, dict(pipeline=1), dict(pipeline=1, reg_bits=4)])
+def test_medium_config_restriction(opts):
+    # medium workload (d = 40, w = 20), restricted to 24 qubits, 64 batches,
+    # k = 6: 8192 tiles per pass, so persistent blocks loop over many tiles
+    # and cross batch boundaries
     from paper_2608_13110_amd import Plan
     c = W.restrict(W.config_circuit(1), 24)
     bits = W.config_bitstrings(1)[:, :24]
     ref = oracle.amplitudes(c, bits, 6)
-    got = gpu_amps(Plan.from_circuit(c), bits, 6)
+    got = gpu_amps(Plan.from_circuit(c, opts), bits, 6)
     assert_close(got, ref, c.n)
 
 
