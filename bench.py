@@ -122,6 +122,144 @@ def run_workload(name, steps, warmup, torch, W, Plan, profile_begin, profile_end
     )
 
 
+def storage_modes(torch, W, Plan, profile_begin, profile_end, batches=16):
+    """The precision workload's batches with complex64 storage and with the
+    FP16 / BF16 block-scaled storage modes: throughput, pass bandwidth
+    (algorithmic bytes of each mode) and p99 per batch, and each 16-bit
+    mode's amplitude error against the complex64 result."""
+    import numpy as np
+    spec = WORKLOADS["precision"]
+    k = spec["k"]
+    circ = W.config_circuit(spec["cid"])
+    bits = torch.from_numpy(W.config_bitstrings(spec["cid"])[:batches]).cuda()
+    plan = Plan.from_circuit(circ)
+    plan.prepare(k)
+    stream = torch.cuda.current_stream()
+    res, ref = {}, None
+    for name, storage in (("c64", 0), ("f16_blockscale", 1), ("bf16_blockscale", 2)):
+        ws = torch.empty(plan.workspace_bytes(k, 1, storage), dtype=torch.uint8, device="cuda")
+        out = torch.empty((batches, 1 << k), dtype=torch.complex128, device="cuda")
+        plan.amplitudes(bits[:1], k, out=out[:1], workspace=ws, stream=stream, storage=storage)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(batches)]
+        profile_begin()
+        t0 = time.time()
+        for i in range(batches):
+            evs[i][0].record(stream)
+            plan.amplitudes(bits[i:i + 1], k, out=out[i:i + 1], workspace=ws, stream=stream, storage=storage)
+            evs[i][1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.time() - t0
+        prof = profile_end()
+        lat = [a.elapsed_time(b) for a, b in evs]
+        z = out.cpu().numpy()
+        r = {"amplitudes_per_s": round(batches * (1 << k) / wall, 3),
+             "latency_ms_p50": round(pct(lat, 50), 3), "latency_ms_p99": round(pct(lat, 99), 3),
+             "pass_gbs": round(prof["pass_bytes"] / (prof["pass_ms"] / 1e3) / 1e9, 1),
+             "bytes_per_entry": 8 if storage == 0 else 4}
+        if ref is None:
+            ref = z
+        else:
+            floor = 2.0 ** (-circ.n / 2)
+            r["max_rel_err_vs_c64"] = float(np.max(np.abs(z - ref) / np.maximum(np.abs(ref), floor)))
+            r["l2_rel_err_vs_c64"] = float(np.linalg.norm(z - ref) / np.linalg.norm(ref))
+        res[name] = r
+        del ws
+        torch.cuda.empty_cache()
+    res["workload"] = WORKLOADS["precision"]["desc"].replace("1 batch/step", f"{batches} batches")
+    return res
+
+
+TUNE_CANDIDATES = [dict(), dict(max_tile_bits=12), dict(max_tile_bits=12, reg_bits=4), dict(max_tile_bits=11, reg_bits=4)]
+
+
+def serving_bench(torch, W, count=512, load=0.8):
+    """The serving stream: Poisson arrivals of mixed-shape requests.
+
+    Autotunes the tile options per width, measures sequential plain launches
+    (one request at a time on one stream, no graphs: the capacity C), then
+    replays the same stream with arrival rate load x C into the server.
+    Planning is warmed up for both (plans cached); latency is submit -> done.
+    The sequential latency under the same arrivals is FIFO queueing over the
+    measured per-request service times.
+    """
+    import threading
+    import numpy as np
+    from paper_2608_13110_amd import Plan, Server, autotune
+    reqs = W.serving_requests(count=count, seed=1)
+    widths = sorted({(r["circuit"].d + 1) // 2 for r in reqs})
+    tuning = {}
+    for h in widths:
+        best, times = autotune(40, 2 * h, 4, TUNE_CANDIDATES, reps=2)
+        tuning[h] = TUNE_CANDIDATES[best]
+    # sequential plain launches with the same tuned plans
+    plans = [Plan.from_circuit(r["circuit"], tuning[(r["circuit"].d + 1) // 2]) for r in reqs]
+    for p_, r in zip(plans, reqs):
+        p_.prepare(r["k"])
+    stream = torch.cuda.current_stream()
+    service = []
+    for p_, r in zip(plans, reqs):
+        t0 = time.perf_counter()
+        bits = torch.from_numpy(np.ascontiguousarray(r["bits"], dtype=np.uint8)).cuda()
+        out = p_.amplitudes(bits, r["k"], stream=stream)
+        z = out.cpu()
+        service.append(time.perf_counter() - t0)
+    seq_total = sum(service)
+    amps = sum(1 << r["k"] for r in reqs)
+    capacity = count / seq_total
+    rate = load * capacity
+    gaps = np.array([r["arrival"] for r in reqs])
+    arrivals = gaps / gaps[-1] * (count / rate)
+    done, seq_lat = 0.0, []
+    for a, sv in zip(arrivals, service):
+        done = max(done, a) + sv
+        seq_lat.append(1e3 * (done - a))
+    del plans
+    torch.cuda.empty_cache()
+    with Server(arena_bytes=16 << 30, n_streams=8, n_planners=8, small_bits=20) as srv:
+        for h, o in tuning.items():
+            srv.set_tuning(h, o)
+        ids = [srv.submit(r["circuit"], r["bits"], r["k"]) for r in reqs]  # warm-up: plans, graphs
+        for i in ids:
+            srv.wait(i)
+        warm = srv.summary()
+        res = [None] * count
+
+        def producer():
+            t0 = time.perf_counter()
+            for i, (r, a) in enumerate(zip(reqs, arrivals)):
+                dt = a - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                res[i] = srv.submit(r["circuit"], r["bits"], r["k"])
+
+        t0 = time.perf_counter()
+        th = threading.Thread(target=producer)
+        th.start()
+        lat = []
+        for i in range(count):
+            while res[i] is None:
+                time.sleep(1e-4)
+            _, st = srv.wait(res[i])
+            lat.append(st["total_ms"])
+        th.join()
+        served_s = time.perf_counter() - t0
+        summ = srv.summary()
+    return {
+        "workload": f"{count} Poisson requests, n in 24..56, even d in 20..48 (w 10..24), k in 0..8, "
+                    f"1 bitstring each; arrival rate {load} x sequential capacity",
+        "amplitudes": amps,
+        "sequential": {"amplitudes_per_s": round(amps / seq_total, 1), "requests_per_s": round(capacity, 1),
+                       "latency_ms_p50": round(pct(seq_lat, 50), 3), "latency_ms_p99": round(pct(seq_lat, 99), 3)},
+        "served": {"amplitudes_per_s": round(amps / served_s, 1), "requests_per_s": round(count / served_s, 1),
+                   "latency_ms_p50": round(pct(lat, 50), 3), "latency_ms_p99": round(pct(lat, 99), 3),
+                   "max_inflight": summ["max_inflight"],
+                   "graph_launches": summ["graph_launches"] - warm["graph_launches"],
+                   "plain_launches": summ["plain_launches"] - warm["plain_launches"]},
+        "tuning": {str(h): o for h, o in tuning.items()},
+    }
+
+
 def cpu_baseline(W):
     """The oracle on a bounded restriction of the full-width circuit."""
     import numpy as np
@@ -149,6 +287,8 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="full_width")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-storage", action="store_true", help="skip the 16-bit storage comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (reference "
                          "dispatches for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -181,6 +321,13 @@ def main():
         steps2 = 16 if other == "precision" else 2
         secondary = run_workload(other, steps2, 1, torch, W, Plan, profile_begin, profile_end)
         torch.cuda.empty_cache()
+    storage = None
+    if not args.no_storage:
+        storage = storage_modes(torch, W, Plan, profile_begin, profile_end)
+    serving = None
+    if not args.no_serving:
+        serving = serving_bench(torch, W)
+        torch.cuda.empty_cache()
     traffic = recorded_traffic(args.workload)
     roofline = {
         "bound": "hbm", "achieved": round(main_r["pass_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -210,6 +357,10 @@ def main():
                              if k2 in ("workload", "amplitudes_per_s", "pass_gbs", "latency_ms_p50",
                                        "latency_ms_p99", "ms_per_step", "steps", "pass_avg_ms")}
         line["secondary"]["hbm_frac"] = round(secondary["pass_gbs"] / HBM_PEAK_GBS, 4)
+    if storage is not None:
+        line["storage_modes"] = storage
+    if serving is not None:
+        line["serving"] = serving
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(line), flush=True)

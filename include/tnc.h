@@ -55,7 +55,18 @@ typedef struct {
 #define TNC_GATE_CZ 0     /* diag(1, 1, 1, -1); m ignored */
 #define TNC_GATE_DENSE4 1 /* m: 4x4 row-major [out][in], basis 2*x_q + x_{q+1} */
 
-#define TNC_STORE_C64 0   /* boundary tensor stored as complex64 */
+/* Storage of the boundary tensor in HBM.  The updates always compute in
+ * complex FP32; the 16-bit modes store each entry as two FP16 or BF16 halves
+ * (re, im) of the entry divided by its block's FP32 power-of-two scale, with
+ * one scale per block of 4096 entries written together by one tile (fewer in
+ * tiles below 2^12 entries); the scale puts the block's largest component
+ * in [2^14, 2^15).  This halves the bytes each pass moves, at a precision the
+ * format sets (about 2^-11 relative per store for FP16, 2^-8 for BF16, for
+ * entries near their block's maximum).  The join and the late phase read the
+ * decoded values in FP64 as in the complex64 mode. */
+#define TNC_STORE_C64 0             /* complex64 (8 bytes per entry) */
+#define TNC_STORE_F16_BLOCKSCALE 1  /* 2 x FP16 + FP32 scale per block (about 4 bytes per entry) */
+#define TNC_STORE_BF16_BLOCKSCALE 2 /* 2 x BF16 + FP32 scale per block */
 
 /* One two-qubit gate of entangling layer `layer` (1..d) on qubits (q, q+1). */
 typedef struct {
@@ -77,7 +88,10 @@ typedef struct {
                             (v_mfma_f32_4x4x1_16b_f32) where a block holds one tile */
   int32_t pipeline;      /* 0: one tile per block (default); 1: persistent blocks that prefetch
                             the next tile into LDS while updating the current one */
-  int32_t reserved[3];
+  int32_t late_fold;     /* k >= 1: late removals folded on the host into the join launch
+                            (0: automatic, 3 for boundary tensors of 2^26 entries or more,
+                            else none; -1: none; 1..3: that many) */
+  int32_t reserved[2];
 } tnc_options;
 
 typedef struct {
@@ -120,7 +134,9 @@ int tnc_plan_info(tnc_plan_t plan, int32_t k, tnc_info* info);
 int tnc_prepare(tnc_plan_t plan, int32_t k);
 
 /* Device workspace needed to run n_batches batches at once with storage mode
- * `storage` (TNC_STORE_C64). */
+ * `storage` (TNC_STORE_*): per batch the tensor (8 or 4 bytes per entry),
+ * for the 16-bit modes two arrays of block scales, and the late-phase
+ * buffers.  The 16-bit modes need low_bits >= 2 (TNC_E_INVALID otherwise). */
 int tnc_workspace_bytes(tnc_plan_t plan, int32_t k, int32_t n_batches, int32_t storage, uint64_t* bytes);
 
 /*
@@ -172,6 +188,92 @@ typedef struct {
 int tnc_profile_begin(void);
 int tnc_profile_end(tnc_profile* out);
 
+/*
+ * Tile autotuner.  Times each candidate tile option set on the current
+ * device for an n-qubit, d-layer brickwork CZ circuit with seeded random
+ * one-qubit unitaries (width and pass structure depend only on n, d and k,
+ * never on the gate values: Sec. 6, the invariance of width and cost) and
+ * reports the fastest.
+ *   candidates: n_candidates option sets (NULL entries not allowed);
+ *   reps:       timed batches per candidate (after one untimed warm-up);
+ *   times_ms:   n_candidates doubles, median time per batch of each
+ *               candidate (infinity for a candidate the library rejects);
+ *   best:       index of the fastest candidate.
+ * Allocates its own device memory (one batch of workspace); synchronous.
+ */
+int tnc_autotune(int32_t n, int32_t d, int32_t k, int32_t storage, const tnc_options* candidates,
+                 int32_t n_candidates, int32_t reps, int32_t* best, double* times_ms);
+
+/*
+ * Serving: a continuous-batching request loop on the current device
+ * (batches of one circuit share its plan: Sec. 5.3).  Requests of any shape
+ * are submitted at any time from any thread; planner threads build (or find
+ * in the plan cache, keyed by the circuit's contents) the plan and upload
+ * its tables; the dispatcher admits a prepared request as soon as one of
+ * n_streams HIP streams is free and the device arena has room for its
+ * footprint (workspace + bits + output), oldest first, letting younger
+ * requests that fit pass an older one that does not at most 16 times.
+ * Requests whose boundary tensor has <= small_bits bits run in a fixed
+ * per-stream region as HIP graphs captured on first use and replayed when
+ * the same (plan, k, batches, storage) returns on that stream.
+ * Results are bit-identical to tnc_amplitudes with the same plan options.
+ */
+typedef struct tnc_server_s* tnc_server_t;
+
+typedef struct {
+  uint64_t arena_bytes;  /* device memory reserved at creation for all requests (> 0) */
+  int32_t n_streams;     /* concurrent requests on the device (default 4, at most 16) */
+  int32_t n_planners;    /* planner threads (default 4, at most 16) */
+  int32_t small_bits;    /* graph-replayed requests: boundary bits <= small_bits (0: none, at most 24) */
+  int32_t max_graphs;    /* cached graph executables (default 256) */
+  int32_t reserved[4];
+} tnc_server_options;
+
+typedef struct {
+  double plan_ms;        /* submit -> plan ready (planning, table upload) */
+  double queue_ms;       /* submit -> admitted to a stream */
+  double run_ms;         /* admitted -> results copied back */
+  double total_ms;       /* submit -> done */
+  int32_t boundary_bits;
+  int32_t graph;         /* 1: ran as a captured graph */
+} tnc_request_stats;
+
+typedef struct {
+  int64_t completed;
+  int64_t graph_launches, graph_captures, plain_launches;
+  int64_t plan_cache_hits, plan_cache_misses;
+  int32_t max_inflight;  /* most requests seen running at once */
+  int32_t reserved;
+  double latency_ms_p50, latency_ms_p99, latency_ms_max;  /* submit -> done */
+  double elapsed_s;      /* first submit -> last completion */
+} tnc_server_stats;
+
+/* Create / destroy (destroy finishes every submitted request first). */
+int tnc_server_create(const tnc_server_options* opt, tnc_server_t* out);
+void tnc_server_destroy(tnc_server_t server);
+
+/* Tile options for plans whose width (boundary bits) is boundary_bits
+ * (unset widths use the defaults); applies to plans built afterwards. */
+int tnc_server_set_tuning(tnc_server_t server, int32_t boundary_bits, const tnc_options* opt);
+
+/*
+ * Submit one request (asynchronous).  The circuit arguments are as for
+ * tnc_plan, bits as for tnc_amplitudes_host (host, n_batches*n bytes); both
+ * are copied.  `out` (host, n_batches * 2^k amplitudes) is written when the
+ * request completes and must stay valid until tnc_server_wait returns.
+ * *id identifies the request for tnc_server_wait.
+ */
+int tnc_server_submit(tnc_server_t server, int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2,
+                      const tnc_gate2* gates, int32_t n_batches, const uint8_t* bits, int32_t k, int32_t storage,
+                      tnc_c128* out, uint64_t* id);
+
+/* Block until request `id` is done; returns its status and timings (stats
+ * may be NULL).  Each id can be waited for once. */
+int tnc_server_wait(tnc_server_t server, uint64_t id, tnc_request_stats* stats);
+
+/* Counters and latency quantiles over every completed request. */
+int tnc_server_summary(tnc_server_t server, tnc_server_stats* stats);
+
 /* Free a plan and its device tables.  NULL is ignored. */
 void tnc_release(tnc_plan_t plan);
 
@@ -182,10 +284,12 @@ const char* tnc_last_error(void);
  * Planner self-checks, host only, FP64 (tests; the device path never calls
  * them).  execute_host runs the plan's own update tables on the host;
  * emulate_device runs the device tables through a host emulation of the
- * pass kernel's thread / LDS mapping.  Width <= 24.
+ * pass kernel's thread / LDS mapping, with the given storage mode.
+ * Width <= 24.
  */
 int tnc_debug_execute_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, tnc_c128* out);
-int tnc_debug_emulate_device(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, tnc_c128* out);
+int tnc_debug_emulate_device(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, int32_t storage,
+                             tnc_c128* out);
 
 #ifdef __cplusplus
 }

@@ -30,11 +30,15 @@ TNC_E_DEVICE = -5
 GATE_CZ = 0
 GATE_DENSE4 = 1
 STORE_C64 = 0
+STORE_F16_BLOCKSCALE = 1
+STORE_BF16_BLOCKSCALE = 2
 
 EXPORTED = [
     "tnc_plan", "tnc_plan_info", "tnc_prepare", "tnc_workspace_bytes", "tnc_amplitudes",
     "tnc_amplitudes_host", "tnc_logxeb", "tnc_release", "tnc_strerror", "tnc_last_error",
     "tnc_debug_execute_host", "tnc_debug_emulate_device", "tnc_profile_begin", "tnc_profile_end",
+    "tnc_autotune", "tnc_server_create", "tnc_server_destroy", "tnc_server_set_tuning", "tnc_server_submit",
+    "tnc_server_wait", "tnc_server_summary",
 ]
 
 
@@ -56,7 +60,7 @@ class Gate2(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("max_tile_bits", ctypes.c_int32), ("reg_bits", ctypes.c_int32),
                 ("low_bits", ctypes.c_int32), ("math", ctypes.c_int32),
-                ("pipeline", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("pipeline", ctypes.c_int32), ("late_fold", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class Info(ctypes.Structure):
@@ -78,6 +82,31 @@ class Profile(ctypes.Structure):
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_uint64), ("n_streams", ctypes.c_int32), ("n_planners", ctypes.c_int32),
+                ("small_bits", ctypes.c_int32), ("max_graphs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class RequestStats(ctypes.Structure):
+    _fields_ = [("plan_ms", ctypes.c_double), ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double), ("boundary_bits", ctypes.c_int32), ("graph", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("graph_launches", ctypes.c_int64),
+                ("graph_captures", ctypes.c_int64), ("plain_launches", ctypes.c_int64),
+                ("plan_cache_hits", ctypes.c_int64), ("plan_cache_misses", ctypes.c_int64),
+                ("max_inflight", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("latency_ms_p50", ctypes.c_double), ("latency_ms_p99", ctypes.c_double),
+                ("latency_ms_max", ctypes.c_double), ("elapsed_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
 _lib = None
@@ -106,11 +135,19 @@ def lib() -> ctypes.CDLL:
     L.tnc_last_error.argtypes = []
     L.tnc_last_error.restype = ctypes.c_char_p
     L.tnc_debug_execute_host.argtypes = [vp, i32, vp, i32, vp]
-    L.tnc_debug_emulate_device.argtypes = [vp, i32, vp, i32, vp]
+    L.tnc_debug_emulate_device.argtypes = [vp, i32, vp, i32, i32, vp]
     L.tnc_profile_begin.argtypes = []
     L.tnc_profile_end.argtypes = [ctypes.POINTER(Profile)]
+    L.tnc_autotune.argtypes = [i32, i32, i32, i32, vp, i32, i32, ctypes.POINTER(i32), vp]
+    L.tnc_server_create.argtypes = [ctypes.POINTER(ServerOptions), ctypes.POINTER(vp)]
+    L.tnc_server_destroy.argtypes = [vp]
+    L.tnc_server_destroy.restype = None
+    L.tnc_server_set_tuning.argtypes = [vp, i32, ctypes.POINTER(Options)]
+    L.tnc_server_submit.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, i32, i32, vp, ctypes.POINTER(u64)]
+    L.tnc_server_wait.argtypes = [vp, u64, ctypes.POINTER(RequestStats)]
+    L.tnc_server_summary.argtypes = [vp, ctypes.POINTER(ServerStats)]
     for name in EXPORTED:
-        if name not in ("tnc_release", "tnc_strerror", "tnc_last_error"):
+        if name not in ("tnc_release", "tnc_strerror", "tnc_last_error", "tnc_server_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -128,6 +165,24 @@ def _c128_array(a: np.ndarray):
     return a, a.ctypes.data
 
 
+def _gate_array(gates: Sequence):
+    garr = (Gate2 * max(1, len(gates)))()
+    for i, g in enumerate(gates):
+        layer, q, kind, m = g[0], g[1], g[2], g[3]
+        garr[i].layer, garr[i].q, garr[i].kind = int(layer), int(q), int(kind)
+        if kind == GATE_DENSE4:
+            mm = np.asarray(m, dtype=np.complex128).reshape(16)
+            for e in range(16):
+                garr[i].m[e].re, garr[i].m[e].im = float(mm[e].real), float(mm[e].imag)
+    return garr
+
+
+def _options(options: dict) -> Options:
+    return Options(int(options.get("max_tile_bits", 0)), int(options.get("reg_bits", 0)),
+                   int(options.get("low_bits", 0)), int(options.get("math", 0)), int(options.get("pipeline", 0)),
+                   int(options.get("late_fold", 0)))
+
+
 class Plan:
     """A planned circuit (``tnc_plan``); owns the library handle."""
 
@@ -137,19 +192,8 @@ class Plan:
         one = np.ascontiguousarray(np.asarray(one_qubit, dtype=np.complex128).reshape(-1))
         if one.size != (self.d + 1) * self.n * 4:
             raise ValueError("one_qubit must hold (d+1)*n 2x2 gates")
-        garr = (Gate2 * max(1, len(gates)))()
-        for i, g in enumerate(gates):
-            layer, q, kind, m = g[0], g[1], g[2], g[3]
-            garr[i].layer, garr[i].q, garr[i].kind = int(layer), int(q), int(kind)
-            if kind == GATE_DENSE4:
-                mm = np.asarray(m, dtype=np.complex128).reshape(16)
-                for e in range(16):
-                    garr[i].m[e].re, garr[i].m[e].im = float(mm[e].real), float(mm[e].imag)
-        opt = None
-        if options:
-            opt = Options(int(options.get("max_tile_bits", 0)), int(options.get("reg_bits", 0)),
-                          int(options.get("low_bits", 0)), int(options.get("math", 0)),
-                          int(options.get("pipeline", 0)))
+        garr = _gate_array(gates)
+        opt = _options(options) if options else None
         h = ctypes.c_void_p()
         self._one = one
         _check(L.tnc_plan(self.n, self.d, one.ctypes.data, len(gates), ctypes.addressof(garr),
@@ -227,10 +271,11 @@ class Plan:
         _check(lib().tnc_debug_execute_host(self._h, bits.shape[0], bits.ctypes.data, int(k), out.ctypes.data))
         return out
 
-    def debug_emulate_device(self, bits: np.ndarray, k: int) -> np.ndarray:
+    def debug_emulate_device(self, bits: np.ndarray, k: int, storage: int = STORE_C64) -> np.ndarray:
         bits = np.ascontiguousarray(bits, dtype=np.uint8)
         out = np.empty((bits.shape[0], 1 << k), dtype=np.complex128)
-        _check(lib().tnc_debug_emulate_device(self._h, bits.shape[0], bits.ctypes.data, int(k), out.ctypes.data))
+        _check(lib().tnc_debug_emulate_device(self._h, bits.shape[0], bits.ctypes.data, int(k), int(storage),
+                                              out.ctypes.data))
         return out
 
 
@@ -260,3 +305,76 @@ def logxeb(amps, k: int, n_qubits: int, select=None, stream=None):
                             select.data_ptr() if select is not None else None, int(n_qubits),
                             res.data_ptr(), ctypes.c_void_p(s.cuda_stream)))
     return res
+
+
+def autotune(n: int, d: int, k: int, candidates: Sequence[dict], storage: int = STORE_C64, reps: int = 3):
+    """Time each candidate tile option set (``tnc_autotune``) on the current
+    device for an (n, d) brickwork circuit; returns (best index, median ms
+    per batch of every candidate)."""
+    arr = (Options * len(candidates))(*[_options(c) for c in candidates])
+    times = np.zeros(len(candidates), dtype=np.float64)
+    best = ctypes.c_int32()
+    _check(lib().tnc_autotune(int(n), int(d), int(k), int(storage), ctypes.addressof(arr), len(candidates),
+                              int(reps), ctypes.byref(best), times.ctypes.data))
+    return int(best.value), times
+
+
+class Server:
+    """Continuous-batching request loop (``tnc_server_*``) on the current device.
+
+    submit() returns a request id at once; wait(id) returns the amplitudes
+    (numpy complex128, (batches, 2^k)) and the request's timings.
+    """
+
+    def __init__(self, arena_bytes: int, n_streams: int = 4, n_planners: int = 4, small_bits: int = 20,
+                 max_graphs: int = 256):
+        o = ServerOptions(int(arena_bytes), int(n_streams), int(n_planners), int(small_bits), int(max_graphs))
+        h = ctypes.c_void_p()
+        _check(lib().tnc_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._pending = {}
+
+    def set_tuning(self, boundary_bits: int, options: dict):
+        o = _options(options)
+        _check(lib().tnc_server_set_tuning(self._h, int(boundary_bits), ctypes.byref(o)))
+
+    def submit(self, circ, bits: np.ndarray, k: int, storage: int = STORE_C64) -> int:
+        bits = np.ascontiguousarray(bits, dtype=np.uint8).reshape(-1, circ.n)
+        one = np.ascontiguousarray(np.asarray(circ.one_qubit, dtype=np.complex128).reshape(-1))
+        garr = _gate_array(circ.gates)
+        out = np.empty((bits.shape[0], 1 << k), dtype=np.complex128)
+        rid = ctypes.c_uint64()
+        _check(lib().tnc_server_submit(self._h, int(circ.n), int(circ.d), one.ctypes.data, len(circ.gates),
+                                       ctypes.addressof(garr), bits.shape[0], bits.ctypes.data, int(k),
+                                       int(storage), out.ctypes.data, ctypes.byref(rid)))
+        self._pending[rid.value] = out
+        return int(rid.value)
+
+    def wait(self, rid: int):
+        st = RequestStats()
+        rc = lib().tnc_server_wait(self._h, int(rid), ctypes.byref(st))
+        out = self._pending.pop(int(rid))
+        _check(rc)
+        return out, st.as_dict()
+
+    def summary(self) -> dict:
+        st = ServerStats()
+        _check(lib().tnc_server_summary(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().tnc_server_destroy(self._h)
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -13,6 +13,21 @@
 
 namespace tnc {
 
+// Storage of the boundary tensor in HBM.  C64: complex64 (re, im floats).
+// F16 / BF16: each entry is two 16-bit halves (re low, im high) of the value
+// divided by its block's FP32 power-of-two scale; a block is the 4096
+// entries (fewer in tiles below 2^12) that one tile wrote together.
+enum StoreMode : int { STORE_C64 = 0, STORE_F16 = 1, STORE_BF16 = 2 };
+
+// How the block scales of a 16-bit tensor were laid out by their writer:
+// tiles of the slots [0, lo_bits) and [win_lo, win_lo + win_len) (tile_bits
+// slots in all), each split into blocks of 2^blk_bits entries along its
+// highest local bits.  Scale slot of entry g (index within its batch):
+//   (tile(g) << (tile_bits - blk_bits)) | (local(g) >> blk_bits).
+struct ScaleMap {
+  int lo_bits, win_lo, win_len, tile_bits, blk_bits;
+};
+
 // One boundary-tensor update inside a pass (16 bytes).  Within a register
 // phase, op b acts on the pairs along register bit b; ops b >= 1 are
 // controlled by register bit b-1, op 0 by the tile bit `cloc` of the thread
@@ -32,13 +47,15 @@ static_assert(sizeof(DevOp) == 16, "DevOp layout");
 // A register phase: n_ops consecutive ops from op_begin, run with local tile
 // bits reg[0..R-1] held in registers (register bit b <-> local bit reg[b]).
 // first_dup: op 0 copies the register half with bit 0 clear onto the half
-// with bit 0 set (the top-slot expand of odd depth).
+// with bit 0 set (the top-slot expand of odd depth).  cloc0: op 0's control
+// as a local tile bit of the thread part (-1: uncontrolled).
 struct DevPhase {
   int32_t op_begin;
   int8_t n_ops;
   int8_t first_dup;
   int8_t reg[8];
-  int16_t pad;
+  int8_t cloc0;
+  int8_t pad;
 };
 static_assert(sizeof(DevPhase) == 16, "DevPhase layout");
 
@@ -52,6 +69,10 @@ struct PassArgs {
   const DevOp* ops;
   const float* mats;
   const float4* mrows;
+  // the batch's own matrices: rmats[b][op][ctl][k00 k01 k10 k11 as (re, im)]
+  // (the variant of every op already picked from batch b's output bits)
+  const float* rmats;
+  long long rstride;     // floats per batch in rmats
   float2* B;             // boundary tensors, batch stride 2^h entries
   const uint8_t* bits;   // output bits, batch stride n
   int n_phases;
@@ -62,14 +83,20 @@ struct PassArgs {
   int n_tiles;           // batches << (h - T)
   int mfma;              // register-controlled updates on the matrix cores
   int pipeline;          // persistent blocks prefetching the next tile
-  int op_begin;          // this pass's ops: [op_begin, op_begin + n_ops)
-  int n_ops;
+  int store;             // StoreMode of B
+  // 16-bit storage only: scales read (written by the previous writer, laid
+  // out by in_map) and written (laid out by this pass's own tiles); batch
+  // stride scale_stride floats
+  const float* scale_in;
+  float* scale_out;
+  long long scale_stride;
+  ScaleMap in_map;
 };
 
 // Launch parameters of a late-phase folded contraction:
 //   out[b][r][c] = sum_kk in[b][r][kk] * J[var(b)][kk][c]
 struct LateArgs {
-  const void* in;        // float2 (first launch) or double2
+  const void* in;        // boundary tensor (first launch, storage `store`) or double2
   double2* out;
   const double2* J;      // [vars][K][N]
   const uint8_t* bits;
@@ -79,6 +106,10 @@ struct LateArgs {
   int n_batches;
   int xrow;              // -1: one variant; else var = x[xrow]
   int n;
+  int store;             // StoreMode of `in` (first launch)
+  const float* scale_in; // 16-bit storage: block scales, laid out by in_map
+  long long scale_stride;
+  ScaleMap in_map;
 };
 
 // One op of a late program (device copy of LateOp, plan.hpp).
@@ -112,8 +143,21 @@ struct LateOpsArgs {
   double2 dot[2][2];
 };
 
+// Resolution of the op variants of a batch group: for batch b and op o,
+// rmats[b][o][0..16) = mats[(o*4 + var(b, o))*16 .. +16).
+struct ResolveArgs {
+  const DevOp* ops;
+  const float* mats;
+  const uint8_t* bits;
+  float* rmats;
+  long long rstride;
+  int n_ops;
+  int n;
+  int n_batches;
+};
+
 struct InitArgs {
-  float2* B;
+  float2* B;             // complex64 tensor, or the 16-bit tensor (store != C64)
   const uint8_t* bits;
   const double2* seg;    // (m0-1) x 4 entries, seg_j[a_j][a_{j-1}] row-major
   double2 v[2];
@@ -122,6 +166,10 @@ struct InitArgs {
   int h;
   int n;
   int n_batches;
+  int store;             // StoreMode of B
+  float* scale_out;      // 16-bit storage: one scale per 2^blk_bits consecutive entries
+  long long scale_stride;
+  int blk_bits;
 };
 
 }  // namespace tnc

@@ -20,8 +20,11 @@ namespace tnc {
 // Row-0 build-up.  The first row only creates slots: its boundary tensor is
 // the product  v[a_0] * prod_{j>=1} seg_j[a_j][a_{j-1}] * f_x[a_{m-1}]
 // (copy tensors of the down-bonds joined by the one-qubit segments).
-// Each thread writes 32 consecutive entries; factors that only involve bits
-// >= 5 are multiplied once per thread.  Entries above 2^m are zeroed.
+// For h >= 11 each wave writes 2048 consecutive entries, lane l taking the
+// entries 64 e + l (e < 32): every store is one contiguous 512-byte run, and
+// the factors of bits 0..5 (the lane) and >= 11 (the wave) are multiplied
+// once per thread, those of bits 6..10 per entry.  Entries above 2^m are
+// zero.
 __device__ inline double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -31,53 +34,152 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
   const int nseg = a.m0 - 1;
   for (int i = threadIdx.x; i < 4 * nseg; i += blockDim.x) seg[i] = a.seg[i];
   __syncthreads();
-  const int per = a.h >= 5 ? 32 : 1;
-  const long long total = ((long long)a.n_batches << a.h) / per;
+  const int m = a.m0;
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= total) return;
-  const long long first = gid * per;
-  const long long batch = first >> a.h;
-  const unsigned long long i0 = (unsigned long long)first & ((1ull << a.h) - 1ull);
-  float2* out = a.B + first;
-  if (i0 >= (1ull << a.m0)) {
-    for (int e = 0; e < per; ++e) out[e] = make_float2(0.f, 0.f);
+  auto sg = [&](int j, unsigned long long i) {
+    return seg[4 * (j - 1) + 2 * (int)((i >> j) & 1ull) + (int)((i >> (j - 1)) & 1ull)];
+  };
+  if (a.h < 11) {
+    const long long total = (long long)a.n_batches << a.h;
+    if (gid >= total) return;
+    const long long batch = gid >> a.h;
+    const unsigned long long i = (unsigned long long)gid & ((1ull << a.h) - 1ull);
+    float2* out = a.B + gid;
+    if (i >> m) {
+      *out = make_float2(0.f, 0.f);
+      return;
+    }
+    const int x0 = a.bits[batch * a.n];
+    double2 val = a.v[i & 1ull];
+    for (int j = 1; j < m; ++j) val = zmul(val, sg(j, i));
+    val = zmul(val, a.f[x0][(i >> (m - 1)) & 1ull]);
+    *out = make_float2((float)val.x, (float)val.y);
     return;
   }
+  const long long wave = gid >> 6;
+  const unsigned long long lane = (unsigned long long)(gid & 63);
+  if (wave >= (((long long)a.n_batches << a.h) >> 11)) return;
+  const long long first = wave << 11;
+  const long long batch = first >> a.h;
+  const unsigned long long i0 = ((unsigned long long)first & ((1ull << a.h) - 1ull)) | lane;
+  float2* out = a.B + first + (long long)lane;
   const int x0 = a.bits[batch * a.n];
-  const int m = a.m0;
-  // With 32 entries per thread, factors seg_j with j >= 6 (and the end vector
-  // when m-1 >= 5) only involve bits >= 5 and are multiplied once.
-  const int jsplit = per == 32 ? 6 : 1;
-  const bool f_hi = per == 32 && (m - 1) >= 5;
-  double2 hi = make_double2(1.0, 0.0);
-  for (int j = jsplit; j < m; ++j) {
-    const int aj = (int)((i0 >> j) & 1ull), ajm = (int)((i0 >> (j - 1)) & 1ull);
-    hi = zmul(hi, seg[4 * (j - 1) + 2 * aj + ajm]);
-  }
-  if (f_hi) hi = zmul(hi, a.f[x0][(i0 >> (m - 1)) & 1ull]);
-  const int jend = m < jsplit ? m : jsplit;
-  for (int e = 0; e < per; ++e) {
-    const unsigned long long i = i0 + (unsigned long long)e;
+  // factors fixed for the thread: bits 0..5 (lane) and >= 11 (wave)
+  double2 fixed = a.v[lane & 1ull];
+  for (int j = 1; j < m && j <= 5; ++j) fixed = zmul(fixed, sg(j, i0));
+  for (int j = 12; j < m; ++j) fixed = zmul(fixed, sg(j, i0));
+  const bool f_var = m - 1 >= 6 && m - 1 <= 10;
+  if (!f_var) fixed = zmul(fixed, a.f[x0][(i0 >> (m - 1)) & 1ull]);
+  const int jhi = m - 1 < 11 ? m - 1 : 11;
+  for (int e = 0; e < 32; ++e) {
+    const unsigned long long i = i0 + ((unsigned long long)e << 6);
     if (i >> m) {
-      out[e] = make_float2(0.f, 0.f);
+      out[e << 6] = make_float2(0.f, 0.f);
       continue;
     }
-    double2 val = zmul(hi, a.v[i & 1ull]);
-    for (int j = 1; j < jend; ++j) {
-      const int aj = (int)((i >> j) & 1ull), ajm = (int)((i >> (j - 1)) & 1ull);
-      val = zmul(val, seg[4 * (j - 1) + 2 * aj + ajm]);
-    }
-    if (!f_hi) val = zmul(val, a.f[x0][(i >> (m - 1)) & 1ull]);
-    out[e] = make_float2((float)val.x, (float)val.y);
+    double2 val = fixed;
+    for (int j = 6; j <= jhi; ++j) val = zmul(val, sg(j, i));
+    if (f_var) val = zmul(val, a.f[x0][(i >> (m - 1)) & 1ull]);
+    out[e << 6] = make_float2((float)val.x, (float)val.y);
   }
 }
 
 hipError_t launch_init(const InitArgs& a, hipStream_t s) {
   if (a.m0 - 1 > 64) return hipErrorInvalidValue;
-  const int per = a.h >= 5 ? 32 : 1;
-  const long long threads = ((long long)a.n_batches << a.h) / per;
+  const long long threads = a.h < 11 ? ((long long)a.n_batches << a.h) : (((long long)a.n_batches << a.h) >> 5);
   const long long blocks = (threads + kBlock - 1) / kBlock;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+// Row-0 build-up into 16-bit block-scaled storage: one workgroup per block
+// of 2^blk_bits consecutive entries (the scale block of this writer); the
+// FP64 product is rounded to FP32 as in the complex64 path, then the block
+// maximum fixes the power-of-two scale.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_init16(InitArgs a) {
+  constexpr int kMaxPer = 4096 / kBlock;
+  __shared__ double2 seg[4 * 64];
+  __shared__ uint32_t smax;
+  const int nseg = a.m0 - 1;
+  for (int i = threadIdx.x; i < 4 * nseg; i += blockDim.x) seg[i] = a.seg[i];
+  if (threadIdx.x == 0) smax = 0u;
+  __syncthreads();
+  const int bb = a.blk_bits;
+  const int per_batch_blocks_log = a.h - bb;
+  const long long batch = (long long)blockIdx.x >> per_batch_blocks_log;
+  const unsigned long long sblk = (unsigned long long)blockIdx.x & ((1ull << per_batch_blocks_log) - 1ull);
+  const unsigned long long i0 = sblk << bb;
+  const int nper = 1 << bb;
+  const int x0 = a.bits[batch * a.n];
+  const int m = a.m0;
+  float2 val[kMaxPer];
+  float amax = 0.f;
+#pragma unroll
+  for (int q = 0; q < kMaxPer; ++q) {
+    const int off = q * kBlock + (int)threadIdx.x;
+    val[q] = make_float2(0.f, 0.f);
+    if (off >= nper) continue;
+    const unsigned long long i = i0 + (unsigned long long)off;
+    if (i >> m) continue;
+    double2 v = a.v[i & 1ull];
+    for (int j = 1; j < m; ++j) {
+      const int aj = (int)((i >> j) & 1ull), ajm = (int)((i >> (j - 1)) & 1ull);
+      v = zmul(v, seg[4 * (j - 1) + 2 * aj + ajm]);
+    }
+    v = zmul(v, a.f[x0][(i >> (m - 1)) & 1ull]);
+    val[q] = make_float2((float)v.x, (float)v.y);
+    amax = fmaxf(amax, fmaxf(fabsf(val[q].x), fabsf(val[q].y)));
+  }
+  if (amax > 0.f) atomicMax(&smax, __float_as_uint(amax));
+  __syncthreads();
+  const int e = block_exponent(__uint_as_float(smax));
+  const float inv = ldexpf(1.f, -e);
+  uint32_t* out = reinterpret_cast<uint32_t*>(a.B) + (batch << a.h) + i0;
+#pragma unroll
+  for (int q = 0; q < kMaxPer; ++q) {
+    const int off = q * kBlock + (int)threadIdx.x;
+    if (off < nper) out[off] = pack16<S>(val[q].x, val[q].y, inv);
+  }
+  if (threadIdx.x == 0) a.scale_out[batch * a.scale_stride + (long long)sblk] = ldexpf(1.f, e);
+}
+
+hipError_t launch_init16(const InitArgs& a, hipStream_t s) {
+  if (a.m0 - 1 > 64 || a.blk_bits > 12 || a.blk_bits < 0 || a.blk_bits > a.h) return hipErrorInvalidValue;
+  const long long blocks = (long long)a.n_batches << (a.h - a.blk_bits);
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (a.store == STORE_F16) hipLaunchKernelGGL(k_init16<STORE_F16>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+  else if (a.store == STORE_BF16) hipLaunchKernelGGL(k_init16<STORE_BF16>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Variant resolution: every op's matrix pair for each batch of the group,
+// picked once from the batch's output bits, so the pass kernels read their
+// matrices at addresses that depend on the op only.
+__global__ __launch_bounds__(kBlock) void k_resolve(ResolveArgs a) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = (long long)a.n_batches * a.n_ops;
+  if (gid >= total) return;
+  const int b = (int)(gid / a.n_ops);
+  const int o = (int)(gid - (long long)b * a.n_ops);
+  const DevOp op = a.ops[o];
+  const uint8_t* x = a.bits + (size_t)b * a.n;
+  const int var = (op.xrow0 >= 0 ? 2 * (x[op.xrow0] & 1) : 0) + (op.xrow1 >= 0 ? (x[op.xrow1] & 1) : 0);
+  const float4* src = reinterpret_cast<const float4*>(a.mats + ((size_t)op.mat * 4 + var) * 16);
+  float4* dst = reinterpret_cast<float4*>(a.rmats + (size_t)b * a.rstride + (size_t)o * 16);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dst[q] = src[q];
+}
+
+hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s) {
+  const long long total = (long long)a.n_batches * a.n_ops;
+  if (total <= 0) return hipSuccess;
+  const long long blocks = (total + kBlock - 1) / kBlock;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_resolve, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -90,7 +192,9 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s) {
 //   slots as register bits), the phase's updates in registers, registers ->
 //   LDS,
 //   LDS -> HBM, in place.
-template <int R, bool MULTI, bool MF>
+// WU: every wave lies inside one tile (one tile per block, or T - R >= 6),
+// so the batch and everything read through it are wave-uniform.
+template <int R, bool MULTI, bool MF, bool WU>
 __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
   extern __shared__ float2 lds[];
   constexpr int E = 1 << R;
@@ -103,7 +207,8 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
   const long long tile = (long long)blockIdx.x * tiles_per_block + tile_in_block;
   const bool active = tile < a.n_tiles;
   const int tbits = a.h - T;
-  const long long batch = active ? (tile >> tbits) : 0;
+  long long batch = active ? (tile >> tbits) : 0;
+  if constexpr (WU) batch = __builtin_amdgcn_readfirstlane((int)batch);
   const unsigned long long blk = active ? ((unsigned long long)tile & ((1ull << tbits) - 1ull)) : 0ull;
   float2* __restrict__ Bt = a.B + (batch << a.h) + block_offset(blk, a.lo_bits, a.win_lo, a.win_len);
   char* region = reinterpret_cast<char*>(lds) + ((size_t)tile_in_block << (T + 3));
@@ -122,15 +227,15 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
   const uint32_t tmask = (1u << T) - 1u;
   PhaseCtx<R, MF> ctx;
   ctx.ops = (const TNC_TBL DevOp*)a.ops;
-  ctx.mats = (const TNC_TBL float*)a.mats;
+  ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
   ctx.mrows = a.mrows;
   ctx.bits = a.bits;
   ctx.xpos = (size_t)batch * a.n;
   ctx.tb = 0;
   ctx.lane = tid & 63;
-  ctx.uniform = !MULTI;
+  ctx.uniform = WU;
   for (int p = 0; p < a.n_phases; ++p) {
-    const DevPhase P = ((const TNC_TBL DevPhase*)a.phases)[p];
+    const DevPhase P = load_phase(a.phases, p);
     phase_dispatch<R, MF>(region, P, ctx, tt, tmask);
     __syncthreads();
   }
@@ -141,6 +246,117 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
       const uint32_t i = (uint32_t)(it * tpt + (int)tt) * 2u;
       const float4 val = *reinterpret_cast<const float4*>(region + ((size_t)swz(i) << 3));
       *reinterpret_cast<float4*>(Bt + tile_offset(i, a.lo_bits, a.win_lo)) = val;
+    }
+  }
+}
+
+// The pass kernel on 16-bit block-scaled storage: the same tiles and
+// phases as k_pass, with the entries decoded (value = stored x block scale
+// of the previous writer) on the way into LDS, and re-encoded on the way out
+// with a fresh power-of-two scale per block of this pass's tiles (taken from
+// the block's largest component after the pass).  4 entries (16 bytes) per
+// HBM access, 2 when a thread holds only 2 entries.
+template <int R, bool MULTI, int S, bool WU>
+__global__ __launch_bounds__(kBlock) void k_pass16(PassArgs a) {
+  extern __shared__ float2 lds[];
+  constexpr int E = 1 << R;
+  constexpr int U = E >= 4 ? 4 : 2;
+  const int T = a.T;
+  const int TB = T - R;
+  const int tid = threadIdx.x;
+  const int tile_in_block = MULTI ? (tid >> TB) : 0;
+  const uint32_t tt = MULTI ? (uint32_t)(tid & ((1 << TB) - 1)) : (uint32_t)tid;
+  const int tiles_per_block = MULTI ? (kBlock >> TB) : 1;
+  const long long tile = (long long)blockIdx.x * tiles_per_block + tile_in_block;
+  const bool active = tile < a.n_tiles;
+  const int tbits = a.h - T;
+  long long batch = active ? (tile >> tbits) : 0;
+  if constexpr (WU) batch = __builtin_amdgcn_readfirstlane((int)batch);
+  const unsigned long long blk = active ? ((unsigned long long)tile & ((1ull << tbits) - 1ull)) : 0ull;
+  const uint64_t boff = block_offset(blk, a.lo_bits, a.win_lo, a.win_len);
+  uint32_t* __restrict__ Bw = reinterpret_cast<uint32_t*>(a.B) + (batch << a.h);
+  const float* __restrict__ sin = a.scale_in + batch * a.scale_stride;
+  char* region = reinterpret_cast<char*>(lds) + ((size_t)tile_in_block << (T + 3));
+  uint32_t* smax = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(lds) + ((size_t)tiles_per_block << (T + 3)));
+  const int tpt = 1 << TB;
+  const int blk_bits = T < 12 ? T : 12;
+  const bool two = T > blk_bits;
+  if (tid < 2 * tiles_per_block) smax[tid] = 0u;
+
+  if (active) {
+#pragma unroll
+    for (int it = 0; it < E / U; ++it) {
+      const uint32_t i = (uint32_t)(it * tpt + (int)tt) * (uint32_t)U;
+      const uint64_t g = boff + tile_offset(i, a.lo_bits, a.win_lo);
+      const float sc = sin[scale_slot(g, a.in_map)];
+      if constexpr (U == 4) {
+        const uint4 w = *reinterpret_cast<const uint4*>(Bw + g);
+        const float2 e0 = unpack16<S>(w.x, sc), e1 = unpack16<S>(w.y, sc);
+        const float2 e2 = unpack16<S>(w.z, sc), e3 = unpack16<S>(w.w, sc);
+        *reinterpret_cast<float4*>(region + ((size_t)swz(i) << 3)) = make_float4(e0.x, e0.y, e1.x, e1.y);
+        *reinterpret_cast<float4*>(region + ((size_t)swz(i + 2u) << 3)) = make_float4(e2.x, e2.y, e3.x, e3.y);
+      } else {
+        const uint2 w = *reinterpret_cast<const uint2*>(Bw + g);
+        const float2 e0 = unpack16<S>(w.x, sc), e1 = unpack16<S>(w.y, sc);
+        *reinterpret_cast<float4*>(region + ((size_t)swz(i) << 3)) = make_float4(e0.x, e0.y, e1.x, e1.y);
+      }
+    }
+  }
+  __syncthreads();
+
+  const uint32_t tmask = (1u << T) - 1u;
+  PhaseCtx<R, false> ctx;
+  ctx.ops = (const TNC_TBL DevOp*)a.ops;
+  ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
+  ctx.mrows = a.mrows;
+  ctx.bits = a.bits;
+  ctx.xpos = (size_t)batch * a.n;
+  ctx.tb = 0;
+  ctx.lane = tid & 63;
+  ctx.uniform = WU;
+  for (int p = 0; p < a.n_phases; ++p) {
+    const DevPhase P = load_phase(a.phases, p);
+    phase_dispatch<R, false>(region, P, ctx, tt, tmask);
+    __syncthreads();
+  }
+
+  // largest component of each block of the tile
+  if (active) {
+    float m0 = 0.f, m1 = 0.f;
+#pragma unroll
+    for (int it = 0; it < E / 2; ++it) {
+      const uint32_t i = (uint32_t)(it * tpt + (int)tt) * 2u;
+      const float4 v = *reinterpret_cast<const float4*>(region + ((size_t)swz(i) << 3));
+      const float am = fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w)));
+      if ((i >> blk_bits) & 1u) m1 = fmaxf(m1, am);
+      else m0 = fmaxf(m0, am);
+    }
+    if (m0 > 0.f) atomicMax(&smax[2 * tile_in_block], __float_as_uint(m0));
+    if (m1 > 0.f) atomicMax(&smax[2 * tile_in_block + 1], __float_as_uint(m1));
+  }
+  __syncthreads();
+  if (active) {
+    const int x0 = block_exponent(__uint_as_float(smax[2 * tile_in_block]));
+    const int x1 = block_exponent(__uint_as_float(smax[2 * tile_in_block + 1]));
+    const float inv0 = ldexpf(1.f, -x0), inv1 = ldexpf(1.f, -x1);
+#pragma unroll
+    for (int it = 0; it < E / U; ++it) {
+      const uint32_t i = (uint32_t)(it * tpt + (int)tt) * (uint32_t)U;
+      const uint64_t g = boff + tile_offset(i, a.lo_bits, a.win_lo);
+      const float inv = ((i >> blk_bits) & 1u) ? inv1 : inv0;
+      const float4 v0 = *reinterpret_cast<const float4*>(region + ((size_t)swz(i) << 3));
+      if constexpr (U == 4) {
+        const float4 v1 = *reinterpret_cast<const float4*>(region + ((size_t)swz(i + 2u) << 3));
+        *reinterpret_cast<uint4*>(Bw + g) = make_uint4(pack16<S>(v0.x, v0.y, inv), pack16<S>(v0.z, v0.w, inv),
+                                                       pack16<S>(v1.x, v1.y, inv), pack16<S>(v1.z, v1.w, inv));
+      } else {
+        *reinterpret_cast<uint2*>(Bw + g) = make_uint2(pack16<S>(v0.x, v0.y, inv), pack16<S>(v0.z, v0.w, inv));
+      }
+    }
+    if (tt == 0) {
+      float* sout = a.scale_out + batch * a.scale_stride + ((long long)blk << (T - blk_bits));
+      sout[0] = ldexpf(1.f, x0);
+      if (two) sout[1] = ldexpf(1.f, x1);
     }
   }
 }
@@ -195,7 +411,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     if (next < a.n_tiles) prefetch(next);
     PhaseCtx<R, MF> ctx;
     ctx.ops = (const TNC_TBL DevOp*)a.ops;
-    ctx.mats = (const TNC_TBL float*)a.mats;
+    ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
     ctx.mrows = a.mrows;
     ctx.bits = a.bits;
     ctx.xpos = (size_t)batch * a.n;
@@ -203,7 +419,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     ctx.lane = tid & 63;
     ctx.uniform = true;
     for (int p = 0; p < a.n_phases; ++p) {
-      const DevPhase P = ((const TNC_TBL DevPhase*)a.phases)[p];
+      const DevPhase P = load_phase(a.phases, p);
       phase_dispatch<R, MF>(region, P, ctx, tt, tmask);
       __syncthreads();
     }
@@ -279,7 +495,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT
     char* region = reinterpret_cast<char*>(cur);
     PhaseCtx<R, false> ctx;
     ctx.ops = (const TNC_TBL DevOp*)a.ops;
-    ctx.mats = (const TNC_TBL float*)a.mats;
+    ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
     ctx.mrows = nullptr;
     ctx.bits = a.bits;
     ctx.xpos = (size_t)batch * a.n;
@@ -287,7 +503,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT
     ctx.lane = tid & 63;
     ctx.uniform = true;
     for (int p = 0; p < a.n_phases; ++p) {
-      const DevPhase P = ((const TNC_TBL DevPhase*)a.phases)[p];
+      const DevPhase P = load_phase(a.phases, p);
       phase_dispatch<R, false>(region, P, ctx, tt, tmask);
       TNC_WAIT_LGKM0();
       __builtin_amdgcn_s_barrier();
@@ -346,8 +562,24 @@ static hipError_t launch_pass_dma(const PassArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int R, int S>
+static hipError_t launch_pass16_rs(const PassArgs& a, hipStream_t s) {
+  const int TB = a.T - R;
+  if (TB < 0 || TB > 8) return hipErrorInvalidValue;
+  const bool multi = TB < 8;
+  const int tiles_per_block = multi ? (kBlock >> TB) : 1;
+  const long long blocks = ((long long)a.n_tiles + tiles_per_block - 1) / tiles_per_block;
+  const size_t lds = ((size_t)tiles_per_block << (a.T + 3)) + 2 * sizeof(uint32_t) * (size_t)kBlock;
+  if (multi && TB >= 6) hipLaunchKernelGGL((k_pass16<R, true, S, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+  else if (multi) hipLaunchKernelGGL((k_pass16<R, true, S, false>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+  else hipLaunchKernelGGL((k_pass16<R, false, S, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+  return hipGetLastError();
+}
+
 template <int R>
 static hipError_t launch_pass_r(const PassArgs& a, hipStream_t s) {
+  if (a.store == STORE_F16) return launch_pass16_rs<R, STORE_F16>(a, s);
+  if (a.store == STORE_BF16) return launch_pass16_rs<R, STORE_BF16>(a, s);
   const int TB = a.T - R;
   const bool dma_ok = a.pipeline && !a.mfma;
   if constexpr (R >= 4) {
@@ -376,11 +608,12 @@ static hipError_t launch_pass_r(const PassArgs& a, hipStream_t s) {
     return hipGetLastError();
   }
   if (multi) {
-    if (mf) hipLaunchKernelGGL((k_pass<R, true, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((k_pass<R, true, false>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    if (mf) hipLaunchKernelGGL((k_pass<R, true, true, false>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    else if (TB >= 6) hipLaunchKernelGGL((k_pass<R, true, false, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    else hipLaunchKernelGGL((k_pass<R, true, false, false>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
   } else {
-    if (mf) hipLaunchKernelGGL((k_pass<R, false, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((k_pass<R, false, false>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    if (mf) hipLaunchKernelGGL((k_pass<R, false, true, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    else hipLaunchKernelGGL((k_pass<R, false, false, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
   }
   return hipGetLastError();
 }
@@ -406,21 +639,38 @@ static void emulate_pass_r(const PassArgs& a) {
   std::vector<float2> lds((size_t)1 << T);
   char* region = reinterpret_cast<char*>(lds.data());
   const uint32_t tmask = (1u << T) - 1u;
+  const bool s16 = a.store == STORE_F16 || a.store == STORE_BF16;
+  auto dec = [&](uint32_t w, float sc) {
+    return a.store == STORE_F16 ? unpack16<STORE_F16>(w, sc) : unpack16<STORE_BF16>(w, sc);
+  };
+  auto enc = [&](float2 v, float inv) {
+    return a.store == STORE_F16 ? pack16<STORE_F16>(v.x, v.y, inv) : pack16<STORE_BF16>(v.x, v.y, inv);
+  };
+  const int blk_bits = T < 12 ? T : 12;
   for (long long tile = 0; tile < a.n_tiles; ++tile) {
     const long long batch = tile >> tbits;
     const unsigned long long blk = (unsigned long long)tile & ((1ull << tbits) - 1ull);
-    float2* Bt = a.B + (batch << a.h) + block_offset(blk, a.lo_bits, a.win_lo, a.win_len);
+    const uint64_t boff = block_offset(blk, a.lo_bits, a.win_lo, a.win_len);
+    float2* Bt = a.B + (batch << a.h) + boff;
+    uint32_t* Bw = reinterpret_cast<uint32_t*>(a.B) + (batch << a.h);
     for (int tt = 0; tt < tpt; ++tt)
       for (int it = 0; it < E / 2; ++it) {
         const uint32_t i = (uint32_t)(it * tpt + tt) * 2u;
-        const float2* src = Bt + tile_offset(i, a.lo_bits, a.win_lo);
         float2* dst = reinterpret_cast<float2*>(region + ((size_t)swz(i) << 3));
-        dst[0] = src[0];
-        dst[1] = src[1];
+        if (s16) {
+          const uint64_t g = boff + tile_offset(i, a.lo_bits, a.win_lo);
+          const float sc = a.scale_in[batch * a.scale_stride + (long long)scale_slot(g, a.in_map)];
+          dst[0] = dec(Bw[g], sc);
+          dst[1] = dec(Bw[g + 1], sc);
+        } else {
+          const float2* src = Bt + tile_offset(i, a.lo_bits, a.win_lo);
+          dst[0] = src[0];
+          dst[1] = src[1];
+        }
       }
     PhaseCtx<R, false> ctx;
     ctx.ops = (const TNC_TBL DevOp*)a.ops;
-    ctx.mats = (const TNC_TBL float*)a.mats;
+    ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
     ctx.mrows = a.mrows;
     ctx.bits = a.bits;
     ctx.xpos = (size_t)batch * a.n;
@@ -428,8 +678,25 @@ static void emulate_pass_r(const PassArgs& a) {
     ctx.lane = 0;
     ctx.uniform = false;
     for (int p = 0; p < a.n_phases; ++p) {
-      const DevPhase P = ((const TNC_TBL DevPhase*)a.phases)[p];
+      const DevPhase P = load_phase(a.phases, p);
       for (int tt = 0; tt < tpt; ++tt) phase_dispatch<R, false>(region, P, ctx, (uint32_t)tt, tmask);
+    }
+    if (s16) {
+      float amax[2] = {0.f, 0.f};
+      for (uint32_t i = 0; i < (1u << T); ++i) {
+        const float2 v = lds[swz(i)];
+        float& m = amax[(i >> blk_bits) & 1u];
+        m = std::max(m, std::max(std::fabs(v.x), std::fabs(v.y)));
+      }
+      const int x0 = block_exponent(amax[0]), x1 = block_exponent(amax[1]);
+      for (uint32_t i = 0; i < (1u << T); ++i) {
+        const uint64_t g = boff + tile_offset(i, a.lo_bits, a.win_lo);
+        Bw[g] = enc(lds[swz(i)], std::ldexp(1.f, -(((i >> blk_bits) & 1u) ? x1 : x0)));
+      }
+      float* sout = a.scale_out + batch * a.scale_stride + ((long long)blk << (T - blk_bits));
+      sout[0] = std::ldexp(1.f, x0);
+      if (T > blk_bits) sout[1] = std::ldexp(1.f, x1);
+      continue;
     }
     for (int tt = 0; tt < tpt; ++tt)
       for (int it = 0; it < E / 2; ++it) {
@@ -462,7 +729,18 @@ void emulate_pass_host(const PassArgs& a, int R) {
 __device__ inline double2 to_d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
 __device__ inline double2 to_d2(double2 v) { return v; }
 
-template <typename TIn>
+// Entry g of batch b of the first late launch's input, in FP64.
+template <typename TIn, int S>
+__device__ inline double2 late_in(const LateArgs& a, const TIn* __restrict__ in, int b, uint64_t g) {
+  if constexpr (S == STORE_F16 || S == STORE_BF16) {
+    const float sc = a.scale_in[(long long)b * a.scale_stride + (long long)scale_slot(g, a.in_map)];
+    return to_d2(unpack16<S>(in[g], sc));
+  } else {
+    return to_d2(in[g]);
+  }
+}
+
+template <typename TIn, int S>
 __global__ __launch_bounds__(kBlock) void k_late(LateArgs a) {
   __shared__ double2 As[16][65];
   __shared__ double2 Bs[16][65];
@@ -493,7 +771,7 @@ __global__ __launch_bounds__(kBlock) void k_late(LateArgs a) {
       const int r = e >> 4, kk = e & 15;
       const int row = row0 + r;
       double2 val = make_double2(0.0, 0.0);
-      if (row < a.M && k0 + kk < a.K) val = to_d2(in[(size_t)row * a.K + k0 + kk]);
+      if (row < a.M && k0 + kk < a.K) val = late_in<TIn, S>(a, in, b, (uint64_t)row * a.K + k0 + kk);
       As[kk][r] = val;
     }
     for (int e = tid; e < 1024; e += kBlock) {
@@ -539,8 +817,10 @@ hipError_t launch_late(const LateArgs& a, bool in_c64, hipStream_t s) {
   const long long tiles = tilesM8 * ((a.N + 63) / 64);
   if (tiles > 0x7fffffffLL || a.n_batches > 65535) return hipErrorInvalidValue;
   dim3 grid((unsigned)tiles, (unsigned)a.n_batches);
-  if (in_c64) hipLaunchKernelGGL(k_late<float2>, grid, dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL(k_late<double2>, grid, dim3(kBlock), 0, s, a);
+  if (!in_c64) hipLaunchKernelGGL((k_late<double2, STORE_C64>), grid, dim3(kBlock), 0, s, a);
+  else if (a.store == STORE_F16) hipLaunchKernelGGL((k_late<uint32_t, STORE_F16>), grid, dim3(kBlock), 0, s, a);
+  else if (a.store == STORE_BF16) hipLaunchKernelGGL((k_late<uint32_t, STORE_BF16>), grid, dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL((k_late<float2, STORE_C64>), grid, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

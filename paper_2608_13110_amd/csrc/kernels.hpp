@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 
 #include "device_tables.hpp"
@@ -45,6 +46,64 @@ TNC_HD inline uint32_t pdep32(uint32_t x, uint32_t mask) {
   return r;
 }
 
+// ---------------------------------------------------------------------------
+// 16-bit block-scaled storage.
+
+// Scale slot of entry g (index within its batch) under the writer's layout.
+TNC_HD inline uint64_t scale_slot(uint64_t g, const ScaleMap& m) {
+  const uint64_t lo_mask = (1ull << m.lo_bits) - 1ull;
+  const uint64_t local = (g & lo_mask) | (((g >> m.win_lo) & ((1ull << m.win_len) - 1ull)) << m.lo_bits);
+  const int gap = m.win_lo - m.lo_bits;
+  const uint64_t tile = ((g >> m.lo_bits) & ((1ull << gap) - 1ull)) | ((g >> (m.win_lo + m.win_len)) << gap);
+  return (tile << (m.tile_bits - m.blk_bits)) | (local >> m.blk_bits);
+}
+
+// Exponent e of the power-of-two block scale 2^e that puts the block's
+// largest component amax in [2^14, 2^15): below the FP16 maximum (65504)
+// with a full binade of headroom, and far inside the BF16 range.  e is kept
+// in [-100, 100] so that 2^e and 2^-e are normal FP32 numbers; a block whose
+// largest component is below 2^-86 (rounding residue of exact zeros) is
+// stored below the top of the range.
+TNC_HD inline int block_exponent(float amax) {
+  if (!(amax > 0.f)) return 0;
+  int e = 0;
+  (void)frexpf(amax, &e);  // amax in [2^(e-1), 2^e)
+  e -= 15;
+  return e < -100 ? -100 : (e > 100 ? 100 : e);
+}
+
+// One component stored in 16 bits (round to nearest even) and read back.
+template <int S>
+TNC_HD inline uint32_t to16(float x) {
+  if constexpr (S == STORE_F16) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)x);
+  } else {
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+  }
+}
+
+template <int S>
+TNC_HD inline float from16(uint32_t v) {
+  if constexpr (S == STORE_F16) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(v & 0xFFFFu));
+  } else {
+    return __builtin_bit_cast(float, v << 16);
+  }
+}
+
+// An entry (re, im) as one 32-bit word of two 16-bit halves.
+template <int S>
+TNC_HD inline uint32_t pack16(float re, float im, float inv_scale) {
+  return to16<S>(re * inv_scale) | (to16<S>(im * inv_scale) << 16);
+}
+
+template <int S>
+TNC_HD inline float2 unpack16(uint32_t w, float scale) {
+  return make_float2(from16<S>(w) * scale, from16<S>(w >> 16) * scale);
+}
+
 // The pass tables (phases, ops, matrices) are read through the constant
 // address space on the device: wave-uniform reads become scalar loads, which
 // are counted apart from vector memory, so reading them never waits for
@@ -54,6 +113,14 @@ TNC_HD inline uint32_t pdep32(uint32_t x, uint32_t mask) {
 #else
 #define TNC_TBL
 #endif
+
+// Phase p of a pass table, read as four 32-bit words (one scalar load
+// when p is wave-uniform; byte fields read one by one would become vector
+// loads).
+TNC_HD inline DevPhase load_phase(const DevPhase* phases, int p) {
+  const uint4 w = ((const TNC_TBL uint4*)phases)[p];
+  return __builtin_bit_cast(DevPhase, w);
+}
 
 // Register-resident complex64 entries of a thread: separate real and
 // imaginary float arrays (keeps every element promotable to a VGPR).
@@ -145,8 +212,8 @@ __device__ __attribute__((always_inline)) inline Regs<R> op_reg_mfma(Regs<R> v, 
 
 template <int R, bool MF>
 struct PhaseCtx {
-  const TNC_TBL DevOp* __restrict__ ops;
-  const TNC_TBL float* __restrict__ mats;
+  const TNC_TBL float* __restrict__ rm;  // the tile's batch: resolved matrices, 16 floats per op
+  const TNC_TBL DevOp* __restrict__ ops;  // matrix-core form only (variants picked per op)
   const float4* __restrict__ mrows;
   const uint8_t* bits;  // output bits, one byte per qubit per batch
   size_t xpos;          // byte offset of this tile's batch in `bits`
@@ -199,16 +266,16 @@ TNC_HD inline float uniform_value(float x) {
 template <int R, int B, int N, bool MF>
 TNC_HD inline Regs<R> stair_rest(Regs<R> v, const PhaseCtx<R, MF>& c, int op_begin) {
   if constexpr (B < N) {
-    const DevOp op = c.ops[op_begin + B];
-    const int var = op_variant(op, c);
 #if defined(__HIP_DEVICE_COMPILE__)
     if constexpr (MF) {
+      const DevOp op = c.ops[op_begin + B];
+      const int var = op_variant(op, c);
       const float4* rows = c.mrows + ((size_t)op.mat * 4 + var) * 8;
       v = op_reg_mfma<R, B, B - 1>(v, rows[c.lane & 3], rows[4 + (c.lane & 3)]);
       return stair_rest<R, B + 1, N, MF>(v, c, op_begin);
     }
 #endif
-    v = op_reg<R, B, B - 1>(v, c.mats + ((size_t)op.mat * 4 + var) * 16);
+    v = op_reg<R, B, B - 1>(v, c.rm + (size_t)(op_begin + B) * 16);
     return stair_rest<R, B + 1, N, MF>(v, c, op_begin);
   }
   return v;
@@ -220,20 +287,25 @@ TNC_HD inline Regs<R> stair(Regs<R> v, const DevPhase& P, const PhaseCtx<R, MF>&
   if (P.first_dup) {
     v = op_dup<R, 0>(v);
   } else {
-    const DevOp op = c.ops[P.op_begin];
-    const int var = op_variant(op, c);
-    const TNC_TBL float* m = c.mats + ((size_t)op.mat * 4 + var) * 16;
-    if (op.cloc < 0) {
+    const TNC_TBL float* m = c.rm + (size_t)P.op_begin * 16;
+    if (P.cloc0 < 0) {
       v = op_sel<R, 0>(v, m);
     } else {
-      const bool hi = (c.tb >> op.cloc) & 1u;
+      const bool hi = (c.tb >> P.cloc0) & 1u;
       if (c.uniform) {
         // thread-controlled: pick the values per thread from the
         // wave-uniform pair of matrices (a per-thread address would need
         // vector loads)
-        float k[8];
+        // (both matrices pinned first, unconditionally: a pinning under
+        // the per-lane condition would become divergent branches)
+        float lo[8], up[8], k[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) k[e] = hi ? uniform_value(m[8 + e]) : uniform_value(m[e]);
+        for (int e = 0; e < 8; ++e) {
+          lo[e] = uniform_value(m[e]);
+          up[e] = uniform_value(m[8 + e]);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) k[e] = hi ? up[e] : lo[e];
         v = op_sel<R, 0>(v, static_cast<const float*>(k));
       } else {
         v = op_sel<R, 0>(v, m + 8 * int(hi));
@@ -296,6 +368,8 @@ TNC_HD inline void phase_dispatch(char* region, const DevPhase& P, const PhaseCt
 
 // Launchers (kernels.hip).
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
+hipError_t launch_init16(const InitArgs& a, hipStream_t s);
+hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int R, hipStream_t s);
 hipError_t launch_late(const LateArgs& a, bool in_c64, hipStream_t s);
 hipError_t launch_late_ops(const LateOpsArgs& a, hipStream_t s);

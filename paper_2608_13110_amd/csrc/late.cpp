@@ -49,7 +49,6 @@ int bitrev(int b, int k) {
 }  // namespace
 
 int build_late(const Plan& p, const Schedule& s, LatePlan* out, std::string* err) {
-  (void)p;
   const auto& L = s.late;
   if (L.empty()) {
     if (err) *err = "empty late program";
@@ -68,11 +67,20 @@ int build_late(const Plan& p, const Schedule& s, LatePlan* out, std::string* err
   for (int i = 0; i < nbody; ++i)
     if (L[i].kind == L_REMOVE) rpos.push_back(i);
   const int nrem = int(rpos.size());
-  // k >= 1: fold up to 3 removals (host cost O(2^(3k+j1)), output 2^(m-j1)
-  // complex128 per batch); k = 0: up to 12 (the state is one qubit).
-  const int j1 = k == 0 ? std::min(nrem, 12) : std::min(nrem, k <= 8 ? 3 : 1);
+  // k = 0: fold up to 12 removals (the state is one qubit).  k >= 1: folding
+  // j removals costs O(2^(3k+j)) on the host and shrinks the first launch's
+  // FP64 output to 2^(m-j) rows; worth it for large tensors only.  With no
+  // removal folded, the join matrix is Z_early itself and every late op runs
+  // on the device.
+  int j1;
+  if (k == 0) {
+    j1 = std::min(nrem, 12);
+  } else {
+    const int want = p.opt.late_fold == 0 ? (s.m_fix >= 26 ? 3 : 0) : std::max(0, p.opt.late_fold);
+    j1 = std::min(nrem, std::min(want, k <= 8 ? 3 : 1));
+  }
   const bool first_final = j1 == nrem;
-  const int first_end = first_final ? nbody : rpos[j1 - 1] + 1;
+  const int first_end = first_final ? nbody : (j1 == 0 ? 0 : rpos[j1 - 1] + 1);
 
   // P_u for each assignment u of the folded removals
   const int nu = 1 << j1;

@@ -118,6 +118,7 @@ struct Options {
   int low_bits = 4;         // contiguous low slots kept in every non-bottom tile
   int math = 0;             // 0: vector ALU updates; 1: register-controlled updates on the matrix cores
   int pipeline = 0;         // 1: persistent, prefetching pass blocks where a block holds one tile
+  int late_fold = 0;        // removals folded into the join launch (0 auto, -1 none, 1..3)
 };
 
 // Everything that depends on k (the number of open output legs).

@@ -1,0 +1,594 @@
+// Continuous-batching request loop for amplitude requests of mixed shape.
+//
+// Requests (circuit, bitstring batch, open legs k, storage) arrive through
+// tnc_server_submit at any time.  A pool of planner threads turns each
+// circuit into a plan (cached by a hash of the circuit, with tile options
+// picked per width by the autotuner) and uploads its tables; the dispatcher
+// thread admits prepared requests onto free HIP streams as soon as the
+// device arena has room for their footprint (tensor workspace, bits,
+// output), so requests that arrive while others run start as soon as a
+// stream and memory free up, and the work of different requests overlaps on
+// the device.  Small requests (boundary bits <= small_bits) run from a
+// per-stream region as captured HIP graphs, replayed when the same plan
+// comes back.  Batches of a plan share only the read-only plan (Sec. 5.3:
+// the batches of one circuit differ only in their output bits).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "tnc.h"
+
+namespace tnc {
+
+int set_error_message(int code, const std::string& msg);  // tnc_api.cpp
+
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// First-fit allocator over [0, size) in 256-byte units, with coalescing.
+class Arena {
+ public:
+  explicit Arena(uint64_t size = 0) { if (size) free_[0] = size; }
+  // Returns the offset or UINT64_MAX.
+  uint64_t alloc(uint64_t bytes) {
+    bytes = (bytes + 255) & ~uint64_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      const uint64_t off = it->first, len = it->second;
+      free_.erase(it);
+      if (len > bytes) free_[off + bytes] = len - bytes;
+      used_[off] = bytes;
+      return off;
+    }
+    return UINT64_MAX;
+  }
+  void release(uint64_t off) {
+    auto u = used_.find(off);
+    if (u == used_.end()) return;
+    uint64_t len = u->second;
+    used_.erase(u);
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + len == next->first) {
+      len += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += len;
+        return;
+      }
+    }
+    free_[off] = len;
+  }
+  uint64_t largest() const {
+    uint64_t m = 0;
+    for (const auto& f : free_) m = std::max(m, f.second);
+    return m;
+  }
+
+ private:
+  std::map<uint64_t, uint64_t> free_, used_;
+};
+
+struct CircuitKey {
+  int32_t n = 0, d = 0;
+  std::vector<tnc_c128> one;
+  std::vector<tnc_gate2> gates;
+  bool operator==(const CircuitKey& o) const {
+    return n == o.n && d == o.d && one.size() == o.one.size() && gates.size() == o.gates.size() &&
+           std::memcmp(one.data(), o.one.data(), one.size() * sizeof(tnc_c128)) == 0 &&
+           std::memcmp(gates.data(), o.gates.data(), gates.size() * sizeof(tnc_gate2)) == 0;
+  }
+};
+
+struct CachedPlan {
+  CircuitKey key;
+  tnc_plan_t plan = nullptr;
+  int h = 0;
+  int ready = 0;  // 0 building, 1 ready, -1 failed
+  int rc = 0;
+};
+
+enum ReqState { R_PLANNING = 0, R_READY = 1, R_RUNNING = 2, R_DONE = 3 };
+
+struct Request {
+  uint64_t id = 0;
+  CircuitKey circuit;
+  uint64_t hash = 0;
+  std::shared_ptr<CachedPlan> cp;
+  int32_t nb = 0, k = 0, storage = 0;
+  std::vector<uint8_t> bits;
+  tnc_c128* out = nullptr;
+  uint64_t ws_bytes = 0, footprint = 0;
+  int h = 0;
+  int state = R_PLANNING;
+  int rc = 0;
+  std::string err;  // what failed, for tnc_last_error of the waiting thread
+  int bypassed = 0;
+  bool small = false;
+  int64_t t_submit = 0, t_ready = 0, t_admit = 0, t_done = 0;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  std::shared_ptr<Request> req;
+  uint64_t off = UINT64_MAX;      // arena block of a large request
+  uint64_t small_off = 0;         // this slot's fixed region for small requests
+  uint8_t* h_bits = nullptr;      // pinned staging
+  tnc_c128* h_out = nullptr;
+  size_t cap_bits = 0, cap_out = 0;
+};
+
+struct GraphKey {
+  tnc_plan_t plan;
+  int k, nb, storage, slot;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(plan, k, nb, storage, slot) < std::tie(o.plan, o.k, o.nb, o.storage, o.slot);
+  }
+};
+
+}  // namespace
+
+struct ServerImpl {
+  tnc_server_options opt{};
+  int device = 0;
+  char* arena_base = nullptr;
+  uint64_t arena_bytes = 0, small_region = 0;
+  Arena arena;
+  std::vector<Slot> slots;
+  std::map<int, tnc_options> tuning;  // boundary bits -> tile options
+
+  std::mutex mu;
+  std::condition_variable cv_plan, cv_dispatch, cv_done;
+  std::deque<std::shared_ptr<Request>> to_plan, ready;
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> reqs;
+  std::unordered_multimap<uint64_t, std::shared_ptr<CachedPlan>> plans;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  uint64_t next_id = 1;
+  bool stop = false;
+  std::vector<std::thread> planners;
+  std::thread dispatcher;
+
+  // statistics
+  uint64_t n_done = 0, n_graph_launch = 0, n_graph_capture = 0, n_plain = 0, plan_hits = 0, plan_misses = 0;
+  int64_t first_submit = 0, last_done = 0;
+  std::vector<double> lat_ms;
+  int max_inflight = 0;
+
+  tnc_options options_for(int h) const {
+    tnc_options o{};
+    auto it = tuning.find(h);
+    if (it != tuning.end()) o = it->second;
+    return o;
+  }
+
+  void planner_loop();
+  void dispatcher_loop();
+  int launch(Slot& s, int si, Request& r);
+  void finish(Slot& s, bool ok);
+};
+
+namespace {
+
+int ceil_half(int d) { return (d + 1) / 2; }
+
+void ensure_pinned(Slot& s, size_t bits, size_t outs) {
+  if (bits > s.cap_bits) {
+    if (s.h_bits) (void)hipHostFree(s.h_bits);
+    s.h_bits = nullptr;
+    s.cap_bits = 0;
+    if (hipHostMalloc((void**)&s.h_bits, bits) == hipSuccess) s.cap_bits = bits;
+  }
+  if (outs > s.cap_out) {
+    if (s.h_out) (void)hipHostFree(s.h_out);
+    s.h_out = nullptr;
+    s.cap_out = 0;
+    if (hipHostMalloc((void**)&s.h_out, outs * sizeof(tnc_c128)) == hipSuccess) s.cap_out = outs;
+  }
+}
+
+}  // namespace
+
+void ServerImpl::planner_loop() {
+  (void)hipSetDevice(device);
+  for (;;) {
+    std::shared_ptr<Request> r;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_plan.wait(lk, [&] { return stop || !to_plan.empty(); });
+      if (stop && to_plan.empty()) return;
+      r = to_plan.front();
+      to_plan.pop_front();
+    }
+    // find or build the plan (one builder per circuit; others wait)
+    std::shared_ptr<CachedPlan> cp;
+    bool build = false;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      auto range = plans.equal_range(r->hash);
+      for (auto it = range.first; it != range.second; ++it)
+        if (it->second->key == r->circuit) cp = it->second;
+      if (!cp) {
+        cp = std::make_shared<CachedPlan>();
+        cp->key = r->circuit;
+        plans.emplace(r->hash, cp);
+        build = true;
+        ++plan_misses;
+      } else {
+        ++plan_hits;
+      }
+    }
+    int rc = 0;
+    if (build) {
+      tnc_plan_t p = nullptr;
+      const tnc_options o = options_for(ceil_half(r->circuit.d));
+      rc = tnc_plan(r->circuit.n, r->circuit.d, r->circuit.one.data(), (int32_t)r->circuit.gates.size(),
+                    r->circuit.gates.data(), &o, &p);
+      std::lock_guard<std::mutex> lk(mu);
+      cp->plan = p;
+      cp->rc = rc;
+      cp->ready = rc ? -1 : 1;
+      cv_done.notify_all();
+    } else {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_done.wait(lk, [&] { return cp->ready != 0; });
+      rc = cp->rc;
+    }
+    tnc_info info{};
+    uint64_t ws = 0;
+    if (!rc) rc = tnc_plan_info(cp->plan, r->k, &info);
+    if (!rc) rc = tnc_prepare(cp->plan, r->k);
+    if (!rc) rc = tnc_workspace_bytes(cp->plan, r->k, r->nb, r->storage, &ws);
+    const std::string perr = rc ? std::string("serving: planning: ") + tnc_last_error() : std::string();
+    std::lock_guard<std::mutex> lk(mu);
+    r->err = perr;
+    r->cp = cp;
+    r->rc = rc;
+    r->h = info.boundary_bits;
+    r->ws_bytes = ws;
+    const uint64_t io = (((uint64_t)r->nb * r->circuit.n + 255) & ~uint64_t(255)) +
+                        (((uint64_t)r->nb << r->k) * sizeof(tnc_c128) + 255) / 256 * 256;
+    r->footprint = ws + io;
+    r->small = opt.small_bits > 0 && r->h <= opt.small_bits && r->footprint <= small_region;
+    r->t_ready = now_ns();
+    if (rc) {
+      r->state = R_DONE;
+      r->t_done = r->t_ready;
+      cv_done.notify_all();
+    } else {
+      r->state = R_READY;
+      ready.push_back(r);
+      cv_dispatch.notify_one();
+    }
+  }
+}
+
+int ServerImpl::launch(Slot& s, int si, Request& r) {
+  auto fail = [&](int code, const char* what, hipError_t e) {
+    r.err = std::string("serving: ") + what + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : "");
+    return code;
+  };
+  const size_t nbits = (size_t)r.nb * r.circuit.n, nout = (size_t)r.nb << r.k;
+  ensure_pinned(s, nbits, nout);
+  if (s.cap_bits < nbits || s.cap_out < nout) return fail(TNC_E_NOMEM, "pinned staging allocation", hipSuccess);
+  const uint64_t base = r.small ? s.small_off : s.off;
+  char* ws = arena_base + base;
+  uint8_t* d_bits = reinterpret_cast<uint8_t*>(ws + r.ws_bytes);
+  tnc_c128* d_out = reinterpret_cast<tnc_c128*>(ws + r.ws_bytes + (((uint64_t)nbits + 255) & ~uint64_t(255)));
+  std::memcpy(s.h_bits, r.bits.data(), nbits);
+  hipError_t e = hipMemcpyAsync(d_bits, s.h_bits, nbits, hipMemcpyHostToDevice, s.stream);
+  if (e != hipSuccess) return fail(TNC_E_DEVICE, "bits upload", e);
+  int rc = TNC_OK;
+  if (r.small) {
+    const GraphKey key{r.cp->plan, r.k, r.nb, r.storage, si};
+    auto it = graphs.find(key);
+    if (it == graphs.end() && graphs.size() < (size_t)std::max(0, opt.max_graphs)) {
+      hipGraph_t g = nullptr;
+      hipGraphExec_t ge = nullptr;
+      e = hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return fail(TNC_E_DEVICE, "begin capture", e);
+      rc = tnc_amplitudes(r.cp->plan, r.nb, d_bits, r.k, r.storage, d_out, ws, r.ws_bytes, s.stream);
+      const hipError_t e2 = hipStreamEndCapture(s.stream, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(rc, "captured launch sequence", hipSuccess);
+      }
+      if (e2 != hipSuccess) return fail(TNC_E_DEVICE, "end capture", e2);
+      e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(TNC_E_DEVICE, "graph instantiate", e);
+      it = graphs.emplace(key, ge).first;
+      ++n_graph_capture;
+    }
+    if (it != graphs.end()) {
+      e = hipGraphLaunch(it->second, s.stream);
+      if (e != hipSuccess) return fail(TNC_E_DEVICE, "graph launch", e);
+      ++n_graph_launch;
+    } else {
+      rc = tnc_amplitudes(r.cp->plan, r.nb, d_bits, r.k, r.storage, d_out, ws, r.ws_bytes, s.stream);
+      if (rc) return fail(rc, "launch sequence", hipSuccess);
+      ++n_plain;
+    }
+  } else {
+    rc = tnc_amplitudes(r.cp->plan, r.nb, d_bits, r.k, r.storage, d_out, ws, r.ws_bytes, s.stream);
+    if (rc) return fail(rc, "launch sequence", hipSuccess);
+    ++n_plain;
+  }
+  e = hipMemcpyAsync(s.h_out, d_out, nout * sizeof(tnc_c128), hipMemcpyDeviceToHost, s.stream);
+  if (e != hipSuccess) return fail(TNC_E_DEVICE, "result download", e);
+  e = hipEventRecord(s.done, s.stream);
+  if (e != hipSuccess) return fail(TNC_E_DEVICE, "completion event", e);
+  return TNC_OK;
+}
+
+void ServerImpl::finish(Slot& s, bool ok) {
+  Request& r = *s.req;
+  if (ok && r.out) std::memcpy(r.out, s.h_out, ((size_t)r.nb << r.k) * sizeof(tnc_c128));
+  if (!r.small && s.off != UINT64_MAX) arena.release(s.off);
+  s.off = UINT64_MAX;
+  r.t_done = now_ns();
+  r.state = R_DONE;
+  ++n_done;
+  last_done = r.t_done;
+  lat_ms.push_back((r.t_done - r.t_submit) * 1e-6);
+  s.req.reset();
+}
+
+void ServerImpl::dispatcher_loop() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    bool progressed = false;
+    // completions
+    int inflight = 0;
+    for (Slot& s : slots) {
+      if (!s.req) continue;
+      const hipError_t q = hipEventQuery(s.done);
+      if (q == hipErrorNotReady) {
+        ++inflight;
+        continue;
+      }
+      if (q != hipSuccess) {
+        s.req->rc = TNC_E_DEVICE;
+        s.req->err = std::string("serving: request execution: ") + hipGetErrorString(q);
+      }
+      finish(s, q == hipSuccess);
+      progressed = true;
+    }
+    if (progressed) cv_done.notify_all();
+    // admissions: oldest first; a request that does not fit lets younger
+    // ones pass at most 16 times, then the queue waits for it
+    for (size_t si = 0; si < slots.size() && !ready.empty(); ++si) {
+      Slot& s = slots[si];
+      if (s.req) continue;
+      for (auto it = ready.begin(); it != ready.end(); ++it) {
+        Request& r = **it;
+        bool fits = r.small;
+        if (!fits) {
+          const uint64_t off = arena.alloc(r.footprint);
+          if (off != UINT64_MAX) {
+            s.off = off;
+            fits = true;
+          }
+        }
+        if (!fits) {
+          if (++r.bypassed > 16) break;
+          continue;
+        }
+        s.req = *it;
+        ready.erase(it);
+        r.state = R_RUNNING;
+        r.t_admit = now_ns();
+        const int rc = launch(s, (int)si, r);
+        if (rc) {
+          r.rc = rc;
+          finish(s, false);
+          cv_done.notify_all();
+        } else {
+          ++inflight;
+        }
+        progressed = true;
+        break;
+      }
+    }
+    max_inflight = std::max(max_inflight, inflight);
+    if (stop && ready.empty() && to_plan.empty() && inflight == 0) {
+      bool planning = false;
+      for (auto& kv : reqs)
+        if (kv.second->state == R_PLANNING) planning = true;
+      if (!planning) return;
+    }
+    if (!progressed) cv_dispatch.wait_for(lk, std::chrono::microseconds(inflight ? 20 : 2000));
+  }
+}
+
+}  // namespace tnc
+
+using namespace tnc;
+
+struct tnc_server_s {
+  std::unique_ptr<ServerImpl> impl;
+};
+
+extern "C" {
+
+int tnc_server_create(const tnc_server_options* opt, tnc_server_t* out) {
+  if (!out) return TNC_E_INVALID;
+  *out = nullptr;
+  auto S = std::make_unique<ServerImpl>();
+  if (opt) S->opt = *opt;
+  tnc_server_options& o = S->opt;
+  if (o.n_streams <= 0) o.n_streams = 4;
+  if (o.n_planners <= 0) o.n_planners = 4;
+  if (o.max_graphs <= 0) o.max_graphs = 256;
+  if (o.small_bits < 0 || o.small_bits > 24 || o.n_streams > 16 || o.n_planners > 16 || o.arena_bytes == 0)
+    return TNC_E_INVALID;
+  if (hipGetDevice(&S->device) != hipSuccess) return TNC_E_DEVICE;
+  // per-stream regions for small requests: tensor + 16-bit scales + tables
+  // + late buffers + bits + output of one batch up to small_bits, k <= 10
+  S->small_region = o.small_bits > 0 ? (((uint64_t)8 << o.small_bits) * 3 / 2 + (16ull << 20)) : 0;
+  const uint64_t small_total = S->small_region * (uint64_t)o.n_streams;
+  if (small_total >= o.arena_bytes) return TNC_E_INVALID;
+  if (hipMalloc((void**)&S->arena_base, o.arena_bytes) != hipSuccess) return TNC_E_NOMEM;
+  S->arena_bytes = o.arena_bytes;
+  S->arena = Arena(o.arena_bytes - small_total);
+  S->slots.resize(o.n_streams);
+  for (int i = 0; i < o.n_streams; ++i) {
+    Slot& s = S->slots[i];
+    if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
+      return TNC_E_DEVICE;
+    s.small_off = o.arena_bytes - small_total + (uint64_t)i * S->small_region;
+  }
+  ServerImpl* raw = S.get();
+  for (int i = 0; i < o.n_planners; ++i) S->planners.emplace_back([raw] { raw->planner_loop(); });
+  S->dispatcher = std::thread([raw] { raw->dispatcher_loop(); });
+  *out = new tnc_server_s{std::move(S)};
+  return TNC_OK;
+}
+
+int tnc_server_set_tuning(tnc_server_t sv, int32_t boundary_bits, const tnc_options* o) {
+  if (!sv || !o || boundary_bits < 1 || boundary_bits > 40) return TNC_E_INVALID;
+  std::lock_guard<std::mutex> lk(sv->impl->mu);
+  sv->impl->tuning[boundary_bits] = *o;
+  return TNC_OK;
+}
+
+int tnc_server_submit(tnc_server_t sv, int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2,
+                      const tnc_gate2* gates, int32_t n_batches, const uint8_t* bits, int32_t k, int32_t storage,
+                      tnc_c128* out, uint64_t* id) {
+  if (!sv || !one_qubit || (n_gate2 > 0 && !gates) || n_gate2 < 0 || n < 2 || d < 2 || n_batches < 1 ||
+      !bits || !out || !id || k < 0 || (int64_t)n * (d + 1) > (1 << 24))
+    return TNC_E_INVALID;
+  ServerImpl& S = *sv->impl;
+  auto r = std::make_shared<Request>();
+  r->circuit.n = n;
+  r->circuit.d = d;
+  r->circuit.one.assign(one_qubit, one_qubit + (size_t)(d + 1) * n * 4);
+  r->circuit.gates.assign(gates, gates + n_gate2);
+  for (tnc_gate2& g : r->circuit.gates) {
+    g.reserved = 0;
+    if (g.kind == TNC_GATE_CZ) std::memset(g.m, 0, sizeof(g.m));
+  }
+  uint64_t h = 1469598103934665603ull;
+  h = fnv1a(h, &n, sizeof(n));
+  h = fnv1a(h, &d, sizeof(d));
+  h = fnv1a(h, r->circuit.one.data(), r->circuit.one.size() * sizeof(tnc_c128));
+  h = fnv1a(h, r->circuit.gates.data(), r->circuit.gates.size() * sizeof(tnc_gate2));
+  r->hash = h;
+  r->nb = n_batches;
+  r->k = k;
+  r->storage = storage;
+  r->bits.assign(bits, bits + (size_t)n_batches * n);
+  r->out = out;
+  r->t_submit = now_ns();
+  std::lock_guard<std::mutex> lk(S.mu);
+  if (S.stop) return TNC_E_INVALID;
+  r->id = S.next_id++;
+  if (!S.first_submit) S.first_submit = r->t_submit;
+  S.reqs[r->id] = r;
+  S.to_plan.push_back(r);
+  S.cv_plan.notify_one();
+  *id = r->id;
+  return TNC_OK;
+}
+
+int tnc_server_wait(tnc_server_t sv, uint64_t id, tnc_request_stats* st) {
+  if (!sv) return TNC_E_INVALID;
+  ServerImpl& S = *sv->impl;
+  std::unique_lock<std::mutex> lk(S.mu);
+  auto it = S.reqs.find(id);
+  if (it == S.reqs.end()) return TNC_E_INVALID;
+  std::shared_ptr<Request> r = it->second;
+  S.cv_done.wait(lk, [&] { return r->state == R_DONE; });
+  if (st) {
+    st->queue_ms = (r->t_admit ? r->t_admit - r->t_submit : 0) * 1e-6;
+    st->plan_ms = (r->t_ready - r->t_submit) * 1e-6;
+    st->run_ms = (r->t_admit ? r->t_done - r->t_admit : 0) * 1e-6;
+    st->total_ms = (r->t_done - r->t_submit) * 1e-6;
+    st->boundary_bits = r->h;
+    st->graph = r->small ? 1 : 0;
+  }
+  const int rc = r->rc;
+  if (rc) set_error_message(rc, r->err);
+  S.reqs.erase(it);
+  return rc;
+}
+
+int tnc_server_summary(tnc_server_t sv, tnc_server_stats* st) {
+  if (!sv || !st) return TNC_E_INVALID;
+  ServerImpl& S = *sv->impl;
+  std::lock_guard<std::mutex> lk(S.mu);
+  std::memset(st, 0, sizeof(*st));
+  st->completed = (int64_t)S.n_done;
+  st->graph_launches = (int64_t)S.n_graph_launch;
+  st->graph_captures = (int64_t)S.n_graph_capture;
+  st->plain_launches = (int64_t)S.n_plain;
+  st->plan_cache_hits = (int64_t)S.plan_hits;
+  st->plan_cache_misses = (int64_t)S.plan_misses;
+  st->max_inflight = S.max_inflight;
+  std::vector<double> l = S.lat_ms;
+  std::sort(l.begin(), l.end());
+  if (!l.empty()) {
+    auto q = [&](double f) { return l[std::min(l.size() - 1, (size_t)(f * (l.size() - 1) + 0.5))]; };
+    st->latency_ms_p50 = q(0.5);
+    st->latency_ms_p99 = q(0.99);
+    st->latency_ms_max = l.back();
+  }
+  if (S.last_done > S.first_submit) st->elapsed_s = (S.last_done - S.first_submit) * 1e-9;
+  return TNC_OK;
+}
+
+void tnc_server_destroy(tnc_server_t sv) {
+  if (!sv) return;
+  ServerImpl& S = *sv->impl;
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.stop = true;
+  }
+  S.cv_plan.notify_all();
+  S.cv_dispatch.notify_all();
+  for (std::thread& t : S.planners) t.join();
+  S.dispatcher.join();
+  for (auto& g : S.graphs) (void)hipGraphExecDestroy(g.second);
+  for (Slot& s : S.slots) {
+    if (s.stream) (void)hipStreamSynchronize(s.stream);
+    if (s.done) (void)hipEventDestroy(s.done);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+    if (s.h_bits) (void)hipHostFree(s.h_bits);
+    if (s.h_out) (void)hipHostFree(s.h_out);
+  }
+  for (auto& kv : S.plans)
+    if (kv.second->plan) tnc_release(kv.second->plan);
+  if (S.arena_base) (void)hipFree(S.arena_base);
+  delete sv;
+}
+
+}  // extern "C"

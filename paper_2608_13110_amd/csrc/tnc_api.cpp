@@ -20,14 +20,18 @@ struct tnc_plan_s {
 };
 
 namespace tnc {
-namespace {
 
 thread_local std::string g_err;
 
-int set_err(int code, const std::string& msg) {
+// The calling thread's last error message (also used by the serving loop).
+int set_error_message(int code, const std::string& msg) {
   g_err = msg;
   return code;
 }
+
+namespace {
+
+int set_err(int code, const std::string& msg) { return set_error_message(code, msg); }
 
 int hip_err(hipError_t e, const char* what) {
   return set_err(TNC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -52,7 +56,6 @@ struct HostTables {
   std::vector<double2> seg;
   LatePlan late;
   std::vector<LateOpDev> prog;
-  uint64_t bytes_B = 0;      // per batch
   uint64_t bytes_late[2] = {0, 0};
 };
 
@@ -105,6 +108,7 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
       dp.op_begin = pp.op_begin;
       dp.n_ops = (int8_t)nops;
       dp.first_dup = s.ops[pp.op_begin].kind == OP_DUP ? 1 : 0;
+      dp.cloc0 = -1;
       for (int b = 0; b < R; ++b) {
         if (pp.reg[b] < 0 || pp.reg[b] >= ps.w.tile_bits()) return fail_t("bad register map");
         for (int c = 0; c < b; ++c)
@@ -126,6 +130,7 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
             for (int q = 0; q < R; ++q)
               if (pp.reg[q] == lc) return fail_t("first op control held in registers");
             d.cloc = (int8_t)lc;
+            t->phases.back().cloc0 = (int8_t)lc;
           }
         } else {
           if (op.kind != OP_CU || op.control < 0 || !ps.w.contains(op.control) ||
@@ -155,7 +160,6 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
     for (size_t e = 0; e < lo.m.size() && e < 16; ++e) d.m[e] = make_double2(lo.m[e].real(), lo.m[e].imag());
     t->prog.push_back(d);
   }
-  t->bytes_B = align256((uint64_t)8 << p.h);
   // late buffers: first output -> buffer 0, ops launch i -> buffer (i+1)&1
   const LateFirst& F = t->late.first;
   if (!F.final) t->bytes_late[0] = align256((uint64_t)F.M * F.N * 16);
@@ -167,6 +171,54 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
     slot = std::max(slot, bytes);
   }
   return 0;
+}
+
+// Per-batch workspace for a storage mode: the boundary tensor, two arrays of
+// block scales (16-bit storage: read by a launch / written by it, swapped
+// after every writer), the batch's resolved update matrices and the two
+// late-phase buffers.
+struct BatchLayout {
+  uint64_t tensor = 0, scales = 0, rmats = 0, late0 = 0, late1 = 0;
+  uint64_t per_batch() const { return tensor + 2 * scales + rmats + late0 + late1; }
+};
+
+bool is_s16(int storage) { return storage == TNC_STORE_F16_BLOCKSCALE || storage == TNC_STORE_BF16_BLOCKSCALE; }
+
+// Block-scale layout of the row-0 build-up (blocks of 2^min(12, h)
+// consecutive entries) and of a pass (its tiles, split in 4096-entry blocks).
+ScaleMap init_map(const Plan& p) {
+  const int b = std::min(12, p.h);
+  return ScaleMap{0, 0, b, b, b};
+}
+
+ScaleMap pass_map(const PassHost& ph) {
+  const int T = ph.w.tile_bits();
+  return ScaleMap{ph.w.lo_bits, ph.w.win_lo, ph.w.win_len, T, std::min(12, T)};
+}
+
+BatchLayout batch_layout(const Plan& p, const HostTables& t, int storage) {
+  BatchLayout L;
+  const bool s16 = is_s16(storage);
+  L.tensor = align256((uint64_t)(s16 ? 4 : 8) << p.h);
+  if (s16) {
+    int blk = std::min(12, p.h);
+    for (const PassHost& ph : t.passes) blk = std::min(blk, std::min(12, ph.w.tile_bits()));
+    L.scales = align256((uint64_t)4 << (p.h - blk));
+  }
+  L.rmats = align256((uint64_t)t.ops.size() * 16 * sizeof(float));
+  L.late0 = t.bytes_late[0];
+  L.late1 = t.bytes_late[1];
+  return L;
+}
+
+// 16-bit storage reads 2 or 4 consecutive entries per access: every tile
+// with a split window must keep at least 2 contiguous low slots.
+int check_storage(const HostTables& t, int storage) {
+  if (storage != TNC_STORE_C64 && !is_s16(storage)) return set_err(TNC_E_INVALID, "unknown storage mode");
+  if (is_s16(storage))
+    for (const PassHost& ph : t.passes)
+      if (ph.w.lo_bits == 1) return set_err(TNC_E_INVALID, "16-bit storage needs low_bits >= 2");
+  return TNC_OK;
 }
 
 // Device copy of the tables for one (k, device).
@@ -190,7 +242,6 @@ struct DevSched {
       (void)hipSetDevice(prev);
     }
   }
-  uint64_t per_batch() const { return host.bytes_B + host.bytes_late[0] + host.bytes_late[1]; }
 };
 
 struct PlanDevice {
@@ -314,8 +365,6 @@ PassArgs pass_args(const Plan& p, const PassHost& ph, const DevPhase* phases, co
   a.mrows = mrows;
   a.mfma = p.opt.math == 1 ? 1 : 0;
   a.pipeline = p.opt.pipeline;
-  a.op_begin = ph.op_begin;
-  a.n_ops = ph.op_end - ph.op_begin;
   a.B = B;
   a.bits = bits;
   a.n_phases = ph.n_phases;
@@ -375,46 +424,101 @@ LateOpsArgs ops_args(const Plan& p, const HostTables& t, const LateOpsLaunch& ln
   return a;
 }
 
-int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k, tnc_c128* d_out, void* ws,
-               uint64_t ws_bytes, hipStream_t stream) {
+int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k, int storage, tnc_c128* d_out,
+               void* ws, uint64_t ws_bytes, hipStream_t stream) {
   const HostTables& t = ds.host;
-  const uint64_t per = ds.per_batch();
+  int rc = check_storage(t, storage);
+  if (rc) return rc;
+  const bool s16 = is_s16(storage);
+  const BatchLayout L = batch_layout(p, t, storage);
+  const uint64_t per = L.per_batch();
   const uint64_t fit = ws_bytes / per;
   if (fit < 1) return set_err(TNC_E_NOMEM, "workspace smaller than one batch");
   const int chunk = (int)std::min<uint64_t>(fit, (uint64_t)std::min(nb_total, 65535));
   char* base = static_cast<char*>(ws);
+  const long long sstride = (long long)(L.scales / 4);
   for (int b0 = 0; b0 < nb_total; b0 += chunk) {
     const int nb = std::min(chunk, nb_total - b0);
-    float2* B = reinterpret_cast<float2*>(base);
-    double2* L0 = reinterpret_cast<double2*>(base + t.bytes_B * (uint64_t)nb);
-    double2* L1 = reinterpret_cast<double2*>(base + (t.bytes_B + t.bytes_late[0]) * (uint64_t)nb);
+    char* q = base;
+    float2* B = reinterpret_cast<float2*>(q);
+    q += L.tensor * nb;
+    float* sc[2] = {reinterpret_cast<float*>(q), reinterpret_cast<float*>(q + L.scales * nb)};
+    q += 2 * L.scales * nb;
+    float* rmats = reinterpret_cast<float*>(q);
+    const long long rstride = (long long)(L.rmats / 4);
+    q += L.rmats * nb;
+    double2* L0 = reinterpret_cast<double2*>(q);
+    double2* L1 = reinterpret_cast<double2*>(q + L.late0 * nb);
     const uint8_t* bits = d_bits + (size_t)b0 * p.n;
     double2* out = reinterpret_cast<double2*>(d_out) + ((size_t)b0 << k);
-    hipError_t e = timed(0, 0.0, stream, [&] { return launch_init(init_args(p, t, B, bits, nb, ds.d_seg), stream); });
+    InitArgs ia = init_args(p, t, B, bits, nb, ds.d_seg);
+    hipError_t e;
+    if (s16) {
+      ia.store = storage;
+      ia.scale_out = sc[0];
+      ia.scale_stride = sstride;
+      ia.blk_bits = std::min(12, p.h);
+      e = timed(0, 0.0, stream, [&] { return launch_init16(ia, stream); });
+    } else {
+      e = timed(0, 0.0, stream, [&] { return launch_init(ia, stream); });
+    }
     if (e != hipSuccess) return hip_err(e, "init launch");
-    const double pass_bytes = 2.0 * 8.0 * (double)(1ull << p.h) * nb;
+    ResolveArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.ops = ds.d_ops;
+    ra.mats = ds.d_mats;
+    ra.bits = bits;
+    ra.rmats = rmats;
+    ra.rstride = rstride;
+    ra.n_ops = (int)t.ops.size();
+    ra.n = p.n;
+    ra.n_batches = nb;
+    e = timed(0, 0.0, stream, [&] { return launch_resolve(ra, stream); });
+    if (e != hipSuccess) return hip_err(e, "resolve launch");
+    const double pass_bytes = 2.0 * (s16 ? 4.0 : 8.0) * (double)(1ull << p.h) * nb;
+    int cur = 0;
+    ScaleMap map = init_map(p);
     for (const PassHost& ph : t.passes) {
-      e = timed(1, pass_bytes, stream, [&] {
-        return launch_pass(pass_args(p, ph, ds.d_phases, ds.d_ops, ds.d_mats, ds.d_mrows, B, bits, nb), ph.R, stream);
-      });
+      PassArgs a = pass_args(p, ph, ds.d_phases, ds.d_ops, ds.d_mats, ds.d_mrows, B, bits, nb);
+      a.rmats = rmats;
+      a.rstride = rstride;
+      if (s16) {
+        a.store = storage;
+        a.scale_in = sc[cur];
+        a.scale_out = sc[cur ^ 1];
+        a.scale_stride = sstride;
+        a.in_map = map;
+      }
+      e = timed(1, pass_bytes, stream, [&] { return launch_pass(a, ph.R, stream); });
       if (e != hipSuccess) return hip_err(e, "pass launch");
+      if (s16) {
+        cur ^= 1;
+        map = pass_map(ph);
+      }
     }
     const LateFirst& F = t.late.first;
     double2* fout = F.final ? out : L0;
     const long long fstride = F.final ? (1ll << k) : (long long)(t.bytes_late[0] / 16);
-    e = timed(2, 0.0, stream, [&] { return launch_late(first_args(p, t, B, fout, fstride, ds.d_J, bits, nb), true, stream); });
+    LateArgs fa = first_args(p, t, B, fout, fstride, ds.d_J, bits, nb);
+    if (s16) {
+      fa.store = storage;
+      fa.scale_in = sc[cur];
+      fa.scale_stride = sstride;
+      fa.in_map = map;
+    }
+    e = timed(2, 0.0, stream, [&] { return launch_late(fa, true, stream); });
     if (e != hipSuccess) return hip_err(e, "late launch");
-    const double2* cur = L0;
+    const double2* curl = L0;
     long long cur_stride = fstride;
     for (size_t i = 0; i < t.late.ops.size(); ++i) {
       const LateOpsLaunch& ln = t.late.ops[i];
       double2* dst = ln.final ? out : ((i + 1) & 1 ? L1 : L0);
       const long long dstride = ln.final ? (1ll << k) : (long long)(t.bytes_late[(i + 1) & 1] / 16);
-      LateOpsArgs a = ops_args(p, t, ln, cur, dst, dstride, ds.d_prog, bits, nb, k);
+      LateOpsArgs a = ops_args(p, t, ln, curl, dst, dstride, ds.d_prog, bits, nb, k);
       a.in_batch_stride = cur_stride;
       e = timed(2, 0.0, stream, [&] { return launch_late_ops(a, stream); });
       if (e != hipSuccess) return hip_err(e, "late-ops launch");
-      cur = dst;
+      curl = dst;
       cur_stride = dstride;
     }
   }
@@ -422,7 +526,7 @@ int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k
 }
 
 // Host emulation of the whole device pipeline with the same tables.
-int emulate(Plan& p, int k, int nb, const uint8_t* bits, cd* out) {
+int emulate(Plan& p, int k, int nb, const uint8_t* bits, int storage, cd* out) {
   std::shared_ptr<Schedule> s;
   std::string err;
   int rc = get_schedule(p, k, &s, &err);
@@ -431,10 +535,19 @@ int emulate(Plan& p, int k, int nb, const uint8_t* bits, cd* out) {
   rc = build_tables(p, *s, &t, &err);
   if (rc) return set_err(rc, err);
   if (p.h > 24) return set_err(TNC_E_DOMAIN, "emulation limited to width 24");
+  if ((rc = check_storage(t, storage))) return rc;
+  const bool s16 = is_s16(storage);
   const size_t dim = size_t(1) << p.h;
+  // complex64 tensor, or (16-bit storage) the packed words in its first half
   std::vector<float2> B(dim * nb);
-  // init (same arithmetic as k_init, FP64 product rounded to FP32)
-  for (int b = 0; b < nb; ++b)
+  uint32_t* Bw = reinterpret_cast<uint32_t*>(B.data());
+  const BatchLayout L = batch_layout(p, t, storage);
+  const long long sstride = (long long)(L.scales / 4);
+  std::vector<float> sc[2] = {std::vector<float>((size_t)sstride * nb), std::vector<float>((size_t)sstride * nb)};
+  // init (same arithmetic as k_init / k_init16: FP64 product rounded to FP32)
+  const int ib = std::min(12, p.h);
+  for (int b = 0; b < nb; ++b) {
+    std::vector<float2> row(dim);
     for (size_t i = 0; i < dim; ++i) {
       cd v = 0;
       if (i < (size_t(1) << p.m0)) {
@@ -442,11 +555,65 @@ int emulate(Plan& p, int k, int nb, const uint8_t* bits, cd* out) {
         for (int j = 1; j < p.m0; ++j) v *= p.init_seg[j - 1](int(i >> j & 1), int(i >> (j - 1) & 1));
         v *= p.init_f[bits[(size_t)b * p.n]][int(i >> (p.m0 - 1) & 1)];
       }
-      B[b * dim + i] = make_float2((float)v.real(), (float)v.imag());
+      row[i] = make_float2((float)v.real(), (float)v.imag());
     }
-  for (const PassHost& ph : t.passes)
-    emulate_pass_host(pass_args(p, ph, t.phases.data(), t.ops.data(), t.mats.data(), t.mrows.data(), B.data(), bits, nb),
-                      ph.R);
+    if (!s16) {
+      std::copy(row.begin(), row.end(), B.begin() + (size_t)b * dim);
+      continue;
+    }
+    for (size_t blk = 0; blk < (dim >> ib); ++blk) {
+      float amax = 0.f;
+      for (size_t i = blk << ib; i < (blk + 1) << ib; ++i)
+        amax = std::max(amax, std::max(std::fabs(row[i].x), std::fabs(row[i].y)));
+      const int e = block_exponent(amax);
+      const float inv = std::ldexp(1.f, -e);
+      for (size_t i = blk << ib; i < (blk + 1) << ib; ++i)
+        Bw[(size_t)b * dim + i] = storage == TNC_STORE_F16_BLOCKSCALE ? pack16<STORE_F16>(row[i].x, row[i].y, inv)
+                                                                      : pack16<STORE_BF16>(row[i].x, row[i].y, inv);
+      sc[0][(size_t)b * sstride + blk] = std::ldexp(1.f, e);
+    }
+  }
+  // variant resolution (k_resolve)
+  const long long rstride = (long long)(L.rmats / 4);
+  std::vector<float> rmats((size_t)rstride * nb);
+  for (int b = 0; b < nb; ++b)
+    for (size_t o = 0; o < t.ops.size(); ++o) {
+      const DevOp& op = t.ops[o];
+      const uint8_t* x = bits + (size_t)b * p.n;
+      const int var = (op.xrow0 >= 0 ? 2 * (x[op.xrow0] & 1) : 0) + (op.xrow1 >= 0 ? (x[op.xrow1] & 1) : 0);
+      for (int e = 0; e < 16; ++e)
+        rmats[(size_t)b * rstride + o * 16 + e] = t.mats[((size_t)op.mat * 4 + var) * 16 + e];
+    }
+  int cur = 0;
+  ScaleMap map = init_map(p);
+  for (const PassHost& ph : t.passes) {
+    PassArgs a = pass_args(p, ph, t.phases.data(), t.ops.data(), t.mats.data(), t.mrows.data(), B.data(), bits, nb);
+    a.rmats = rmats.data();
+    a.rstride = rstride;
+    if (s16) {
+      a.store = storage;
+      a.scale_in = sc[cur].data();
+      a.scale_out = sc[cur ^ 1].data();
+      a.scale_stride = sstride;
+      a.in_map = map;
+    }
+    emulate_pass_host(a, ph.R);
+    if (s16) {
+      cur ^= 1;
+      map = pass_map(ph);
+    }
+  }
+  // the first late launch's input, decoded
+  auto entry = [&](int b, uint64_t g) -> cd {
+    if (!s16) {
+      const float2 x = B[(size_t)b * dim + g];
+      return cd(x.x, x.y);
+    }
+    const float scl = sc[cur][(size_t)b * sstride + scale_slot(g, map)];
+    const uint32_t w = Bw[(size_t)b * dim + g];
+    const float2 x = storage == TNC_STORE_F16_BLOCKSCALE ? unpack16<STORE_F16>(w, scl) : unpack16<STORE_BF16>(w, scl);
+    return cd(x.x, x.y);
+  };
   // late (FP64), same tables
   const LateFirst& F = t.late.first;
   const int sb = t.late.s;
@@ -456,10 +623,7 @@ int emulate(Plan& p, int k, int nb, const uint8_t* bits, cd* out) {
     for (long long r = 0; r < F.M; ++r)
       for (int c = 0; c < F.N; ++c) {
         cd acc = 0;
-        for (int kk = 0; kk < F.K; ++kk) {
-          const float2 x = B[b * dim + (size_t)r * F.K + kk];
-          acc += cd(x.x, x.y) * F.J[((size_t)var * F.K + kk) * F.N + c];
-        }
+        for (int kk = 0; kk < F.K; ++kk) acc += entry(b, (uint64_t)r * F.K + kk) * F.J[((size_t)var * F.K + kk) * F.N + c];
         cur[(size_t)r * F.N + c] = acc;
       }
     for (const LateOpsLaunch& ln : t.late.ops) {
@@ -546,9 +710,11 @@ int tnc_plan(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, c
     if (opt->low_bits) o.low_bits = opt->low_bits;
     o.math = opt->math;
     o.pipeline = opt->pipeline;
+    o.late_fold = opt->late_fold;
   }
   if (o.max_tile_bits < 6 || o.max_tile_bits > 13 || o.reg_bits < 1 || o.reg_bits > 5 || o.low_bits < 1 ||
       o.low_bits > o.max_tile_bits - 2 || o.math < 0 || o.math > 1 || o.pipeline < 0 || o.pipeline > 1 ||
+      o.late_fold < -1 || o.late_fold > 3 ||
       o.max_tile_bits - o.reg_bits > (o.pipeline && o.math == 0 ? 9 : 8))
     return set_err(TNC_E_INVALID, "tile options out of range");
   if (n < 2 || d < 2 || (int64_t)n * (d + 1) > (1 << 24)) return set_err(TNC_E_DOMAIN, "need n >= 2, d >= 2");
@@ -593,7 +759,7 @@ int tnc_plan_info(tnc_plan_t plan, int32_t k, tnc_info* info) {
   info->early_layers = k >= 1 ? 2 * k : 0;
   info->late_layers = k >= 1 ? p->d - 2 * k : 0;
   info->log2_cost = s->log2_cost;
-  info->workspace_per_batch = t.bytes_B + t.bytes_late[0] + t.bytes_late[1];
+  info->workspace_per_batch = batch_layout(*p, t, TNC_STORE_C64).per_batch();
   return TNC_OK;
 }
 
@@ -607,7 +773,6 @@ int tnc_prepare(tnc_plan_t plan, int32_t k) {
 int tnc_workspace_bytes(tnc_plan_t plan, int32_t k, int32_t n_batches, int32_t storage, uint64_t* bytes) {
   Plan* p = get(plan);
   if (!p || !bytes || n_batches < 0) return set_err(TNC_E_INVALID, "bad argument");
-  if (storage != TNC_STORE_C64) return set_err(TNC_E_INVALID, "unknown storage mode");
   std::shared_ptr<Schedule> s;
   std::string err;
   int rc = get_schedule(*p, k, &s, &err);
@@ -615,7 +780,8 @@ int tnc_workspace_bytes(tnc_plan_t plan, int32_t k, int32_t n_batches, int32_t s
   HostTables t;
   rc = build_tables(*p, *s, &t, &err);
   if (rc) return set_err(rc, err);
-  *bytes = (uint64_t)n_batches * (t.bytes_B + t.bytes_late[0] + t.bytes_late[1]);
+  if ((rc = check_storage(t, storage))) return rc;
+  *bytes = (uint64_t)n_batches * batch_layout(*p, t, storage).per_batch();
   return TNC_OK;
 }
 
@@ -624,12 +790,12 @@ int tnc_amplitudes(tnc_plan_t plan, int32_t n_batches, const uint8_t* d_bits, in
   Plan* p = get(plan);
   if (!p || n_batches < 0 || (n_batches > 0 && (!d_bits || !d_out || !d_workspace)))
     return set_err(TNC_E_INVALID, "bad argument");
-  if (storage != TNC_STORE_C64) return set_err(TNC_E_INVALID, "unknown storage mode");
+  if (storage != TNC_STORE_C64 && !is_s16(storage)) return set_err(TNC_E_INVALID, "unknown storage mode");
   if (n_batches == 0) return TNC_OK;
   std::shared_ptr<DevSched> ds;
   int rc = get_dev_sched(*p, k, &ds);
   if (rc) return rc;
-  return run_device(*p, *ds, n_batches, d_bits, k, d_out, d_workspace, workspace_bytes,
+  return run_device(*p, *ds, n_batches, d_bits, k, storage, d_out, d_workspace, workspace_bytes,
                     static_cast<hipStream_t>(stream));
 }
 
@@ -745,11 +911,12 @@ int tnc_debug_execute_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bi
   return TNC_OK;
 }
 
-int tnc_debug_emulate_device(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, tnc_c128* out) {
+int tnc_debug_emulate_device(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, int32_t storage,
+                             tnc_c128* out) {
   Plan* p = get(plan);
   if (!p || !bits || !out || n_batches < 0) return set_err(TNC_E_INVALID, "bad argument");
   std::vector<cd> o((size_t)n_batches << k);
-  int rc = emulate(*p, k, n_batches, bits, o.data());
+  int rc = emulate(*p, k, n_batches, bits, storage, o.data());
   if (rc) return rc;
   for (size_t i = 0; i < o.size(); ++i) out[i] = tnc_c128{o[i].real(), o[i].imag()};
   return TNC_OK;

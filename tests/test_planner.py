@@ -107,7 +107,9 @@ def test_host_execution_matches_oracle(n, d, fp, dense):
 
 
 TILES = [dict(max_tile_bits=6, low_bits=2, reg_bits=3), dict(max_tile_bits=6, low_bits=1, reg_bits=5),
-         dict(max_tile_bits=7, low_bits=3, reg_bits=2), dict(max_tile_bits=8, low_bits=4, reg_bits=4), None]
+         dict(max_tile_bits=7, low_bits=3, reg_bits=2), dict(max_tile_bits=8, low_bits=4, reg_bits=4), None,
+         # late removals folded into the join launch (the default for large tensors)
+         dict(late_fold=3), dict(late_fold=1, max_tile_bits=8, low_bits=3, reg_bits=4)]
 
 
 @pytest.mark.parametrize("opts", TILES)
@@ -138,3 +140,33 @@ def test_emulation_matches_tableau_at_full_size(n, d):
     for x, a in zip(xs, got):
         pt = tab.prob(x)
         assert abs(abs(a) ** 2 - pt) <= 1e-5 * max(pt, 2.0 ** -n)
+
+
+# 16-bit block-scaled storage in the host emulation: the error is the storage
+# format's (FP16 keeps 11 significant bits, BF16 8), well above complex64's
+# and well below O(1).  Bounds: measured errors of these circuits with a
+# margin of about 2x.
+@pytest.mark.parametrize("storage,bound", [(1, (1.5e-2, 6e-3)), (2, (1.2e-1, 5e-2))])
+@pytest.mark.parametrize("opts,n,d,k", [
+    (None, 14, 29, 2),
+    (dict(max_tile_bits=10, low_bits=4, reg_bits=4), 16, 30, 4),
+    (dict(max_tile_bits=8, low_bits=2, reg_bits=3), 12, 24, 4),
+    (dict(max_tile_bits=6, low_bits=2, reg_bits=1), 10, 21, 1),
+])
+def test_emulated_block_scaled_storage(storage, bound, opts, n, d, k):
+    c = H.mixed_circuit(n, d, 7 * n + d, dense=0.3)
+    bits = W.random_bitstrings(n, 3, W.rng_for(309, n, d))
+    ref = oracle.amplitudes(c, bits, k)
+    got = Plan.from_circuit(c, opts).debug_emulate_device(bits, k, storage)
+    per, l2 = H.amp_errors(got, ref, n)
+    assert np.isfinite(got).all()
+    assert per < bound[0] and l2 < bound[1], (per, l2)
+    # and it is a real rounding error, not an exact result
+    assert l2 > 1e-6
+
+
+def test_block_scaled_storage_is_rejected_with_one_low_slot():
+    c = H.mixed_circuit(14, 28, 98)
+    p = Plan.from_circuit(c, dict(max_tile_bits=8, low_bits=1, reg_bits=3))
+    with pytest.raises(TncError):
+        p.debug_emulate_device(W.random_bitstrings(14, 1, W.rng_for(310)), 2, 1)
