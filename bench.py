@@ -253,7 +253,7 @@ def serving_bench(torch, W, count=512, load=0.8):
                        "latency_ms_p50": round(pct(seq_lat, 50), 3), "latency_ms_p99": round(pct(seq_lat, 99), 3)},
         "served": {"amplitudes_per_s": round(amps / served_s, 1), "requests_per_s": round(count / served_s, 1),
                    "latency_ms_p50": round(pct(lat, 50), 3), "latency_ms_p99": round(pct(lat, 99), 3),
-                   "max_inflight": summ["max_inflight"],
+                   "max_inflight": summ["max_inflight"], "capture_failures": summ["capture_failures"],
                    "graph_launches": summ["graph_launches"] - warm["graph_launches"],
                    "plain_launches": summ["plain_launches"] - warm["plain_launches"]},
         "tuning": {str(h): o for h, o in tuning.items()},
@@ -321,12 +321,20 @@ def main():
         steps2 = 16 if other == "precision" else 2
         secondary = run_workload(other, steps2, 1, torch, W, Plan, profile_begin, profile_end)
         torch.cuda.empty_cache()
+    # the side sections report their own failure instead of losing the line
     storage = None
     if not args.no_storage:
-        storage = storage_modes(torch, W, Plan, profile_begin, profile_end)
+        try:
+            storage = storage_modes(torch, W, Plan, profile_begin, profile_end)
+        except Exception as e:  # noqa: BLE001
+            storage = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.empty_cache()
     serving = None
     if not args.no_serving:
-        serving = serving_bench(torch, W)
+        try:
+            serving = serving_bench(torch, W)
+        except Exception as e:  # noqa: BLE001
+            serving = {"error": f"{type(e).__name__}: {e}"}
         torch.cuda.empty_cache()
     traffic = recorded_traffic(args.workload)
     roofline = {

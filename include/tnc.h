@@ -213,9 +213,10 @@ int tnc_autotune(int32_t n, int32_t d, int32_t k, int32_t storage, const tnc_opt
  * n_streams HIP streams is free and the device arena has room for its
  * footprint (workspace + bits + output), oldest first, letting younger
  * requests that fit pass an older one that does not at most 16 times.
- * Requests whose boundary tensor has <= small_bits bits run in a fixed
- * per-stream region as HIP graphs captured on first use and replayed when
- * the same (plan, k, batches, storage) returns on that stream.
+ * Requests whose boundary tensor has <= small_bits bits run as HIP graphs
+ * captured on first use; each cached graph owns its device region (within a
+ * quarter of the arena) and is replayed, from any stream, when the same
+ * (plan, k, batches, storage) returns while it is idle.
  * Results are bit-identical to tnc_amplitudes with the same plan options.
  */
 typedef struct tnc_server_s* tnc_server_t;
@@ -240,7 +241,7 @@ typedef struct {
 
 typedef struct {
   int64_t completed;
-  int64_t graph_launches, graph_captures, plain_launches;
+  int64_t graph_launches, graph_captures, capture_failures, plain_launches;
   int64_t plan_cache_hits, plan_cache_misses;
   int32_t max_inflight;  /* most requests seen running at once */
   int32_t reserved;

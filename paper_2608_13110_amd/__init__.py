@@ -99,7 +99,8 @@ class RequestStats(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("graph_launches", ctypes.c_int64),
-                ("graph_captures", ctypes.c_int64), ("plain_launches", ctypes.c_int64),
+                ("graph_captures", ctypes.c_int64), ("capture_failures", ctypes.c_int64),
+                ("plain_launches", ctypes.c_int64),
                 ("plan_cache_hits", ctypes.c_int64), ("plan_cache_misses", ctypes.c_int64),
                 ("max_inflight", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("latency_ms_p50", ctypes.c_double), ("latency_ms_p99", ctypes.c_double),

@@ -8,10 +8,12 @@
 // device arena has room for their footprint (tensor workspace, bits,
 // output), so requests that arrive while others run start as soon as a
 // stream and memory free up, and the work of different requests overlaps on
-// the device.  Small requests (boundary bits <= small_bits) run from a
-// per-stream region as captured HIP graphs, replayed when the same plan
-// comes back.  Batches of a plan share only the read-only plan (Sec. 5.3:
-// the batches of one circuit differ only in their output bits).
+// the device.  Small requests (boundary bits <= small_bits) run as captured
+// HIP graphs; each cached graph owns its device region (workspace, bits,
+// output), so it is replayed from any stream whenever the same plan, k and
+// batch count come back and the graph is not already running.  Batches of a
+// plan share only the read-only plan (Sec. 5.3: the batches of one circuit
+// differ only in their output bits).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -132,15 +134,23 @@ struct Request {
   std::string err;  // what failed, for tnc_last_error of the waiting thread
   int bypassed = 0;
   bool small = false;
+  bool graph_used = false;
   int64_t t_submit = 0, t_ready = 0, t_admit = 0, t_done = 0;
+};
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  uint64_t off = 0;  // its own arena block: workspace, bits, output
+  bool busy = false;
+  bool failed = false;  // capture did not work: run plainly from the region
 };
 
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   std::shared_ptr<Request> req;
-  uint64_t off = UINT64_MAX;      // arena block of a large request
-  uint64_t small_off = 0;         // this slot's fixed region for small requests
+  uint64_t off = UINT64_MAX;      // arena block of a request run without a graph
+  GraphEntry* graph = nullptr;    // or the graph it replays
   uint8_t* h_bits = nullptr;      // pinned staging
   tnc_c128* h_out = nullptr;
   size_t cap_bits = 0, cap_out = 0;
@@ -148,9 +158,9 @@ struct Slot {
 
 struct GraphKey {
   tnc_plan_t plan;
-  int k, nb, storage, slot;
+  int k, nb, storage;
   bool operator<(const GraphKey& o) const {
-    return std::tie(plan, k, nb, storage, slot) < std::tie(o.plan, o.k, o.nb, o.storage, o.slot);
+    return std::tie(plan, k, nb, storage) < std::tie(o.plan, o.k, o.nb, o.storage);
   }
 };
 
@@ -160,24 +170,28 @@ struct ServerImpl {
   tnc_server_options opt{};
   int device = 0;
   char* arena_base = nullptr;
-  uint64_t arena_bytes = 0, small_region = 0;
+  uint64_t arena_bytes = 0, graph_bytes = 0, graph_budget = 0;
   Arena arena;
   std::vector<Slot> slots;
   std::map<int, tnc_options> tuning;  // boundary bits -> tile options
 
   std::mutex mu;
+  // held around table uploads (planners) and around graph capture
+  // (dispatcher): no allocation or blocking copy runs while a capture is open
+  std::mutex dev_mu;
   std::condition_variable cv_plan, cv_dispatch, cv_done;
   std::deque<std::shared_ptr<Request>> to_plan, ready;
   std::unordered_map<uint64_t, std::shared_ptr<Request>> reqs;
   std::unordered_multimap<uint64_t, std::shared_ptr<CachedPlan>> plans;
-  std::map<GraphKey, hipGraphExec_t> graphs;
+  std::map<GraphKey, std::unique_ptr<GraphEntry>> graphs;
   uint64_t next_id = 1;
   bool stop = false;
   std::vector<std::thread> planners;
   std::thread dispatcher;
 
   // statistics
-  uint64_t n_done = 0, n_graph_launch = 0, n_graph_capture = 0, n_plain = 0, plan_hits = 0, plan_misses = 0;
+  uint64_t n_done = 0, n_graph_launch = 0, n_graph_capture = 0, n_capture_failed = 0, n_plain = 0, plan_hits = 0,
+           plan_misses = 0;
   int64_t first_submit = 0, last_done = 0;
   std::vector<double> lat_ms;
   int max_inflight = 0;
@@ -191,7 +205,8 @@ struct ServerImpl {
 
   void planner_loop();
   void dispatcher_loop();
-  int launch(Slot& s, int si, Request& r);
+  int launch(Slot& s, Request& r, uint64_t base, GraphEntry* g);
+  bool place(Slot& s, Request& r, uint64_t* base, GraphEntry** g);
   void finish(Slot& s, bool ok);
 };
 
@@ -264,7 +279,10 @@ void ServerImpl::planner_loop() {
     tnc_info info{};
     uint64_t ws = 0;
     if (!rc) rc = tnc_plan_info(cp->plan, r->k, &info);
-    if (!rc) rc = tnc_prepare(cp->plan, r->k);
+    if (!rc) {
+      std::lock_guard<std::mutex> dk(dev_mu);
+      rc = tnc_prepare(cp->plan, r->k);
+    }
     if (!rc) rc = tnc_workspace_bytes(cp->plan, r->k, r->nb, r->storage, &ws);
     const std::string perr = rc ? std::string("serving: planning: ") + tnc_last_error() : std::string();
     std::lock_guard<std::mutex> lk(mu);
@@ -276,7 +294,7 @@ void ServerImpl::planner_loop() {
     const uint64_t io = (((uint64_t)r->nb * r->circuit.n + 255) & ~uint64_t(255)) +
                         (((uint64_t)r->nb << r->k) * sizeof(tnc_c128) + 255) / 256 * 256;
     r->footprint = ws + io;
-    r->small = opt.small_bits > 0 && r->h <= opt.small_bits && r->footprint <= small_region;
+    r->small = opt.small_bits > 0 && r->h <= opt.small_bits;
     r->t_ready = now_ns();
     if (rc) {
       r->state = R_DONE;
@@ -290,54 +308,49 @@ void ServerImpl::planner_loop() {
   }
 }
 
-int ServerImpl::launch(Slot& s, int si, Request& r) {
+// Runs request r on slot s from the arena block at `base`, either by
+// replaying (or first capturing) graph g, or by plain launches (g null).
+int ServerImpl::launch(Slot& s, Request& r, uint64_t base, GraphEntry* g) {
   auto fail = [&](int code, const char* what, hipError_t e) {
-    r.err = std::string("serving: ") + what + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : "");
+    r.err = std::string("serving: ") + what + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : "") +
+            (code != TNC_OK && e == hipSuccess ? std::string(": ") + tnc_last_error() : std::string());
     return code;
   };
   const size_t nbits = (size_t)r.nb * r.circuit.n, nout = (size_t)r.nb << r.k;
   ensure_pinned(s, nbits, nout);
   if (s.cap_bits < nbits || s.cap_out < nout) return fail(TNC_E_NOMEM, "pinned staging allocation", hipSuccess);
-  const uint64_t base = r.small ? s.small_off : s.off;
   char* ws = arena_base + base;
   uint8_t* d_bits = reinterpret_cast<uint8_t*>(ws + r.ws_bytes);
   tnc_c128* d_out = reinterpret_cast<tnc_c128*>(ws + r.ws_bytes + (((uint64_t)nbits + 255) & ~uint64_t(255)));
   std::memcpy(s.h_bits, r.bits.data(), nbits);
   hipError_t e = hipMemcpyAsync(d_bits, s.h_bits, nbits, hipMemcpyHostToDevice, s.stream);
   if (e != hipSuccess) return fail(TNC_E_DEVICE, "bits upload", e);
-  int rc = TNC_OK;
-  if (r.small) {
-    const GraphKey key{r.cp->plan, r.k, r.nb, r.storage, si};
-    auto it = graphs.find(key);
-    if (it == graphs.end() && graphs.size() < (size_t)std::max(0, opt.max_graphs)) {
-      hipGraph_t g = nullptr;
-      hipGraphExec_t ge = nullptr;
-      e = hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal);
-      if (e != hipSuccess) return fail(TNC_E_DEVICE, "begin capture", e);
-      rc = tnc_amplitudes(r.cp->plan, r.nb, d_bits, r.k, r.storage, d_out, ws, r.ws_bytes, s.stream);
-      const hipError_t e2 = hipStreamEndCapture(s.stream, &g);
-      if (rc) {
-        if (g) (void)hipGraphDestroy(g);
-        return fail(rc, "captured launch sequence", hipSuccess);
-      }
-      if (e2 != hipSuccess) return fail(TNC_E_DEVICE, "end capture", e2);
-      e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (e != hipSuccess) return fail(TNC_E_DEVICE, "graph instantiate", e);
-      it = graphs.emplace(key, ge).first;
-      ++n_graph_capture;
+  if (g && !g->exec && !g->failed) {
+    // capture once; a capture that does not work leaves the region to plain
+    // launches (the stream leaves capture mode either way)
+    std::lock_guard<std::mutex> dk(dev_mu);
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      const int rc = tnc_amplitudes(r.cp->plan, r.nb, d_bits, r.k, r.storage, d_out, ws, r.ws_bytes, s.stream);
+      const hipError_t e2 = hipStreamEndCapture(s.stream, &graph);
+      if (rc == TNC_OK && e2 == hipSuccess && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) == hipSuccess)
+        ++n_graph_capture;
+      else
+        g->exec = nullptr;
+      if (graph) (void)hipGraphDestroy(graph);
     }
-    if (it != graphs.end()) {
-      e = hipGraphLaunch(it->second, s.stream);
-      if (e != hipSuccess) return fail(TNC_E_DEVICE, "graph launch", e);
-      ++n_graph_launch;
-    } else {
-      rc = tnc_amplitudes(r.cp->plan, r.nb, d_bits, r.k, r.storage, d_out, ws, r.ws_bytes, s.stream);
-      if (rc) return fail(rc, "launch sequence", hipSuccess);
-      ++n_plain;
+    (void)hipGetLastError();
+    if (!g->exec) {
+      g->failed = true;
+      ++n_capture_failed;
     }
+  }
+  if (g && g->exec) {
+    e = hipGraphLaunch(g->exec, s.stream);
+    if (e != hipSuccess) return fail(TNC_E_DEVICE, "graph launch", e);
+    ++n_graph_launch;
   } else {
-    rc = tnc_amplitudes(r.cp->plan, r.nb, d_bits, r.k, r.storage, d_out, ws, r.ws_bytes, s.stream);
+    const int rc = tnc_amplitudes(r.cp->plan, r.nb, d_bits, r.k, r.storage, d_out, ws, r.ws_bytes, s.stream);
     if (rc) return fail(rc, "launch sequence", hipSuccess);
     ++n_plain;
   }
@@ -351,7 +364,11 @@ int ServerImpl::launch(Slot& s, int si, Request& r) {
 void ServerImpl::finish(Slot& s, bool ok) {
   Request& r = *s.req;
   if (ok && r.out) std::memcpy(r.out, s.h_out, ((size_t)r.nb << r.k) * sizeof(tnc_c128));
-  if (!r.small && s.off != UINT64_MAX) arena.release(s.off);
+  if (s.graph) {
+    s.graph->busy = false;
+    s.graph = nullptr;
+  }
+  if (s.off != UINT64_MAX) arena.release(s.off);
   s.off = UINT64_MAX;
   r.t_done = now_ns();
   r.state = R_DONE;
@@ -359,6 +376,41 @@ void ServerImpl::finish(Slot& s, bool ok) {
   last_done = r.t_done;
   lat_ms.push_back((r.t_done - r.t_submit) * 1e-6);
   s.req.reset();
+}
+
+// Memory for request r on slot s: the region of its cached graph when it
+// has one that is idle (or can get one within the graph budget), else a
+// fresh arena block.  Returns false when neither fits now.
+bool ServerImpl::place(Slot& s, Request& r, uint64_t* base, GraphEntry** g) {
+  *g = nullptr;
+  if (r.small) {
+    const GraphKey key{r.cp->plan, r.k, r.nb, r.storage};
+    auto it = graphs.find(key);
+    if (it != graphs.end() && !it->second->busy) {
+      *g = it->second.get();
+    } else if (it == graphs.end() && graphs.size() < (size_t)opt.max_graphs &&
+               graph_bytes + r.footprint <= graph_budget) {
+      const uint64_t off = arena.alloc(r.footprint);
+      if (off != UINT64_MAX) {
+        auto e = std::make_unique<GraphEntry>();
+        e->off = off;
+        graph_bytes += (r.footprint + 255) & ~uint64_t(255);
+        *g = e.get();
+        graphs.emplace(key, std::move(e));
+      }
+    }
+    if (*g) {
+      (*g)->busy = true;
+      s.graph = *g;
+      *base = (*g)->off;
+      return true;
+    }
+  }
+  const uint64_t off = arena.alloc(r.footprint);
+  if (off == UINT64_MAX) return false;
+  s.off = off;
+  *base = off;
+  return true;
 }
 
 void ServerImpl::dispatcher_loop() {
@@ -372,6 +424,7 @@ void ServerImpl::dispatcher_loop() {
       if (!s.req) continue;
       const hipError_t q = hipEventQuery(s.done);
       if (q == hipErrorNotReady) {
+        (void)hipGetLastError();  // "not ready" is a status, not an error to keep
         ++inflight;
         continue;
       }
@@ -390,15 +443,9 @@ void ServerImpl::dispatcher_loop() {
       if (s.req) continue;
       for (auto it = ready.begin(); it != ready.end(); ++it) {
         Request& r = **it;
-        bool fits = r.small;
-        if (!fits) {
-          const uint64_t off = arena.alloc(r.footprint);
-          if (off != UINT64_MAX) {
-            s.off = off;
-            fits = true;
-          }
-        }
-        if (!fits) {
+        uint64_t base = 0;
+        GraphEntry* g = nullptr;
+        if (!place(s, r, &base, &g)) {
           if (++r.bypassed > 16) break;
           continue;
         }
@@ -406,7 +453,8 @@ void ServerImpl::dispatcher_loop() {
         ready.erase(it);
         r.state = R_RUNNING;
         r.t_admit = now_ns();
-        const int rc = launch(s, (int)si, r);
+        const int rc = launch(s, r, base, g);
+        r.graph_used = g != nullptr && g->exec != nullptr;
         if (rc) {
           r.rc = rc;
           finish(s, false);
@@ -451,21 +499,17 @@ int tnc_server_create(const tnc_server_options* opt, tnc_server_t* out) {
   if (o.small_bits < 0 || o.small_bits > 24 || o.n_streams > 16 || o.n_planners > 16 || o.arena_bytes == 0)
     return TNC_E_INVALID;
   if (hipGetDevice(&S->device) != hipSuccess) return TNC_E_DEVICE;
-  // per-stream regions for small requests: tensor + 16-bit scales + tables
-  // + late buffers + bits + output of one batch up to small_bits, k <= 10
-  S->small_region = o.small_bits > 0 ? (((uint64_t)8 << o.small_bits) * 3 / 2 + (16ull << 20)) : 0;
-  const uint64_t small_total = S->small_region * (uint64_t)o.n_streams;
-  if (small_total >= o.arena_bytes) return TNC_E_INVALID;
+  // cached graphs keep their regions: at most a quarter of the arena
   if (hipMalloc((void**)&S->arena_base, o.arena_bytes) != hipSuccess) return TNC_E_NOMEM;
   S->arena_bytes = o.arena_bytes;
-  S->arena = Arena(o.arena_bytes - small_total);
+  S->graph_budget = o.arena_bytes / 4;
+  S->arena = Arena(o.arena_bytes);
   S->slots.resize(o.n_streams);
   for (int i = 0; i < o.n_streams; ++i) {
     Slot& s = S->slots[i];
     if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
       return TNC_E_DEVICE;
-    s.small_off = o.arena_bytes - small_total + (uint64_t)i * S->small_region;
   }
   ServerImpl* raw = S.get();
   for (int i = 0; i < o.n_planners; ++i) S->planners.emplace_back([raw] { raw->planner_loop(); });
@@ -534,7 +578,7 @@ int tnc_server_wait(tnc_server_t sv, uint64_t id, tnc_request_stats* st) {
     st->run_ms = (r->t_admit ? r->t_done - r->t_admit : 0) * 1e-6;
     st->total_ms = (r->t_done - r->t_submit) * 1e-6;
     st->boundary_bits = r->h;
-    st->graph = r->small ? 1 : 0;
+    st->graph = r->graph_used ? 1 : 0;
   }
   const int rc = r->rc;
   if (rc) set_error_message(rc, r->err);
@@ -550,6 +594,7 @@ int tnc_server_summary(tnc_server_t sv, tnc_server_stats* st) {
   st->completed = (int64_t)S.n_done;
   st->graph_launches = (int64_t)S.n_graph_launch;
   st->graph_captures = (int64_t)S.n_graph_capture;
+  st->capture_failures = (int64_t)S.n_capture_failed;
   st->plain_launches = (int64_t)S.n_plain;
   st->plan_cache_hits = (int64_t)S.plan_hits;
   st->plan_cache_misses = (int64_t)S.plan_misses;
@@ -577,7 +622,8 @@ void tnc_server_destroy(tnc_server_t sv) {
   S.cv_dispatch.notify_all();
   for (std::thread& t : S.planners) t.join();
   S.dispatcher.join();
-  for (auto& g : S.graphs) (void)hipGraphExecDestroy(g.second);
+  for (auto& g : S.graphs)
+    if (g.second->exec) (void)hipGraphExecDestroy(g.second->exec);
   for (Slot& s : S.slots) {
     if (s.stream) (void)hipStreamSynchronize(s.stream);
     if (s.done) (void)hipEventDestroy(s.done);

@@ -429,6 +429,10 @@ int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k
   const HostTables& t = ds.host;
   int rc = check_storage(t, storage);
   if (rc) return rc;
+  // each launch is checked with hipGetLastError: drop a status left on this
+  // thread by earlier calls (a hipEventQuery that returned hipErrorNotReady
+  // leaves one) so that it is not taken for a launch failure
+  (void)hipGetLastError();
   const bool s16 = is_s16(storage);
   const BatchLayout L = batch_layout(p, t, storage);
   const uint64_t per = L.per_batch();
