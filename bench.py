@@ -70,13 +70,22 @@ def pct(xs, q):
     return xs[i]
 
 
-def run_workload(name, steps, warmup, torch, W, Plan, profile_begin, profile_end):
+# tile candidates the autotuner times for the large workloads
+MAIN_CANDIDATES = [dict(), dict(max_tile_bits=12), dict(low_bits=5)]
+
+
+def run_workload(name, steps, warmup, torch, W, Plan, profile_begin, profile_end, fixed=None):
+    from paper_2608_13110_amd import autotune
     spec = WORKLOADS[name]
     k = spec["k"]
     circ = W.config_circuit(spec["cid"])
     bits_all = W.config_bitstrings(spec["cid"])
+    options, tune_ms = (fixed or {}), None
+    if fixed is None:
+        best, times = autotune(circ.n, circ.d, k, MAIN_CANDIDATES, reps=1)
+        options, tune_ms = MAIN_CANDIDATES[best], [round(float(t), 1) for t in times]
     t0 = time.time()
-    plan = Plan.from_circuit(circ)
+    plan = Plan.from_circuit(circ, options or None)
     plan.prepare(k)
     prep_s = time.time() - t0
     info = plan.info(k)
@@ -119,6 +128,7 @@ def run_workload(name, steps, warmup, torch, W, Plan, profile_begin, profile_end
         pass_avg_ms=prof["pass_ms"] / max(1, prof["pass_launches"]),
         sweep_tflops=sweep_flops / (prof["pass_ms"] / 1e3) / 1e12 if prof["pass_ms"] > 0 else 0.0,
         n_passes=info["n_passes"], n_ops=info["n_ops"], log2_cost=info["log2_cost"],
+        tile_options=options, autotune_ms=tune_ms,
     )
 
 
@@ -289,6 +299,9 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-storage", action="store_true", help="skip the 16-bit storage comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--options", default=None,
+                    help="tile options as JSON (e.g. '{\"max_tile_bits\": 12}') instead of autotuning "
+                         "(profiling runs fix them so that only the timed configuration launches)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (reference "
                          "dispatches for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -313,7 +326,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes_read": nbytes, "copy_calibration_bytes_written": nbytes,
                           "dispatches": 5}), flush=True)
         return
-    main_r = run_workload(args.workload, args.steps, args.warmup, torch, W, Plan, profile_begin, profile_end)
+    fixed = json.loads(args.options) if args.options else None
+    main_r = run_workload(args.workload, args.steps, args.warmup, torch, W, Plan, profile_begin, profile_end, fixed)
     torch.cuda.empty_cache()
     secondary = None
     if not args.no_secondary:
@@ -353,7 +367,8 @@ def main():
         "vs_baseline": None, "dtype": "c64", "data": "synthetic",
         "config": {"workload": main_r["workload"], "batch_amplitudes": 1 << main_r["k"],
                    "boundary_bits": main_r["h"], "passes": main_r["n_passes"], "updates": main_r["n_ops"],
-                   "log2_cost": round(main_r["log2_cost"], 3)},
+                   "log2_cost": round(main_r["log2_cost"], 3), "tile_options": main_r["tile_options"],
+                   "autotune_candidates": MAIN_CANDIDATES, "autotune_ms_per_batch": main_r["autotune_ms"]},
         "hbm_gbs": round(main_r["pass_gbs"], 1), "hbm_frac": roofline["frac"],
         "latency_ms_p50": main_r["latency_ms_p50"], "latency_ms_p99": main_r["latency_ms_p99"],
         "kernel_ms": {"pass": round(main_r["pass_ms"], 2), "late": round(main_r["late_ms"], 2),

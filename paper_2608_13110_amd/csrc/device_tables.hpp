@@ -73,6 +73,9 @@ struct PassArgs {
   // (the variant of every op already picked from batch b's output bits)
   const float* rmats;
   long long rstride;     // floats per batch in rmats
+  // the same for the matrix-core form: rmrows[b][op][ctl][row] (8 float4)
+  const float4* rmrows;
+  long long rmstride;    // float4 per batch in rmrows
   float2* B;             // boundary tensors, batch stride 2^h entries
   const uint8_t* bits;   // output bits, batch stride n
   int n_phases;
@@ -148,9 +151,12 @@ struct LateOpsArgs {
 struct ResolveArgs {
   const DevOp* ops;
   const float* mats;
+  const float4* mrows;
   const uint8_t* bits;
   float* rmats;
   long long rstride;
+  float4* rmrows;        // null: no matrix-core form
+  long long rmstride;
   int n_ops;
   int n;
   int n_batches;

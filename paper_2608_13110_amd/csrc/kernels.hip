@@ -172,6 +172,12 @@ __global__ __launch_bounds__(kBlock) void k_resolve(ResolveArgs a) {
   float4* dst = reinterpret_cast<float4*>(a.rmats + (size_t)b * a.rstride + (size_t)o * 16);
 #pragma unroll
   for (int q = 0; q < 4; ++q) dst[q] = src[q];
+  if (a.rmrows) {
+    const float4* rs = a.mrows + ((size_t)op.mat * 4 + var) * 8;
+    float4* rd = a.rmrows + (size_t)b * a.rmstride + (size_t)o * 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rd[q] = rs[q];
+  }
 }
 
 hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s) {
@@ -195,7 +201,7 @@ hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s) {
 // WU: every wave lies inside one tile (one tile per block, or T - R >= 6),
 // so the batch and everything read through it are wave-uniform.
 template <int R, bool MULTI, bool MF, bool WU>
-__global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MF ? 2 : 1))) void k_pass(PassArgs a) {
   extern __shared__ float2 lds[];
   constexpr int E = 1 << R;
   const int T = a.T;
@@ -226,9 +232,8 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
 
   const uint32_t tmask = (1u << T) - 1u;
   PhaseCtx<R, MF> ctx;
-  ctx.ops = (const TNC_TBL DevOp*)a.ops;
   ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
-  ctx.mrows = a.mrows;
+  ctx.rmr = a.rmrows ? a.rmrows + (size_t)batch * a.rmstride : nullptr;
   ctx.bits = a.bits;
   ctx.xpos = (size_t)batch * a.n;
   ctx.tb = 0;
@@ -306,9 +311,8 @@ __global__ __launch_bounds__(kBlock) void k_pass16(PassArgs a) {
 
   const uint32_t tmask = (1u << T) - 1u;
   PhaseCtx<R, false> ctx;
-  ctx.ops = (const TNC_TBL DevOp*)a.ops;
   ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
-  ctx.mrows = a.mrows;
+  ctx.rmr = a.rmrows ? a.rmrows + (size_t)batch * a.rmstride : nullptr;
   ctx.bits = a.bits;
   ctx.xpos = (size_t)batch * a.n;
   ctx.tb = 0;
@@ -410,9 +414,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     const long long next = tile + gridDim.x;
     if (next < a.n_tiles) prefetch(next);
     PhaseCtx<R, MF> ctx;
-    ctx.ops = (const TNC_TBL DevOp*)a.ops;
     ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
-    ctx.mrows = a.mrows;
+    ctx.rmr = a.rmrows ? a.rmrows + (size_t)batch * a.rmstride : nullptr;
     ctx.bits = a.bits;
     ctx.xpos = (size_t)batch * a.n;
     ctx.tb = 0;
@@ -494,9 +497,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT
     if (next < a.n_tiles) fetch(next, nxt);
     char* region = reinterpret_cast<char*>(cur);
     PhaseCtx<R, false> ctx;
-    ctx.ops = (const TNC_TBL DevOp*)a.ops;
     ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
-    ctx.mrows = nullptr;
+    ctx.rmr = nullptr;
     ctx.bits = a.bits;
     ctx.xpos = (size_t)batch * a.n;
     ctx.tb = 0;
@@ -594,7 +596,7 @@ static hipError_t launch_pass_r(const PassArgs& a, hipStream_t s) {
   const long long blocks = ((long long)a.n_tiles + tiles_per_block - 1) / tiles_per_block;
   const size_t lds = (size_t)kBlock * (1 << R) * sizeof(float2);
   // matrix-core updates need the four lanes of an MFMA block in one tile
-  const bool mf = a.mfma && TB >= 2 && a.mrows != nullptr;
+  const bool mf = a.mfma && TB >= 2 && a.rmrows != nullptr;
   if (!multi && a.pipeline && mf) {
     const void* fn = mf ? reinterpret_cast<const void*>(&k_pass_pipe<R, true>)
                         : reinterpret_cast<const void*>(&k_pass_pipe<R, false>);
@@ -669,9 +671,8 @@ static void emulate_pass_r(const PassArgs& a) {
         }
       }
     PhaseCtx<R, false> ctx;
-    ctx.ops = (const TNC_TBL DevOp*)a.ops;
     ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
-    ctx.mrows = a.mrows;
+    ctx.rmr = a.rmrows ? a.rmrows + (size_t)batch * a.rmstride : nullptr;
     ctx.bits = a.bits;
     ctx.xpos = (size_t)batch * a.n;
     ctx.tb = 0;

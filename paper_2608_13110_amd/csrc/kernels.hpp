@@ -213,8 +213,7 @@ __device__ __attribute__((always_inline)) inline Regs<R> op_reg_mfma(Regs<R> v, 
 template <int R, bool MF>
 struct PhaseCtx {
   const TNC_TBL float* __restrict__ rm;  // the tile's batch: resolved matrices, 16 floats per op
-  const TNC_TBL DevOp* __restrict__ ops;  // matrix-core form only (variants picked per op)
-  const float4* __restrict__ mrows;
+  const float4* __restrict__ rmr;         // the same in matrix-core rows, 8 float4 per op
   const uint8_t* bits;  // output bits, one byte per qubit per batch
   size_t xpos;          // byte offset of this tile's batch in `bits`
   uint32_t tb;
@@ -236,20 +235,6 @@ TNC_HD inline int out_bit(const uint8_t* bits, size_t pos) {
 #endif
 }
 
-// Variant index of an op from its batch's output bits.  With one tile per
-// block the index is wave-uniform, so the bit reads and the matrix loads
-// that follow are scalar.
-template <int R, bool MF>
-TNC_HD inline int op_variant(const DevOp& op, const PhaseCtx<R, MF>& c) {
-  int var = 0;
-  if (op.xrow0 >= 0) var += 2 * out_bit(c.bits, c.xpos + op.xrow0);
-  if (op.xrow1 >= 0) var += out_bit(c.bits, c.xpos + op.xrow1);
-#if defined(__HIP_DEVICE_COMPILE__)
-  if (c.uniform) var = __builtin_amdgcn_readfirstlane(var);
-#endif
-  return var;
-}
-
 // A value read at a wave-uniform address (valid only where the address is
 // the same for every lane of the wave).  Selecting between two such values
 // per lane must not be turned into a load from a per-lane address (a vector
@@ -268,9 +253,7 @@ TNC_HD inline Regs<R> stair_rest(Regs<R> v, const PhaseCtx<R, MF>& c, int op_beg
   if constexpr (B < N) {
 #if defined(__HIP_DEVICE_COMPILE__)
     if constexpr (MF) {
-      const DevOp op = c.ops[op_begin + B];
-      const int var = op_variant(op, c);
-      const float4* rows = c.mrows + ((size_t)op.mat * 4 + var) * 8;
+      const float4* rows = c.rmr + (size_t)(op_begin + B) * 8;
       v = op_reg_mfma<R, B, B - 1>(v, rows[c.lane & 3], rows[4 + (c.lane & 3)]);
       return stair_rest<R, B + 1, N, MF>(v, c, op_begin);
     }

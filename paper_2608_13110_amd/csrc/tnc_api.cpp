@@ -178,8 +178,8 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
 // after every writer), the batch's resolved update matrices and the two
 // late-phase buffers.
 struct BatchLayout {
-  uint64_t tensor = 0, scales = 0, rmats = 0, late0 = 0, late1 = 0;
-  uint64_t per_batch() const { return tensor + 2 * scales + rmats + late0 + late1; }
+  uint64_t tensor = 0, scales = 0, rmats = 0, rmrows = 0, late0 = 0, late1 = 0;
+  uint64_t per_batch() const { return tensor + 2 * scales + rmats + rmrows + late0 + late1; }
 };
 
 bool is_s16(int storage) { return storage == TNC_STORE_F16_BLOCKSCALE || storage == TNC_STORE_BF16_BLOCKSCALE; }
@@ -206,6 +206,7 @@ BatchLayout batch_layout(const Plan& p, const HostTables& t, int storage) {
     L.scales = align256((uint64_t)4 << (p.h - blk));
   }
   L.rmats = align256((uint64_t)t.ops.size() * 16 * sizeof(float));
+  if (p.opt.math == 1) L.rmrows = align256((uint64_t)t.ops.size() * 8 * sizeof(float4));
   L.late0 = t.bytes_late[0];
   L.late1 = t.bytes_late[1];
   return L;
@@ -451,6 +452,9 @@ int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k
     float* rmats = reinterpret_cast<float*>(q);
     const long long rstride = (long long)(L.rmats / 4);
     q += L.rmats * nb;
+    float4* rmrows = L.rmrows ? reinterpret_cast<float4*>(q) : nullptr;
+    const long long rmstride = (long long)(L.rmrows / 16);
+    q += L.rmrows * nb;
     double2* L0 = reinterpret_cast<double2*>(q);
     double2* L1 = reinterpret_cast<double2*>(q + L.late0 * nb);
     const uint8_t* bits = d_bits + (size_t)b0 * p.n;
@@ -471,9 +475,12 @@ int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k
     std::memset(&ra, 0, sizeof(ra));
     ra.ops = ds.d_ops;
     ra.mats = ds.d_mats;
+    ra.mrows = ds.d_mrows;
     ra.bits = bits;
     ra.rmats = rmats;
     ra.rstride = rstride;
+    ra.rmrows = rmrows;
+    ra.rmstride = rmstride;
     ra.n_ops = (int)t.ops.size();
     ra.n = p.n;
     ra.n_batches = nb;
@@ -486,6 +493,8 @@ int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k
       PassArgs a = pass_args(p, ph, ds.d_phases, ds.d_ops, ds.d_mats, ds.d_mrows, B, bits, nb);
       a.rmats = rmats;
       a.rstride = rstride;
+      a.rmrows = rmrows;
+      a.rmstride = rmstride;
       if (s16) {
         a.store = storage;
         a.scale_in = sc[cur];
