@@ -180,7 +180,8 @@ def storage_modes(torch, W, Plan, profile_begin, profile_end, batches=16):
     return res
 
 
-TUNE_CANDIDATES = [dict(), dict(max_tile_bits=12), dict(max_tile_bits=12, reg_bits=4), dict(max_tile_bits=11, reg_bits=4)]
+TUNE_CANDIDATES = [dict(), dict(max_tile_bits=12), dict(max_tile_bits=12, reg_adapt=1),
+                   dict(max_tile_bits=12, reg_bits=4), dict(max_tile_bits=11, reg_bits=4)]
 
 
 def serving_bench(torch, W, count=512, load=0.8):

@@ -91,7 +91,10 @@ typedef struct {
   int32_t late_fold;     /* k >= 1: late removals folded on the host into the join launch
                             (0: automatic, 3 for boundary tensors of 2^26 entries or more,
                             else none; -1: none; 1..3: that many) */
-  int32_t reserved[2];
+  int32_t reg_adapt;     /* 1: a pass takes reg_bits - 1 when that needs no more register
+                            phases and its tile fits 256 threads (more resident waves);
+                            0: every pass uses reg_bits (default) */
+  int32_t reserved[1];
 } tnc_options;
 
 typedef struct {

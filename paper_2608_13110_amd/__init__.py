@@ -60,7 +60,8 @@ class Gate2(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("max_tile_bits", ctypes.c_int32), ("reg_bits", ctypes.c_int32),
                 ("low_bits", ctypes.c_int32), ("math", ctypes.c_int32),
-                ("pipeline", ctypes.c_int32), ("late_fold", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("pipeline", ctypes.c_int32), ("late_fold", ctypes.c_int32), ("reg_adapt", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class Info(ctypes.Structure):
@@ -181,7 +182,7 @@ def _gate_array(gates: Sequence):
 def _options(options: dict) -> Options:
     return Options(int(options.get("max_tile_bits", 0)), int(options.get("reg_bits", 0)),
                    int(options.get("low_bits", 0)), int(options.get("math", 0)), int(options.get("pipeline", 0)),
-                   int(options.get("late_fold", 0)))
+                   int(options.get("late_fold", 0)), int(options.get("reg_adapt", 0)))
 
 
 class Plan:

@@ -620,7 +620,19 @@ std::vector<Pass> plan_passes(const Plan& p, const std::vector<SweepOp>& ops, in
     ps.w = ws[best_w];
     ps.op_begin = i;
     ps.op_end = i + best_len;
-    plan_phases(ps, ops, R);
+    const int T = ps.w.tile_bits();
+    ps.R = pass_reg_bits(R, T);
+    plan_phases(ps, ops, ps.R);
+    // Fewer entries per thread leave registers for more resident waves:
+    // take one register bit less when the pass needs no more phases with
+    // it and a tile still fits one 256-thread block.
+    if (p.opt.reg_adapt == 1 && ps.R >= 3 && T - (ps.R - 1) <= 8) {
+      Pass alt = ps;
+      alt.R = ps.R - 1;
+      alt.phases.clear();
+      plan_phases(alt, ops, alt.R);
+      if (alt.phases.size() == ps.phases.size()) ps = alt;
+    }
     passes.push_back(ps);
     i += best_len;
   }

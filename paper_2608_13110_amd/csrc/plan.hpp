@@ -109,6 +109,7 @@ struct Phase {
 struct Pass {
   Window w;
   int op_begin = 0, op_end = 0;
+  int R = 0;  // register bits of this pass's phases
   std::vector<Phase> phases;
 };
 
@@ -119,6 +120,7 @@ struct Options {
   int math = 0;             // 0: vector ALU updates; 1: register-controlled updates on the matrix cores
   int pipeline = 0;         // 1: persistent, prefetching pass blocks where a block holds one tile
   int late_fold = 0;        // removals folded into the join launch (0 auto, -1 none, 1..3)
+  int reg_adapt = 0;        // 1: a pass uses reg_bits - 1 when that needs no more phases; 0: never
 };
 
 // Everything that depends on k (the number of open output legs).

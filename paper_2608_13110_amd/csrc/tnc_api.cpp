@@ -86,7 +86,7 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
   for (const Pass& ps : s.passes) {
     PassHost ph;
     ph.w = ps.w;
-    ph.R = pass_reg_bits(s.reg_bits, ps.w.tile_bits());
+    ph.R = ps.R;
     ph.phase_off = int(t->phases.size());
     ph.n_phases = int(ps.phases.size());
     ph.op_begin = ps.op_begin;
@@ -724,10 +724,11 @@ int tnc_plan(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, c
     o.math = opt->math;
     o.pipeline = opt->pipeline;
     o.late_fold = opt->late_fold;
+    o.reg_adapt = opt->reg_adapt;
   }
   if (o.max_tile_bits < 6 || o.max_tile_bits > 13 || o.reg_bits < 1 || o.reg_bits > 5 || o.low_bits < 1 ||
       o.low_bits > o.max_tile_bits - 2 || o.math < 0 || o.math > 1 || o.pipeline < 0 || o.pipeline > 1 ||
-      o.late_fold < -1 || o.late_fold > 3 ||
+      o.late_fold < -1 || o.late_fold > 3 || o.reg_adapt < 0 || o.reg_adapt > 1 ||
       o.max_tile_bits - o.reg_bits > (o.pipeline && o.math == 0 ? 9 : 8))
     return set_err(TNC_E_INVALID, "tile options out of range");
   if (n < 2 || d < 2 || (int64_t)n * (d + 1) > (1 << 24)) return set_err(TNC_E_DOMAIN, "need n >= 2, d >= 2");

@@ -109,7 +109,9 @@ def test_host_execution_matches_oracle(n, d, fp, dense):
 TILES = [dict(max_tile_bits=6, low_bits=2, reg_bits=3), dict(max_tile_bits=6, low_bits=1, reg_bits=5),
          dict(max_tile_bits=7, low_bits=3, reg_bits=2), dict(max_tile_bits=8, low_bits=4, reg_bits=4), None,
          # late removals folded into the join launch (the default for large tensors)
-         dict(late_fold=3), dict(late_fold=1, max_tile_bits=8, low_bits=3, reg_bits=4)]
+         dict(late_fold=3), dict(late_fold=1, max_tile_bits=8, low_bits=3, reg_bits=4),
+         # passes narrowed to reg_bits - 1 where that costs no phase
+         dict(reg_adapt=1, max_tile_bits=8, low_bits=4, reg_bits=5)]
 
 
 @pytest.mark.parametrize("opts", TILES)
