@@ -256,6 +256,12 @@ def serving_bench(torch, W, count=512, load=0.8):
         th.join()
         served_s = time.perf_counter() - t0
         summ = srv.summary()
+        # saturated: the whole stream at once (capacity of the served path)
+        t1 = time.perf_counter()
+        ids = [srv.submit(r["circuit"], r["bits"], r["k"]) for r in reqs]
+        for i in ids:
+            srv.wait(i)
+        sat_s = time.perf_counter() - t1
     return {
         "workload": f"{count} Poisson requests, n in 24..56, even d in 20..48 (w 10..24), k in 0..8, "
                     f"1 bitstring each; arrival rate {load} x sequential capacity",
@@ -267,6 +273,8 @@ def serving_bench(torch, W, count=512, load=0.8):
                    "max_inflight": summ["max_inflight"], "capture_failures": summ["capture_failures"],
                    "graph_launches": summ["graph_launches"] - warm["graph_launches"],
                    "plain_launches": summ["plain_launches"] - warm["plain_launches"]},
+        "saturated": {"amplitudes_per_s": round(amps / sat_s, 1), "requests_per_s": round(count / sat_s, 1),
+                      "vs_sequential": round(seq_total / sat_s, 3)},
         "tuning": {str(h): o for h, o in tuning.items()},
     }
 
