@@ -87,7 +87,8 @@ typedef struct {
   int32_t math;          /* 0: vector-ALU updates (default); 1: matrix-core updates
                             (v_mfma_f32_4x4x1_16b_f32) where a block holds one tile */
   int32_t pipeline;      /* 0: one tile per block (default); 1: persistent blocks that prefetch
-                            the next tile into LDS while updating the current one */
+                            the next tile into LDS while updating the current one; 2: persistent
+                            blocks that prefetch the next tile into registers */
   int32_t late_fold;     /* k >= 1: late removals folded on the host into the join launch
                             (0: automatic, 3 for boundary tensors of 2^26 entries or more,
                             else none; -1: none; 1..3: that many) */
@@ -294,6 +295,11 @@ const char* tnc_last_error(void);
 int tnc_debug_execute_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, tnc_c128* out);
 int tnc_debug_emulate_device(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, int32_t storage,
                              tnc_c128* out);
+
+/* Host self-check of the serving loop's device-arena allocator: n_ops
+ * seeded random allocations and releases, checked for overlap, bounds and
+ * full coalescing at the end.  TNC_OK or TNC_E_INVALID (message says why). */
+int tnc_debug_arena_check(uint64_t seed, int32_t n_ops);
 
 #ifdef __cplusplus
 }

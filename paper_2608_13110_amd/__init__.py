@@ -38,7 +38,7 @@ EXPORTED = [
     "tnc_amplitudes_host", "tnc_logxeb", "tnc_release", "tnc_strerror", "tnc_last_error",
     "tnc_debug_execute_host", "tnc_debug_emulate_device", "tnc_profile_begin", "tnc_profile_end",
     "tnc_autotune", "tnc_server_create", "tnc_server_destroy", "tnc_server_set_tuning", "tnc_server_submit",
-    "tnc_server_wait", "tnc_server_summary",
+    "tnc_server_wait", "tnc_server_summary", "tnc_debug_arena_check",
 ]
 
 
@@ -148,6 +148,7 @@ def lib() -> ctypes.CDLL:
     L.tnc_server_submit.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, i32, i32, vp, ctypes.POINTER(u64)]
     L.tnc_server_wait.argtypes = [vp, u64, ctypes.POINTER(RequestStats)]
     L.tnc_server_summary.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.tnc_debug_arena_check.argtypes = [u64, i32]
     for name in EXPORTED:
         if name not in ("tnc_release", "tnc_strerror", "tnc_last_error", "tnc_server_destroy"):
             getattr(L, name).restype = ctypes.c_int

@@ -200,8 +200,9 @@ hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s) {
 //   LDS -> HBM, in place.
 // WU: every wave lies inside one tile (one tile per block, or T - R >= 6),
 // so the batch and everything read through it are wave-uniform.
-template <int R, bool MULTI, bool MF, bool WU>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MF ? 2 : 1))) void k_pass(PassArgs a) {
+// NT: threads per block (256; 512 for one 2^(R+9)-entry tile per block).
+template <int R, bool MULTI, bool MF, bool WU, int NT = kBlock>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MF ? 2 : 1))) void k_pass(PassArgs a) {
   extern __shared__ float2 lds[];
   constexpr int E = 1 << R;
   const int T = a.T;
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MF ? 2 :
   const int tid = threadIdx.x;
   const int tile_in_block = MULTI ? (tid >> TB) : 0;
   const uint32_t tt = MULTI ? (uint32_t)(tid & ((1 << TB) - 1)) : (uint32_t)tid;
-  const int tiles_per_block = MULTI ? (kBlock >> TB) : 1;
+  const int tiles_per_block = MULTI ? (NT >> TB) : 1;
   const long long tile = (long long)blockIdx.x * tiles_per_block + tile_in_block;
   const bool active = tile < a.n_tiles;
   const int tbits = a.h - T;
@@ -288,12 +289,19 @@ __global__ __launch_bounds__(kBlock) void k_pass16(PassArgs a) {
   const bool two = T > blk_bits;
   if (tid < 2 * tiles_per_block) smax[tid] = 0u;
 
+  // A scale slot gathers bit fields of the entry index, and the block part
+  // (boff), the thread part (tt) and the iteration part (it) of an entry's
+  // index occupy disjoint bits, so its slot is the OR of the three parts'
+  // slots; the iteration part is the same for every thread (scalar work).
+  const uint64_t slot_t = scale_slot(boff, a.in_map) |
+                          scale_slot(tile_offset(tt * (uint32_t)U, a.lo_bits, a.win_lo), a.in_map);
   if (active) {
 #pragma unroll
     for (int it = 0; it < E / U; ++it) {
       const uint32_t i = (uint32_t)(it * tpt + (int)tt) * (uint32_t)U;
       const uint64_t g = boff + tile_offset(i, a.lo_bits, a.win_lo);
-      const float sc = sin[scale_slot(g, a.in_map)];
+      const uint64_t slot_i = scale_slot(tile_offset((uint32_t)(it * tpt) * (uint32_t)U, a.lo_bits, a.win_lo), a.in_map);
+      const float sc = sin[slot_t | slot_i];
       if constexpr (U == 4) {
         const uint4 w = *reinterpret_cast<const uint4*>(Bw + g);
         const float2 e0 = unpack16<S>(w.x, sc), e1 = unpack16<S>(w.y, sc);
@@ -371,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_pass16(PassArgs a) {
 // after the current tile has been staged in LDS, so they are in flight while
 // the current tile's register phases run.
 template <int R, bool MF>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pass_pipe(PassArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_pass_pipe(PassArgs a) {
   extern __shared__ float2 lds[];
   constexpr int E = 1 << R;
   constexpr int HALF = E / 2;
@@ -583,12 +591,18 @@ static hipError_t launch_pass_r(const PassArgs& a, hipStream_t s) {
   if (a.store == STORE_F16) return launch_pass16_rs<R, STORE_F16>(a, s);
   if (a.store == STORE_BF16) return launch_pass16_rs<R, STORE_BF16>(a, s);
   const int TB = a.T - R;
-  const bool dma_ok = a.pipeline && !a.mfma;
+  const bool dma_ok = a.pipeline == 1 && !a.mfma;
   if constexpr (R >= 4) {
     if (dma_ok && TB == 8) return launch_pass_dma<R, 256>(a, s);
   }
   if constexpr (R == 4) {
     if (dma_ok && TB == 9) return launch_pass_dma<R, 512>(a, s);
+  }
+  if (TB == 9 && !a.mfma) {
+    // one 2^(R+9)-entry tile per 512-thread block
+    const size_t lds9 = (size_t)512 * (1 << R) * sizeof(float2);
+    hipLaunchKernelGGL((k_pass<R, false, false, true, 512>), dim3((unsigned)a.n_tiles), dim3(512), lds9, s, a);
+    return hipGetLastError();
   }
   if (TB < 0 || TB > 8) return hipErrorInvalidValue;
   const bool multi = TB < 8;
@@ -597,7 +611,9 @@ static hipError_t launch_pass_r(const PassArgs& a, hipStream_t s) {
   const size_t lds = (size_t)kBlock * (1 << R) * sizeof(float2);
   // matrix-core updates need the four lanes of an MFMA block in one tile
   const bool mf = a.mfma && TB >= 2 && a.rmrows != nullptr;
-  if (!multi && a.pipeline && mf) {
+  // persistent blocks with the next tile prefetched into registers
+  // (pipeline = 2; the matrix-core form uses them for pipeline = 1 too)
+  if (!multi && (a.pipeline == 2 || (a.pipeline && mf))) {
     const void* fn = mf ? reinterpret_cast<const void*>(&k_pass_pipe<R, true>)
                         : reinterpret_cast<const void*>(&k_pass_pipe<R, false>);
     static int per_cu[2][8] = {{0}};
@@ -813,11 +829,102 @@ __global__ __launch_bounds__(kBlock) void k_late(LateArgs a) {
   }
 }
 
+// The same contraction on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
+// a 64 x 64 output tile per 256-thread block, 32 x 32 (2 x 2 MFMA tiles)
+// per wave; the complex product takes four real MFMAs per tile and k-step
+// (re += ar*br - ai*bi, im += ar*bi + ai*br).  Lane l supplies A[l%16][k]
+// and B[k][l%16] with k = l/16 and receives D[l/16 + 4q][l%16], q < 4.
+typedef double tnc_d4 __attribute__((ext_vector_type(4)));
+
+template <typename TIn, int S>
+__global__ __launch_bounds__(kBlock) void k_late_mf(LateArgs a) {
+  __shared__ double2 As[16][65];
+  __shared__ double2 Bs[16][65];
+  const int b = blockIdx.y;
+  const int tilesN = (a.N + 63) / 64;
+  const int tilesM = (a.M + 63) / 64;
+  const int xcd = blockIdx.x & 7;
+  const int g = blockIdx.x >> 3;
+  const int bn = g % tilesN;
+  const int bm = (g / tilesN) * 8 + xcd;
+  if (bm >= tilesM) return;
+  const int row0 = bm * 64, col0 = bn * 64;
+  const int var = a.xrow >= 0 ? (int)a.bits[(size_t)b * a.n + a.xrow] : 0;
+  const double2* __restrict__ J = a.J + (size_t)var * a.K * a.N;
+  const TIn* __restrict__ in = reinterpret_cast<const TIn*>(a.in) + (size_t)b * a.in_batch_stride;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  tnc_d4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = tnc_d4{0.0, 0.0, 0.0, 0.0};
+      ci[i][j] = tnc_d4{0.0, 0.0, 0.0, 0.0};
+    }
+  for (int k0 = 0; k0 < a.K; k0 += 16) {
+    for (int e = tid; e < 1024; e += kBlock) {
+      const int r = e >> 4, kk = e & 15;
+      const int row = row0 + r;
+      double2 val = make_double2(0.0, 0.0);
+      if (row < a.M && k0 + kk < a.K) val = late_in<TIn, S>(a, in, b, (uint64_t)row * a.K + k0 + kk);
+      As[kk][r] = val;
+    }
+    for (int e = tid; e < 1024; e += kBlock) {
+      const int kk = e >> 6, c = e & 63;
+      const int col = col0 + c;
+      double2 val = make_double2(0.0, 0.0);
+      if (col < a.N && k0 + kk < a.K) val = J[(size_t)(k0 + kk) * a.N + col];
+      Bs[kk][c] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      const int kk = kc * 4 + lk;
+      double2 av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = As[kk][wr + 16 * i + li];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = Bs[kk][wc + 16 * j + li];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, cr[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[i].y, bv[j].y, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].y, ci[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].x, ci[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  double2* out = a.out + (size_t)b * a.out_batch_stride;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = row0 + wr + 16 * i + lk + 4 * q;
+        const int col = col0 + wc + 16 * j + li;
+        if (row < a.M && col < a.N) out[(size_t)row * a.N + col] = make_double2(cr[i][j][q], ci[i][j][q]);
+      }
+}
+
 hipError_t launch_late(const LateArgs& a, bool in_c64, hipStream_t s) {
   const long long tilesM8 = ((long long)(a.M + 63) / 64 + 7) / 8 * 8;
   const long long tiles = tilesM8 * ((a.N + 63) / 64);
   if (tiles > 0x7fffffffLL || a.n_batches > 65535) return hipErrorInvalidValue;
   dim3 grid((unsigned)tiles, (unsigned)a.n_batches);
+  // matrix cores for contractions large enough to fill their 16 x 16 tiles
+  if (in_c64 && a.N >= 32 && a.K >= 16 && a.M >= 64) {
+    if (a.store == STORE_F16) hipLaunchKernelGGL((k_late_mf<uint32_t, STORE_F16>), grid, dim3(kBlock), 0, s, a);
+    else if (a.store == STORE_BF16) hipLaunchKernelGGL((k_late_mf<uint32_t, STORE_BF16>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_late_mf<float2, STORE_C64>), grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+  }
   if (!in_c64) hipLaunchKernelGGL((k_late<double2, STORE_C64>), grid, dim3(kBlock), 0, s, a);
   else if (a.store == STORE_F16) hipLaunchKernelGGL((k_late<uint32_t, STORE_F16>), grid, dim3(kBlock), 0, s, a);
   else if (a.store == STORE_BF16) hipLaunchKernelGGL((k_late<uint32_t, STORE_BF16>), grid, dim3(kBlock), 0, s, a);

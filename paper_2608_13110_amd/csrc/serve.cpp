@@ -611,6 +611,47 @@ int tnc_server_summary(tnc_server_t sv, tnc_server_stats* st) {
   return TNC_OK;
 }
 
+int tnc_debug_arena_check(uint64_t seed, int32_t n_ops) {
+  // random first-fit allocations and releases against an explicit model:
+  // no two live blocks overlap, every block lies inside the arena, and
+  // after releasing everything the free space is one block again
+  if (n_ops < 0) return TNC_E_INVALID;
+  const uint64_t size = 1ull << 24;
+  Arena ar(size);
+  std::map<uint64_t, uint64_t> live;  // offset -> bytes
+  uint64_t x = seed * 0x9E3779B97F4A7C15ull + 1;
+  auto rnd = [&]() {
+    x ^= x << 13;
+    x ^= x >> 7;
+    x ^= x << 17;
+    return x;
+  };
+  for (int i = 0; i < n_ops; ++i) {
+    if (live.empty() || rnd() % 3 != 0) {
+      const uint64_t bytes = 1 + rnd() % (size / 16);
+      const uint64_t off = ar.alloc(bytes);
+      if (off == UINT64_MAX) continue;
+      const uint64_t len = (bytes + 255) & ~uint64_t(255);
+      if (off % 256 != 0 || off + len > size) return set_error_message(TNC_E_INVALID, "block outside the arena");
+      auto nx = live.lower_bound(off);
+      if (nx != live.end() && nx->first < off + len) return set_error_message(TNC_E_INVALID, "overlap");
+      if (nx != live.begin()) {
+        auto pv = std::prev(nx);
+        if (pv->first + pv->second > off) return set_error_message(TNC_E_INVALID, "overlap");
+      }
+      live[off] = len;
+    } else {
+      auto it = live.begin();
+      std::advance(it, (long)(rnd() % live.size()));
+      ar.release(it->first);
+      live.erase(it);
+    }
+  }
+  for (auto& kv : live) ar.release(kv.first);
+  if (ar.largest() != size) return set_error_message(TNC_E_INVALID, "free space not coalesced");
+  return TNC_OK;
+}
+
 void tnc_server_destroy(tnc_server_t sv) {
   if (!sv) return;
   ServerImpl& S = *sv->impl;

@@ -59,29 +59,86 @@ struct HostTables {
   uint64_t bytes_late[2] = {0, 0};
 };
 
+// FP32 form of an update matrix K (FP64), 8 floats (re, im) row-major.
+// Every update acts on the whole boundary tensor, so a rounding bias shared
+// by a matrix's entries multiplies every amplitude: 1/sqrt(2) rounds to
+// nearest 1.7e-8 low, and the ~900 Hadamard-like factors of a width-33
+// sweep would scale every amplitude by 1 - 1.5e-5.  Each component is
+// therefore rounded down or up (the two FP32 neighbours of its value),
+// choosing among those combinations the one whose least-squares factor
+// rho = <K, K32> / <K, K> best cancels the bias accumulated so far (`acc`,
+// the running sum of rho - 1 over the sweep's earlier updates).  Returns
+// the chosen rho - 1.
+cd round_matrix(const M2& K, const cd& acc, float* out) {
+  double nk = 0;
+  for (int e = 0; e < 4; ++e) nk += std::norm(K.a[e]);
+  double v[8];
+  float lo[8], hi[8];
+  int free_bits[8], nfree = 0;
+  for (int e = 0; e < 4; ++e) {
+    v[2 * e] = K.a[e].real();
+    v[2 * e + 1] = K.a[e].imag();
+  }
+  for (int q = 0; q < 8; ++q) {
+    const float f = (float)v[q];
+    lo[q] = hi[q] = f;
+    if ((double)f != v[q]) {
+      const float g = std::nextafter(f, (double)f < v[q] ? INFINITY : -INFINITY);
+      lo[q] = f;
+      hi[q] = g;
+      free_bits[nfree++] = q;
+    }
+  }
+  float best[8];
+  std::copy(lo, lo + 8, best);
+  cd best_rho = 0;
+  double best_err = 1e300;
+  const int combos = 1 << nfree;
+  for (int m = 0; m < combos; ++m) {
+    float f[8];
+    std::copy(lo, lo + 8, f);
+    for (int b = 0; b < nfree; ++b)
+      if (m >> b & 1) f[free_bits[b]] = hi[free_bits[b]];
+    cd dot = 0;
+    for (int e = 0; e < 4; ++e) dot += std::conj(K.a[e]) * cd(f[2 * e], f[2 * e + 1]);
+    const cd rho = nk > 0 ? dot / nk - 1.0 : cd(0);
+    // cancel the running bias; among equals prefer the smaller own bias
+    const double err = std::abs(acc + rho) + 1e-3 * std::abs(rho);
+    if (err < best_err) {
+      best_err = err;
+      best_rho = rho;
+      std::copy(f, f + 8, best);
+    }
+  }
+  std::copy(best, best + 8, out);
+  return best_rho;
+}
+
 int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
   const size_t nops = s.ops.size();
   t->ops.resize(nops);
   t->mats.assign(nops * 4 * 16, 0.f);
   t->mrows.assign(nops * 4 * 8, make_float4(0.f, 0.f, 0.f, 0.f));
+  cd acc = 0;  // running rounding bias of the sweep (sum of rho - 1)
   for (size_t o = 0; o < nops; ++o) {
     const SweepOp& op = s.ops[o];
+    cd step = 0;
     for (int var = 0; var < 4; ++var)
       for (int c = 0; c < 2; ++c) {
-        const M2& K = op.mat[var][c];
-        for (int e = 0; e < 4; ++e) {
-          t->mats[(o * 4 + var) * 16 + c * 8 + 2 * e] = (float)K.a[e].real();
-          t->mats[(o * 4 + var) * 16 + c * 8 + 2 * e + 1] = (float)K.a[e].imag();
-        }
-        // real form on (re b0, im b0, re b1, im b1): rows (re o0, im o0, re o1, im o1)
+        const cd r = round_matrix(op.mat[var][c], acc, t->mats.data() + (o * 4 + var) * 16 + c * 8);
+        if (var == 0 && c == 0) step = r;
+        // real form on (re b0, im b0, re b1, im b1): rows (re o0, im o0, re o1, im o1),
+        // from the same rounded values
+        const float* f = t->mats.data() + (o * 4 + var) * 16 + c * 8;
         for (int r = 0; r < 2; ++r) {
-          const cd k0 = K(r, 0), k1 = K(r, 1);
+          const cd k0(f[4 * r], f[4 * r + 1]), k1(f[4 * r + 2], f[4 * r + 3]);
           t->mrows[((o * 4 + var) * 2 + c) * 4 + 2 * r] =
               make_float4((float)k0.real(), (float)-k0.imag(), (float)k1.real(), (float)-k1.imag());
           t->mrows[((o * 4 + var) * 2 + c) * 4 + 2 * r + 1] =
               make_float4((float)k0.imag(), (float)k0.real(), (float)k1.imag(), (float)k1.real());
         }
       }
+    acc += step;
   }
   for (const Pass& ps : s.passes) {
     PassHost ph;
@@ -97,7 +154,7 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
       return TNC_E_INVALID;
     };
     // 256 threads per tile (T - R = 8), or 512 with the prefetching kernel
-    if (ps.w.tile_bits() - R > (p.opt.pipeline && p.opt.math == 0 ? 9 : 8))
+    if (ps.w.tile_bits() - R > (p.opt.math == 0 ? 9 : 8))
       return fail_t("pass tile too large for the thread block");
     if (!(ps.w.lo_bits >= 1 || ps.w.win_lo == 0)) return fail_t("pass tile lacks slot 0");
     for (const Phase& pp : ps.phases) {
@@ -217,8 +274,11 @@ BatchLayout batch_layout(const Plan& p, const HostTables& t, int storage) {
 int check_storage(const HostTables& t, int storage) {
   if (storage != TNC_STORE_C64 && !is_s16(storage)) return set_err(TNC_E_INVALID, "unknown storage mode");
   if (is_s16(storage))
-    for (const PassHost& ph : t.passes)
+    for (const PassHost& ph : t.passes) {
       if (ph.w.lo_bits == 1) return set_err(TNC_E_INVALID, "16-bit storage needs low_bits >= 2");
+      if (ph.w.tile_bits() - ph.R > 8)
+        return set_err(TNC_E_INVALID, "16-bit storage needs max_tile_bits - reg_bits <= 8");
+    }
   return TNC_OK;
 }
 
@@ -726,10 +786,10 @@ int tnc_plan(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, c
     o.late_fold = opt->late_fold;
     o.reg_adapt = opt->reg_adapt;
   }
-  if (o.max_tile_bits < 6 || o.max_tile_bits > 13 || o.reg_bits < 1 || o.reg_bits > 5 || o.low_bits < 1 ||
-      o.low_bits > o.max_tile_bits - 2 || o.math < 0 || o.math > 1 || o.pipeline < 0 || o.pipeline > 1 ||
+  if (o.max_tile_bits < 6 || o.max_tile_bits > 14 || o.reg_bits < 1 || o.reg_bits > 5 || o.low_bits < 1 ||
+      o.low_bits > o.max_tile_bits - 2 || o.math < 0 || o.math > 1 || o.pipeline < 0 || o.pipeline > 2 ||
       o.late_fold < -1 || o.late_fold > 3 || o.reg_adapt < 0 || o.reg_adapt > 1 ||
-      o.max_tile_bits - o.reg_bits > (o.pipeline && o.math == 0 ? 9 : 8))
+      o.max_tile_bits - o.reg_bits > (o.math == 0 && o.pipeline != 2 ? 9 : 8))
     return set_err(TNC_E_INVALID, "tile options out of range");
   if (n < 2 || d < 2 || (int64_t)n * (d + 1) > (1 << 24)) return set_err(TNC_E_DOMAIN, "need n >= 2, d >= 2");
   std::vector<cd> one((size_t)(d + 1) * n * 4);

@@ -79,12 +79,19 @@ SMALL = [
     (13, 25, 0, 0.0, 8, 3, dict(max_tile_bits=6, low_bits=1, reg_bits=5)),
     (16, 30, 1, 0.0, 4, 8, None),
     (14, 29, 0, 0.3, 2, 6, None),
+    (10, 8, 1, 0.3, 4, 3, None),   # 2k = d: no late layer beyond the early region
+    (6, 12, 0, 0.5, 5, 2, None),   # k = n - 1: one fixed row
     (16, 30, 1, 0.3, 4, 8, dict(math=1)),
     (12, 24, 0, 0.3, 6, 4, dict(max_tile_bits=8, low_bits=4, reg_bits=4, math=1)),
     # persistent prefetching pass blocks: 256 threads x 32, 512 x 16, 256 x 16
     (16, 30, 1, 0.3, 4, 8, dict(pipeline=1)),
     (16, 30, 0, 0.3, 3, 8, dict(pipeline=1, reg_bits=4)),
     (16, 31, 1, 0.3, 2, 8, dict(pipeline=1, reg_bits=4, max_tile_bits=12)),
+    # one 2^14-entry tile per 512-thread block, 64-byte low runs
+    (17, 32, 1, 0.3, 4, 4, dict(max_tile_bits=14, low_bits=3)),
+    # persistent blocks prefetching into registers
+    (16, 30, 1, 0.3, 4, 8, dict(pipeline=2, reg_bits=4, max_tile_bits=12)),
+    (15, 29, 0, 0.3, 3, 8, dict(pipeline=2, reg_bits=3, max_tile_bits=11)),
 ]
 
 
@@ -98,7 +105,9 @@ def test_small_circuits(n, d, fp, dense, k, nb, opts):
     assert_close(got, ref, n)
 
 
-@pytest.mark.parametrize("opts", [None, dict(pipeline=1), dict(pipeline=1, reg_bits=4)])
+@pytest.mark.parametrize("opts", [None, dict(pipeline=1), dict(pipeline=1, reg_bits=4),
+                                  dict(pipeline=2, reg_bits=4, max_tile_bits=12),
+                                  dict(max_tile_bits=14, low_bits=3)])
 def test_medium_config_restriction(opts):
     # medium workload (d = 40, w = 20), restricted to 24 qubits, 64 batches,
     # k = 6: 8192 tiles per pass, so persistent blocks loop over many tiles
@@ -135,26 +144,36 @@ def test_precision_config_restriction():
     assert_close(got, ref, c.n)
 
 
-def test_full_width_restriction():
+@pytest.mark.parametrize("opts", [None, dict(max_tile_bits=12), dict(max_tile_bits=14, low_bits=3)])
+def test_full_width_restriction(opts):
     # full-width shape (d = 66, w = 33: a 2^33 complex64 boundary tensor)
-    # restricted to 22 qubits, k = 8, the launch configuration of the benchmark
+    # restricted to 22 qubits, k = 8, in the tile configurations the
+    # benchmark's autotuner chooses from
     from paper_2608_13110_amd import Plan
     c = W.restrict(W.config_circuit(4), 22)
     bits = W.config_bitstrings(4)[:1, :22]
     ref = oracle.amplitudes(c, bits, 8)
-    got = gpu_amps(Plan.from_circuit(c), bits, 8)
+    got = gpu_amps(Plan.from_circuit(c, opts), bits, 8)
     assert_close(got, ref, c.n)
 
 
-@pytest.mark.parametrize("n,d,k", [(70, 20, 0), (70, 21, 4), (40, 33, 8)])
-def test_full_size_clifford_matches_tableau(n, d, k):
+@pytest.mark.parametrize("n,d,k,opts", [(70, 20, 0, None), (70, 21, 4, None), (40, 33, 8, None),
+                                         # the full-width shape itself (2^33-entry tensor, 81 GiB
+                                         # of workspace) in the benchmark's tile configuration
+                                         (70, 66, 8, dict(max_tile_bits=12))])
+def test_full_size_clifford_matches_tableau(n, d, k, opts):
     from paper_2608_13110_amd import Plan
     c = W.brickwork_circuit(n, d, 0, W.rng_for(402, n, d))
     _, words = W.clifford_table()
     tab = tableau.run_clifford(c, words)
     rng = W.rng_for(402, 1)
-    bits = np.stack([tab.sample(rng) for _ in range(3)] + list(W.random_bitstrings(n, 2, rng)))
-    got = gpu_amps(Plan.from_circuit(c), bits, k)
+    big = d > 60
+    bits = np.stack([tab.sample(rng) for _ in range(1 if big else 3)] + list(W.random_bitstrings(n, 1 if big else 2, rng)))
+    p = Plan.from_circuit(c, opts)
+    kw = {}
+    if big:  # one batch of workspace at a time (the batches run in groups)
+        kw["workspace"] = torch.empty(p.workspace_bytes(k, 1), dtype=torch.uint8, device="cuda")
+    got = gpu_amps(p, bits, k, **kw)
     for row, amps in zip(bits, got):
         for b in range(0, 1 << k, max(1, (1 << k) // 8)):
             x = row.copy()
@@ -256,3 +275,13 @@ def test_block_scaled_storage_needs_two_low_slots():
     with pytest.raises(TncError) as e:
         p.workspace_bytes(3, 1, 1)
     assert e.value.code == TNC_E_INVALID
+
+
+def test_empty_batch():
+    from paper_2608_13110_amd import Plan
+    c = H.mixed_circuit(10, 12, 7)
+    p = Plan.from_circuit(c)
+    bits = torch.zeros((0, c.n), dtype=torch.uint8, device="cuda")
+    out = p.amplitudes(bits, 3, workspace=torch.empty(p.workspace_bytes(3, 1), dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    assert tuple(out.shape) == (0, 8)

@@ -128,6 +128,17 @@ def test_device_emulation_matches_oracle(opts, n, d, fp):
         assert per < H.TOL_C64 and l2 < H.TOL_C64, (k, per, l2)
 
 
+def test_device_emulation_large_tiles():
+    # 2^14-entry tiles (512 threads of 32 entries) with 64-byte low runs
+    c = H.mixed_circuit(17, 32, 171, dense=0.3)
+    bits = W.random_bitstrings(17, 2, W.rng_for(311, 1))
+    for k in (0, 4):
+        ref = oracle.amplitudes(c, bits, k)
+        got = Plan.from_circuit(c, dict(max_tile_bits=14, low_bits=3)).debug_emulate_device(bits, k)
+        per, l2 = H.amp_errors(got, ref, 17)
+        assert per < H.TOL_C64 and l2 < H.TOL_C64, (k, per, l2)
+
+
 @pytest.mark.parametrize("n,d", [(30, 12), (40, 9), (24, 16)])
 def test_emulation_matches_tableau_at_full_size(n, d):
     # T-free Clifford circuits at n beyond the state vector: |psi|^2 from the
@@ -172,3 +183,10 @@ def test_block_scaled_storage_is_rejected_with_one_low_slot():
     p = Plan.from_circuit(c, dict(max_tile_bits=8, low_bits=1, reg_bits=3))
     with pytest.raises(TncError):
         p.debug_emulate_device(W.random_bitstrings(14, 1, W.rng_for(310)), 2, 1)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_serving_arena_allocator(seed):
+    # the serving loop's first-fit device-arena allocator, on the host
+    from paper_2608_13110_amd import _check
+    _check(lib().tnc_debug_arena_check(seed, 5000))
