@@ -64,8 +64,15 @@ static_assert(sizeof(DevPhase) == 16, "DevPhase layout");
 //   mrows: per op [var 4][ctl 2][row 4][4]: the real 4x4 form of the same
 //          2x2, acting on (re b0, im b0, re b1, im b1); row r feeds the
 //          matrix-core update's A operand of lane r (mod 4)
+// Entries of a phase's LDS offset table (one per register entry, up to 2^5).
+constexpr int kPhaseOffs = 32;
+
 struct PassArgs {
   const DevPhase* phases;
+  // per phase of the pass: kPhaseOffs byte offsets in the LDS tile of the
+  // phase's register entries (tile index with register bits = the entry's
+  // bits, after the LDS swizzle)
+  const uint32_t* poffs;
   const DevOp* ops;
   const float* mats;
   const float4* mrows;

@@ -240,9 +240,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MF ? 2 : 1))
   ctx.tb = 0;
   ctx.lane = tid & 63;
   ctx.uniform = WU;
+  const uint32_t rbase = (uint32_t)tile_in_block << (T + 3);
   for (int p = 0; p < a.n_phases; ++p) {
     const DevPhase P = load_phase(a.phases, p);
-    phase_dispatch<R, MF>(region, P, ctx, tt, tmask);
+    phase_dispatch<R, MF>(reinterpret_cast<char*>(lds), rbase, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs,
+                          ctx, tt, tmask);
     __syncthreads();
   }
 
@@ -328,7 +330,8 @@ __global__ __launch_bounds__(kBlock) void k_pass16(PassArgs a) {
   ctx.uniform = WU;
   for (int p = 0; p < a.n_phases; ++p) {
     const DevPhase P = load_phase(a.phases, p);
-    phase_dispatch<R, false>(region, P, ctx, tt, tmask);
+    phase_dispatch<R, false>(reinterpret_cast<char*>(lds), (uint32_t)tile_in_block << (T + 3), P,
+                             (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, tmask);
     __syncthreads();
   }
 
@@ -431,7 +434,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     ctx.uniform = true;
     for (int p = 0; p < a.n_phases; ++p) {
       const DevPhase P = load_phase(a.phases, p);
-      phase_dispatch<R, MF>(region, P, ctx, tt, tmask);
+      phase_dispatch<R, MF>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, tmask);
       __syncthreads();
     }
     float2* dst = tile_base(tile);
@@ -514,7 +517,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT
     ctx.uniform = true;
     for (int p = 0; p < a.n_phases; ++p) {
       const DevPhase P = load_phase(a.phases, p);
-      phase_dispatch<R, false>(region, P, ctx, tt, tmask);
+      phase_dispatch<R, false>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, tmask);
       TNC_WAIT_LGKM0();
       __builtin_amdgcn_s_barrier();
     }
@@ -696,7 +699,8 @@ static void emulate_pass_r(const PassArgs& a) {
     ctx.uniform = false;
     for (int p = 0; p < a.n_phases; ++p) {
       const DevPhase P = load_phase(a.phases, p);
-      for (int tt = 0; tt < tpt; ++tt) phase_dispatch<R, false>(region, P, ctx, (uint32_t)tt, tmask);
+      for (int tt = 0; tt < tpt; ++tt)
+        phase_dispatch<R, false>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, (uint32_t)tt, tmask);
     }
     if (s16) {
       float amax[2] = {0.f, 0.f};

@@ -264,14 +264,17 @@ TNC_HD inline Regs<R> stair_rest(Regs<R> v, const PhaseCtx<R, MF>& c, int op_beg
   return v;
 }
 
-// A whole canonical phase of N ops on a thread's registers.
-template <int R, int N, bool MF>
+// A whole canonical phase of N ops on a thread's registers.  K0 is the
+// form of op 0: 0 a duplication, 1 an update with no control, 2 an update
+// controlled by a thread bit (cloc0).  Each form is its own code path, so no
+// register values merge across forms.
+template <int R, int N, bool MF, int K0>
 TNC_HD inline Regs<R> stair(Regs<R> v, const DevPhase& P, const PhaseCtx<R, MF>& c) {
-  if (P.first_dup) {
+  if constexpr (K0 == 0) {
     v = op_dup<R, 0>(v);
   } else {
     const TNC_TBL float* m = c.rm + (size_t)P.op_begin * 16;
-    if (P.cloc0 < 0) {
+    if constexpr (K0 == 1) {
       v = op_sel<R, 0>(v, m);
     } else {
       const bool hi = (c.tb >> P.cloc0) & 1u;
@@ -300,53 +303,64 @@ TNC_HD inline Regs<R> stair(Regs<R> v, const DevPhase& P, const PhaseCtx<R, MF>&
 
 // One register phase: LDS -> registers (phase layout), the phase's ops,
 // registers -> LDS.  Each thread writes back exactly the entries it read.
-template <int R, int N, bool MF>
-TNC_HD inline void phase_exec(char* region, const DevPhase& P, const PhaseCtx<R, MF>& c0, uint32_t tt,
-                              uint32_t tmask) {
+// The tile sits at byte offset `rbase` of `base`, with rbase's bits above
+// the tile's own (rbase = 0 or a multiple of 2^(T+3)), so an entry's byte
+// offset is rbase | (swz(thread bits) << 3) ^ po[i].  po[i] (from the pass
+// tables) is swz(r_i) << 3 for the tile index r_i of register entry i.
+template <int R, int N, bool MF, int K0>
+TNC_HD inline void phase_exec(char* base, uint32_t rbase, const DevPhase& P, const TNC_TBL uint32_t* po,
+                              const PhaseCtx<R, MF>& c0, uint32_t tt, uint32_t tmask) {
   constexpr int E = 1 << R;
-  uint32_t rm[R];
   uint32_t rmask = 0;
 #pragma unroll
-  for (int b = 0; b < R; ++b) {
-    rm[b] = 1u << P.reg[b];
-    rmask |= rm[b];
-  }
+  for (int b = 0; b < R; ++b) rmask |= 1u << P.reg[b];
   PhaseCtx<R, MF> c = c0;
   c.tb = pdep32(tt, tmask & ~rmask);
-  const uint32_t vbase = swz(c.tb) << 3;
+  const uint32_t vbase = rbase | (swz(c.tb) << 3);
+  uint32_t off[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) off[i] = vbase ^ po[i];
   Regs<R> v;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    uint32_t r = 0;
-#pragma unroll
-    for (int b = 0; b < R; ++b)
-      if (i & (1 << b)) r |= rm[b];
-    const float2 t = *reinterpret_cast<const float2*>(region + (vbase ^ (swz(r) << 3)));
+    const float2 t = *reinterpret_cast<const float2*>(base + off[i]);
     v.x[i] = t.x;
     v.y[i] = t.y;
   }
-  v = stair<R, N, MF>(v, P, c);
+  v = stair<R, N, MF, K0>(v, P, c);
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    uint32_t r = 0;
-#pragma unroll
-    for (int b = 0; b < R; ++b)
-      if (i & (1 << b)) r |= rm[b];
-    *reinterpret_cast<float2*>(region + (vbase ^ (swz(r) << 3))) = make_float2(v.x[i], v.y[i]);
-  }
+  for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(base + off[i]) = make_float2(v.x[i], v.y[i]);
+}
+
+template <int R, int N, bool MF>
+TNC_HD inline void phase_forms(char* base, uint32_t rbase, const DevPhase& P, const TNC_TBL uint32_t* po,
+                               const PhaseCtx<R, MF>& c, uint32_t tt, uint32_t tmask) {
+  if (P.first_dup) phase_exec<R, N, MF, 0>(base, rbase, P, po, c, tt, tmask);
+  else if (P.cloc0 < 0) phase_exec<R, N, MF, 1>(base, rbase, P, po, c, tt, tmask);
+  else phase_exec<R, N, MF, 2>(base, rbase, P, po, c, tt, tmask);
 }
 
 template <int R, bool MF>
-TNC_HD inline void phase_dispatch(char* region, const DevPhase& P, const PhaseCtx<R, MF>& c, uint32_t tt,
-                                  uint32_t tmask) {
+TNC_HD inline void phase_dispatch(char* base, uint32_t rbase, const DevPhase& P, const TNC_TBL uint32_t* po,
+                                  const PhaseCtx<R, MF>& c, uint32_t tt, uint32_t tmask) {
   switch (P.n_ops) {
-    case 1: phase_exec<R, 1, MF>(region, P, c, tt, tmask); break;
-    case 2: if constexpr (R >= 2) phase_exec<R, 2, MF>(region, P, c, tt, tmask); break;
-    case 3: if constexpr (R >= 3) phase_exec<R, 3, MF>(region, P, c, tt, tmask); break;
-    case 4: if constexpr (R >= 4) phase_exec<R, 4, MF>(region, P, c, tt, tmask); break;
-    case 5: if constexpr (R >= 5) phase_exec<R, 5, MF>(region, P, c, tt, tmask); break;
+    case 1: phase_forms<R, 1, MF>(base, rbase, P, po, c, tt, tmask); break;
+    case 2: if constexpr (R >= 2) phase_forms<R, 2, MF>(base, rbase, P, po, c, tt, tmask); break;
+    case 3: if constexpr (R >= 3) phase_forms<R, 3, MF>(base, rbase, P, po, c, tt, tmask); break;
+    case 4: if constexpr (R >= 4) phase_forms<R, 4, MF>(base, rbase, P, po, c, tt, tmask); break;
+    case 5: if constexpr (R >= 5) phase_forms<R, 5, MF>(base, rbase, P, po, c, tt, tmask); break;
     default: break;
   }
+}
+
+// Byte offsets of a phase's register entries in the LDS tile: entry i holds
+// the tile index whose register bits reg[b] are the bits of i, placed by
+// swz (the po[] table of phase_exec).
+TNC_HD inline uint32_t phase_entry_offset(const DevPhase& P, int R, int i) {
+  uint32_t r = 0;
+  for (int b = 0; b < R; ++b)
+    if (i & (1 << b)) r |= 1u << P.reg[b];
+  return swz(r) << 3;
 }
 
 // Launchers (kernels.hip).

@@ -120,6 +120,11 @@ int build_late(const Plan& p, const Schedule& s, LatePlan* out, std::string* err
       }
     } else {
       const int de = 1 << ub;
+      if (first_end == 0) {
+        // nothing folded: P is the identity and J is the join matrix
+        std::copy(s.join.begin(), s.join.begin() + (size_t)de * dim, Ju.begin() + ((size_t)u << ub) * dim);
+        continue;
+      }
       for (int ue = 0; ue < de; ++ue) {
         cd* row = Ju.data() + ((size_t)((u << ub) | ue)) * dim;
         for (int tp = 0; tp < dim; ++tp) {

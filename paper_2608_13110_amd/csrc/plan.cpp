@@ -749,22 +749,40 @@ int get_schedule(Plan& p, int k, std::shared_ptr<Schedule>* out, std::string* er
     if (int(X.size()) < k || X[k - 1] > c) return fail(err, kErrDomain, "fewer than k crossings in the early layers");
     const int dim = 1 << k;
     s->join.assign((size_t)dim * dim, cd(0));
-    for (int u = 0; u < dim; ++u) {
-      std::vector<cd> st(dim, cd(0));
-      st[0] = 1;
-      for (int l = 1; l <= c; ++l) {
+    // One band state per assignment of the crossings met so far: states
+    // branch at each crossing, so assignments share their common prefix
+    // (u's bit j is the j-th crossing's index alpha).
+    std::vector<std::vector<cd>> sts(1, std::vector<cd>(dim, cd(0)));
+    sts[0][0] = 1;
+    for (int l = 1; l <= c; ++l) {
+      for (auto& st : sts) {
         for (int j = 0; j < k; ++j) band_apply_u1(st, k, j, p.one[(size_t)(l - 1) * n + (n - k + j)]);
         for (int j = 0; j + 1 < k; ++j) {
           int q = n - k + j;
           if (in_pattern(p, l, q)) band_apply_g4(st, k, j, p.g4[pair_index(p, l, q)]);
         }
-        if (in_pattern(p, l, cut)) {
-          int cj = int(std::lower_bound(X.begin(), X.end(), l) - X.begin());
-          band_apply_u1(st, k, 0, p.split[pair_index(p, l, cut)].C[(u >> cj) & 1]);
+      }
+      if (in_pattern(p, l, cut)) {
+        const int cj = int(std::lower_bound(X.begin(), X.end(), l) - X.begin());
+        const Split& sp = p.split[pair_index(p, l, cut)];
+        if (cj >= k) {
+          for (auto& st : sts) band_apply_u1(st, k, 0, sp.C[0]);
+        } else {
+          // states are indexed by the bits of crossings 0..cj-1
+          const size_t m = sts.size();
+          if (m != (size_t)1 << cj) return fail(err, kErrInvalid, "early crossings out of order");
+          sts.resize(2 * m);
+          for (size_t i = 0; i < m; ++i) {
+            sts[m + i] = sts[i];
+            band_apply_u1(sts[i], k, 0, sp.C[0]);
+            band_apply_u1(sts[m + i], k, 0, sp.C[1]);
+          }
         }
       }
-      for (int t = 0; t < dim; ++t) s->join[(size_t)u * dim + t] = st[t];
     }
+    if ((int)sts.size() != dim) return fail(err, kErrInvalid, "early crossings do not match k");
+    for (int u = 0; u < dim; ++u)
+      for (int t = 0; t < dim; ++t) s->join[(size_t)u * dim + t] = sts[u][t];
     for (int l = c + 1; l <= d + 1; ++l) {
       for (int j = 0; j < k; ++j) {
         LateOp u1;

@@ -52,6 +52,7 @@ struct HostTables {
   std::vector<float> mats;
   std::vector<float4> mrows;
   std::vector<DevPhase> phases;
+  std::vector<uint32_t> poffs;  // kPhaseOffs per phase
   std::vector<PassHost> passes;
   std::vector<double2> seg;
   LatePlan late;
@@ -64,54 +65,32 @@ struct HostTables {
 // by a matrix's entries multiplies every amplitude: 1/sqrt(2) rounds to
 // nearest 1.7e-8 low, and the ~900 Hadamard-like factors of a width-33
 // sweep would scale every amplitude by 1 - 1.5e-5.  Each component is
-// therefore rounded down or up (the two FP32 neighbours of its value),
-// choosing among those combinations the one whose least-squares factor
-// rho = <K, K32> / <K, K> best cancels the bias accumulated so far (`acc`,
-// the running sum of rho - 1 over the sweep's earlier updates).  Returns
-// the chosen rho - 1.
+// therefore rounded down or up (the two FP32 neighbours of its value).
+// rho - 1 = <K, K32> / <K, K> - 1, the least-squares factor's deviation, is
+// a sum of one term per component, so the components are taken in turn and
+// each picks the neighbour that brings the running sum `acc` (rho - 1 of
+// the sweep's earlier updates, plus this matrix's terms so far) closer to
+// zero: error diffusion over the sweep.  Returns this matrix's rho - 1.
 cd round_matrix(const M2& K, const cd& acc, float* out) {
   double nk = 0;
   for (int e = 0; e < 4; ++e) nk += std::norm(K.a[e]);
-  double v[8];
-  float lo[8], hi[8];
-  int free_bits[8], nfree = 0;
-  for (int e = 0; e < 4; ++e) {
-    v[2 * e] = K.a[e].real();
-    v[2 * e + 1] = K.a[e].imag();
-  }
+  cd run = acc, rho = 0;
   for (int q = 0; q < 8; ++q) {
-    const float f = (float)v[q];
-    lo[q] = hi[q] = f;
-    if ((double)f != v[q]) {
-      const float g = std::nextafter(f, (double)f < v[q] ? INFINITY : -INFINITY);
-      lo[q] = f;
-      hi[q] = g;
-      free_bits[nfree++] = q;
-    }
+    const cd ke = K.a[q >> 1];
+    const double v = (q & 1) ? ke.imag() : ke.real();
+    const float f = (float)v;
+    out[q] = f;
+    if ((double)f == v || nk == 0) continue;
+    const float g = std::nextafter(f, (double)f < v ? INFINITY : -INFINITY);
+    // term of component q: conj(K_e) (x - v) (1 or i) / <K, K>
+    const cd w = std::conj(ke) * ((q & 1) ? cd(0, 1) : cd(1, 0)) / nk;
+    const cd tf = w * ((double)f - v), tg = w * ((double)g - v);
+    const bool up = std::abs(run + tg) < std::abs(run + tf);
+    out[q] = up ? g : f;
+    run += up ? tg : tf;
+    rho += up ? tg : tf;
   }
-  float best[8];
-  std::copy(lo, lo + 8, best);
-  cd best_rho = 0;
-  double best_err = 1e300;
-  const int combos = 1 << nfree;
-  for (int m = 0; m < combos; ++m) {
-    float f[8];
-    std::copy(lo, lo + 8, f);
-    for (int b = 0; b < nfree; ++b)
-      if (m >> b & 1) f[free_bits[b]] = hi[free_bits[b]];
-    cd dot = 0;
-    for (int e = 0; e < 4; ++e) dot += std::conj(K.a[e]) * cd(f[2 * e], f[2 * e + 1]);
-    const cd rho = nk > 0 ? dot / nk - 1.0 : cd(0);
-    // cancel the running bias; among equals prefer the smaller own bias
-    const double err = std::abs(acc + rho) + 1e-3 * std::abs(rho);
-    if (err < best_err) {
-      best_err = err;
-      best_rho = rho;
-      std::copy(f, f + 8, best);
-    }
-  }
-  std::copy(best, best + 8, out);
-  return best_rho;
+  return rho;
 }
 
 int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
@@ -173,6 +152,7 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
         dp.reg[b] = (int8_t)pp.reg[b];
       }
       t->phases.push_back(dp);
+      for (int i = 0; i < kPhaseOffs; ++i) t->poffs.push_back(i < (1 << R) ? phase_entry_offset(dp, R, i) : 0u);
       for (int b = 0; b < nops; ++b) {
         const int o = pp.op_begin + b;
         const SweepOp& op = s.ops[o];
@@ -290,6 +270,7 @@ struct DevSched {
   float* d_mats = nullptr;
   float4* d_mrows = nullptr;
   DevPhase* d_phases = nullptr;
+  uint32_t* d_poffs = nullptr;
   double2* d_seg = nullptr;
   double2* d_J = nullptr;
   LateOpDev* d_prog = nullptr;
@@ -297,7 +278,7 @@ struct DevSched {
     int prev = 0;
     if (device >= 0 && hipGetDevice(&prev) == hipSuccess) {
       (void)hipSetDevice(device);
-      void* ptrs[] = {d_ops, d_mats, d_mrows, d_phases, d_seg, d_J, d_prog};
+      void* ptrs[] = {d_ops, d_mats, d_mrows, d_phases, d_poffs, d_seg, d_J, d_prog};
       for (void* q : ptrs)
         if (q) (void)hipFree(q);
       (void)hipSetDevice(prev);
@@ -354,7 +335,8 @@ int get_dev_sched(Plan& p, int k, std::shared_ptr<DevSched>* out) {
   for (const cd& z : ds->host.late.first.J) J.push_back(make_double2(z.real(), z.imag()));
   if ((rc = upload(&ds->d_ops, ds->host.ops)) || (rc = upload(&ds->d_mats, ds->host.mats)) ||
       (rc = upload(&ds->d_mrows, ds->host.mrows)) ||
-      (rc = upload(&ds->d_phases, ds->host.phases)) || (rc = upload(&ds->d_seg, ds->host.seg)) ||
+      (rc = upload(&ds->d_phases, ds->host.phases)) || (rc = upload(&ds->d_poffs, ds->host.poffs)) ||
+      (rc = upload(&ds->d_seg, ds->host.seg)) ||
       (rc = upload(&ds->d_J, J)) || (rc = upload(&ds->d_prog, ds->host.prog)))
     return rc;
   pd.m[{k, dev}] = ds;
@@ -416,11 +398,12 @@ InitArgs init_args(const Plan& p, const HostTables& t, float2* B, const uint8_t*
   return a;
 }
 
-PassArgs pass_args(const Plan& p, const PassHost& ph, const DevPhase* phases, const DevOp* ops, const float* mats,
-                   const float4* mrows, float2* B, const uint8_t* bits, int nb) {
+PassArgs pass_args(const Plan& p, const PassHost& ph, const DevPhase* phases, const uint32_t* poffs, const DevOp* ops,
+                   const float* mats, const float4* mrows, float2* B, const uint8_t* bits, int nb) {
   PassArgs a;
   std::memset(&a, 0, sizeof(a));
   a.phases = phases + ph.phase_off;
+  a.poffs = poffs + (size_t)ph.phase_off * kPhaseOffs;
   a.ops = ops;
   a.mats = mats;
   a.mrows = mrows;
@@ -550,7 +533,7 @@ int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k
     int cur = 0;
     ScaleMap map = init_map(p);
     for (const PassHost& ph : t.passes) {
-      PassArgs a = pass_args(p, ph, ds.d_phases, ds.d_ops, ds.d_mats, ds.d_mrows, B, bits, nb);
+      PassArgs a = pass_args(p, ph, ds.d_phases, ds.d_poffs, ds.d_ops, ds.d_mats, ds.d_mrows, B, bits, nb);
       a.rmats = rmats;
       a.rstride = rstride;
       a.rmrows = rmrows;
@@ -660,7 +643,7 @@ int emulate(Plan& p, int k, int nb, const uint8_t* bits, int storage, cd* out) {
   int cur = 0;
   ScaleMap map = init_map(p);
   for (const PassHost& ph : t.passes) {
-    PassArgs a = pass_args(p, ph, t.phases.data(), t.ops.data(), t.mats.data(), t.mrows.data(), B.data(), bits, nb);
+    PassArgs a = pass_args(p, ph, t.phases.data(), t.poffs.data(), t.ops.data(), t.mats.data(), t.mrows.data(), B.data(), bits, nb);
     a.rmats = rmats.data();
     a.rstride = rstride;
     if (s16) {
