@@ -71,7 +71,7 @@ def pct(xs, q):
 
 
 # tile candidates the autotuner times for the large workloads
-MAIN_CANDIDATES = [dict(), dict(max_tile_bits=12), dict(low_bits=5)]
+MAIN_CANDIDATES = [dict(), dict(max_tile_bits=12), dict(math=2), dict(max_tile_bits=12, math=2)]
 
 
 def run_workload(name, steps, warmup, torch, W, Plan, profile_begin, profile_end, fixed=None):
@@ -181,7 +181,7 @@ def storage_modes(torch, W, Plan, profile_begin, profile_end, batches=16):
 
 
 TUNE_CANDIDATES = [dict(), dict(max_tile_bits=12), dict(max_tile_bits=12, reg_adapt=1),
-                   dict(max_tile_bits=12, reg_bits=4), dict(max_tile_bits=11, reg_bits=4)]
+                   dict(max_tile_bits=12, reg_bits=4), dict(max_tile_bits=11, reg_bits=4), dict(math=2)]
 
 
 def serving_bench(torch, W, count=512, load=0.8):

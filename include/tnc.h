@@ -79,13 +79,16 @@ typedef struct {
 
 /* Tiling options of the pass kernels; zero fields take the defaults. */
 typedef struct {
-  int32_t max_tile_bits; /* entries per pass tile = 2^max_tile_bits (default 13, 6..13) */
-  int32_t reg_bits;      /* entries per thread = 2^reg_bits (default 5, 1..5); 256 threads
-                            per tile; max_tile_bits - reg_bits = 9 (512 threads) only with
-                            pipeline = 1 and math = 0 */
+  int32_t max_tile_bits; /* entries per pass tile = 2^max_tile_bits (default 13, 6..14) */
+  int32_t reg_bits;      /* entries per thread = 2^reg_bits (default 5, 1..5); at most 512
+                            threads per tile: max_tile_bits - reg_bits <= 9 (<= 8 with
+                            math = 1) */
   int32_t low_bits;      /* contiguous low slots in every non-bottom tile (default 4) */
   int32_t math;          /* 0: vector-ALU updates (default); 1: matrix-core updates
-                            (v_mfma_f32_4x4x1_16b_f32) where a block holds one tile */
+                            (v_mfma_f32_4x4x1_16b_f32) where a block holds one tile;
+                            2: runs of three updates without output-bit variants fused into
+                            one complex 8x8 per control value, on v_mfma_f32_16x16x4f32
+                            (tiles of 64 threads or more; pipeline 0 or 2; complex64 storage) */
   int32_t pipeline;      /* 0: one tile per block (default); 1: persistent blocks that prefetch
                             the next tile into LDS while updating the current one; 2: persistent
                             blocks that prefetch the next tile into registers */

@@ -55,7 +55,7 @@ struct DevPhase {
   int8_t first_dup;
   int8_t reg[8];
   int8_t cloc0;
-  int8_t pad;
+  int8_t pad;   // 1: a fused phase (three updates as one 8x8 on the matrix cores)
 };
 static_assert(sizeof(DevPhase) == 16, "DevPhase layout");
 
@@ -64,8 +64,12 @@ static_assert(sizeof(DevPhase) == 16, "DevPhase layout");
 //   mrows: per op [var 4][ctl 2][row 4][4]: the real 4x4 form of the same
 //          2x2, acting on (re b0, im b0, re b1, im b1); row r feeds the
 //          matrix-core update's A operand of lane r (mod 4)
-// Entries of a phase's LDS offset table (one per register entry, up to 2^5).
-constexpr int kPhaseOffs = 32;
+// A phase's LDS offset table: one word per register entry (up to 2^5), then
+// (fused phases) one per thread bit: the offset of that tile bit alone.
+constexpr int kPhaseEntries = 32;
+constexpr int kPhaseOffs = 48;
+// Matrix-core operands of a fused phase: [control 2][lane 64] float4.
+constexpr int kFusedWords = 128;
 
 struct PassArgs {
   const DevPhase* phases;
@@ -73,6 +77,9 @@ struct PassArgs {
   // phase's register entries (tile index with register bits = the entry's
   // bits, after the LDS swizzle)
   const uint32_t* poffs;
+  // per phase of the pass: kFusedWords float4, the fused phases' matrix-core
+  // operands (null when the pass tables have no fused phase)
+  const float4* fmats;
   const DevOp* ops;
   const float* mats;
   const float4* mrows;

@@ -243,8 +243,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MF ? 2 : 1))
   const uint32_t rbase = (uint32_t)tile_in_block << (T + 3);
   for (int p = 0; p < a.n_phases; ++p) {
     const DevPhase P = load_phase(a.phases, p);
-    phase_dispatch<R, MF>(reinterpret_cast<char*>(lds), rbase, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs,
-                          ctx, tt, tmask);
+    phase_dispatch<R, MF, WU && !MF>(reinterpret_cast<char*>(lds), rbase, P,
+                                     (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, tmask,
+                                     a.fmats + (size_t)p * kFusedWords, TB);
     __syncthreads();
   }
 
@@ -376,13 +377,33 @@ __global__ __launch_bounds__(kBlock) void k_pass16(PassArgs a) {
   }
 }
 
+// Waits for outstanding vector-memory operations only (vmcnt <= n; gfx9
+// encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at
+// their maxima), and the LDS-only wait used before raw barriers.
+#define TNC_WAIT_VMCNT0() __builtin_amdgcn_s_waitcnt(0x0F70)
+// vmcnt <= n for n < 16 (vector-memory operations retire in issue order)
+#define TNC_WAIT_VMCNT(n) __builtin_amdgcn_s_waitcnt(0x0F70 | ((n) & 15))
+#define TNC_WAIT_LGKM0() __builtin_amdgcn_s_waitcnt(0xC07F)
+
+// Workgroup barrier for LDS only: waits for this wave's LDS operations,
+// not for vector-memory ones (a prefetch in flight stays in flight; the
+// plain __syncthreads() would wait for it).  The empty asm statements keep
+// the compiler from moving memory accesses across.
+__device__ __attribute__((always_inline)) inline void tnc_lds_barrier() {
+  asm volatile("" ::: "memory");
+  TNC_WAIT_LGKM0();
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Persistent, software-pipelined form of the pass for one 2^T-entry tile
-// per 256-thread block (T - R = 8): each block walks tiles blockIdx.x,
-// blockIdx.x + gridDim.x, ...; the next tile's HBM loads are issued right
-// after the current tile has been staged in LDS, so they are in flight while
-// the current tile's register phases run.
-template <int R, bool MF>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_pass_pipe(PassArgs a) {
+// per NT-thread block (T - R = 8 with 256 threads, 9 with 512): each block
+// walks tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's HBM
+// loads are issued right after the current tile has been staged in LDS, so
+// they are in flight while the current tile's register phases run (the
+// phase barriers wait for LDS only).
+template <int R, bool MF, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_pass_pipe(PassArgs a) {
   extern __shared__ float2 lds[];
   constexpr int E = 1 << R;
   constexpr int HALF = E / 2;
@@ -404,7 +425,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     const float2* src = tile_base(t);
 #pragma unroll
     for (int it = 0; it < HALF; ++it) {
-      const uint32_t i = (uint32_t)(it * kBlock + tid) * 2u;
+      const uint32_t i = (uint32_t)(it * NT + tid) * 2u;
       const float4 q = *reinterpret_cast<const float4*>(src + tile_offset(i, a.lo_bits, a.win_lo));
       p0[it] = q.x;
       p1[it] = q.y;
@@ -418,10 +439,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     const long long batch = tile >> tbits;
 #pragma unroll
     for (int it = 0; it < HALF; ++it) {
-      const uint32_t i = (uint32_t)(it * kBlock + tid) * 2u;
+      const uint32_t i = (uint32_t)(it * NT + tid) * 2u;
       *reinterpret_cast<float4*>(region + ((size_t)swz(i) << 3)) = make_float4(p0[it], p1[it], p2[it], p3[it]);
     }
-    __syncthreads();
+    tnc_lds_barrier();
     const long long next = tile + gridDim.x;
     if (next < a.n_tiles) prefetch(next);
     PhaseCtx<R, MF> ctx;
@@ -434,27 +455,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     ctx.uniform = true;
     for (int p = 0; p < a.n_phases; ++p) {
       const DevPhase P = load_phase(a.phases, p);
-      phase_dispatch<R, MF>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, tmask);
-      __syncthreads();
+      phase_dispatch<R, MF, !MF>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, tmask,
+                                 a.fmats + (size_t)p * kFusedWords, T - R);
+      tnc_lds_barrier();
     }
     float2* dst = tile_base(tile);
 #pragma unroll
     for (int it = 0; it < HALF; ++it) {
-      const uint32_t i = (uint32_t)(it * kBlock + tid) * 2u;
+      const uint32_t i = (uint32_t)(it * NT + tid) * 2u;
       const float4 val = *reinterpret_cast<const float4*>(region + ((size_t)swz(i) << 3));
       *reinterpret_cast<float4*>(dst + tile_offset(i, a.lo_bits, a.win_lo)) = val;
     }
-    __syncthreads();
+    tnc_lds_barrier();
   }
 }
-
-// Waits for outstanding vector-memory operations only (vmcnt <= n; gfx9
-// encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at
-// their maxima), and the LDS-only wait used before raw barriers.
-#define TNC_WAIT_VMCNT0() __builtin_amdgcn_s_waitcnt(0x0F70)
-// vmcnt <= n for n < 16 (vector-memory operations retire in issue order)
-#define TNC_WAIT_VMCNT(n) __builtin_amdgcn_s_waitcnt(0x0F70 | ((n) & 15))
-#define TNC_WAIT_LGKM0() __builtin_amdgcn_s_waitcnt(0xC07F)
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
@@ -544,9 +558,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT
   }
 }
 
-static int pipe_blocks_per_cu(const void* fn, size_t lds) {
+static int pipe_blocks_per_cu(const void* fn, int nt, size_t lds) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kBlock, lds) != hipSuccess || blocks < 1) blocks = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, nt, lds) != hipSuccess || blocks < 1) blocks = 1;
   return blocks;
 }
 
@@ -604,6 +618,13 @@ static hipError_t launch_pass_r(const PassArgs& a, hipStream_t s) {
   if (TB == 9 && !a.mfma) {
     // one 2^(R+9)-entry tile per 512-thread block
     const size_t lds9 = (size_t)512 * (1 << R) * sizeof(float2);
+    if (a.pipeline == 2) {
+      static int bpc9[8] = {0};
+      if (bpc9[R] == 0) bpc9[R] = pipe_blocks_per_cu(reinterpret_cast<const void*>(&k_pass_pipe<R, false, 512>), 512, lds9);
+      const long long grid = std::min<long long>(a.n_tiles, (long long)bpc9[R] * device_cus());
+      hipLaunchKernelGGL((k_pass_pipe<R, false, 512>), dim3((unsigned)grid), dim3(512), lds9, s, a);
+      return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_pass<R, false, false, true, 512>), dim3((unsigned)a.n_tiles), dim3(512), lds9, s, a);
     return hipGetLastError();
   }
@@ -617,15 +638,15 @@ static hipError_t launch_pass_r(const PassArgs& a, hipStream_t s) {
   // persistent blocks with the next tile prefetched into registers
   // (pipeline = 2; the matrix-core form uses them for pipeline = 1 too)
   if (!multi && (a.pipeline == 2 || (a.pipeline && mf))) {
-    const void* fn = mf ? reinterpret_cast<const void*>(&k_pass_pipe<R, true>)
-                        : reinterpret_cast<const void*>(&k_pass_pipe<R, false>);
+    const void* fn = mf ? reinterpret_cast<const void*>(&k_pass_pipe<R, true, kBlock>)
+                        : reinterpret_cast<const void*>(&k_pass_pipe<R, false, kBlock>);
     static int per_cu[2][8] = {{0}};
     int& bpc = per_cu[mf ? 1 : 0][R];
-    if (bpc == 0) bpc = pipe_blocks_per_cu(fn, lds);
+    if (bpc == 0) bpc = pipe_blocks_per_cu(fn, kBlock, lds);
     const long long resident = (long long)bpc * device_cus();
     const long long grid = std::min<long long>(a.n_tiles, resident);
-    if (mf) hipLaunchKernelGGL((k_pass_pipe<R, true>), dim3((unsigned)grid), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((k_pass_pipe<R, false>), dim3((unsigned)grid), dim3(kBlock), lds, s, a);
+    if (mf) hipLaunchKernelGGL((k_pass_pipe<R, true, kBlock>), dim3((unsigned)grid), dim3(kBlock), lds, s, a);
+    else hipLaunchKernelGGL((k_pass_pipe<R, false, kBlock>), dim3((unsigned)grid), dim3(kBlock), lds, s, a);
     return hipGetLastError();
   }
   if (multi) {
@@ -647,6 +668,79 @@ hipError_t launch_pass(const PassArgs& a, int R, hipStream_t s) {
     case 4: return launch_pass_r<4>(a, s);
     case 5: return launch_pass_r<5>(a, s);
     default: return hipErrorInvalidValue;
+  }
+}
+
+// Host emulation of a fused phase, wave by wave, with the lane layout of
+// phase_tri: D[4 g + r][j] = sum_k A[4 g + r][k] B[k][j], A[i][k] from the
+// operand table of lane i + 16 (k % 4) at step k / 4, B[k][j] the step-(k/4)
+// value of lane 16 (k % 4) + j.  FP32 sums in step order.
+template <int R>
+static void emulate_tri(char* region, const DevPhase& P, const uint32_t* po, const float4* F, const float* rm, int TB) {
+  constexpr int E = 1 << R;
+  constexpr int G = E / 2;
+  const int tpt = 1 << TB;
+  auto comp = [](const float4& q, int st) { return st == 0 ? q.x : st == 1 ? q.y : st == 2 ? q.z : q.w; };
+  for (int w0 = 0; w0 < tpt; w0 += 64) {
+    static thread_local float vx[64][E], vy[64][E];
+    uint32_t off[64][E];
+    for (int l = 0; l < 64; ++l) {
+      const uint32_t tt = (uint32_t)(w0 + l);
+      uint32_t vb = 0;
+      for (int t = 0; t < TB; ++t)
+        if ((tt >> t) & 1u) vb ^= po[kPhaseEntries + t];
+      for (int i = 0; i < E; ++i) {
+        off[l][i] = vb ^ po[i];
+        const float2 x = *reinterpret_cast<const float2*>(region + off[l][i]);
+        vx[l][i] = x.x;
+        vy[l][i] = x.y;
+      }
+    }
+    for (int j = 0; j < G; ++j) {
+      const float4* A = F + (j >= G / 2 ? 64 : 0);
+      float out[64][4];
+      for (int l = 0; l < 64; ++l) {
+        const int g = l / 16, jj = l % 16;
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * g + r;
+          float d = 0.f;
+          for (int st = 0; st < 4; ++st)
+            for (int gg = 0; gg < 4; ++gg) {
+              const int src = 16 * gg + jj;
+              const float b = st == 0 ? vx[src][2 * j] : st == 1 ? vy[src][2 * j] : st == 2 ? vx[src][2 * j + 1]
+                                                                                         : vy[src][2 * j + 1];
+              d = std::fma(comp(A[i + 16 * gg], st), b, d);
+            }
+          out[l][r] = d;
+        }
+      }
+      for (int l = 0; l < 64; ++l) {
+        vx[l][2 * j] = out[l][0];
+        vy[l][2 * j] = out[l][1];
+        vx[l][2 * j + 1] = out[l][2];
+        vy[l][2 * j + 1] = out[l][3];
+      }
+    }
+    // the staircase tail, lane by lane
+    for (int l = 0; l < 64; ++l) {
+      Regs<R> v;
+      for (int i = 0; i < E; ++i) {
+        v.x[i] = vx[l][i];
+        v.y[i] = vy[l][i];
+      }
+      if constexpr (R >= 4) {
+        if (P.n_ops >= 4) v = op_sel<R, 1>(v, rm + (size_t)(P.op_begin + 3) * 16 + 8 * ((l >> 5) & 1));
+      }
+      if constexpr (R >= 5) {
+        if (P.n_ops >= 5) v = op_reg<R, 2, 1>(v, (const TNC_TBL float*)(rm + (size_t)(P.op_begin + 4) * 16));
+      }
+      for (int i = 0; i < E; ++i) {
+        vx[l][i] = v.x[i];
+        vy[l][i] = v.y[i];
+      }
+    }
+    for (int l = 0; l < 64; ++l)
+      for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(region + off[l][i]) = make_float2(vx[l][i], vy[l][i]);
   }
 }
 
@@ -699,6 +793,12 @@ static void emulate_pass_r(const PassArgs& a) {
     ctx.uniform = false;
     for (int p = 0; p < a.n_phases; ++p) {
       const DevPhase P = load_phase(a.phases, p);
+      if (P.pad) {
+        if constexpr (R >= 3)
+          emulate_tri<R>(region, P, a.poffs + p * kPhaseOffs, a.fmats + (size_t)p * kFusedWords,
+                         a.rmats + (size_t)batch * a.rstride, TB);
+        continue;
+      }
       for (int tt = 0; tt < tpt; ++tt)
         phase_dispatch<R, false>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, (uint32_t)tt, tmask);
     }

@@ -179,6 +179,8 @@ TNC_HD inline Regs<R> op_dup(Regs<R> v) {
   return v;
 }
 
+constexpr int kMaxThreadBitsDev = 9;
+
 #if defined(__HIP_DEVICE_COMPILE__)
 typedef float tnc_floatx4 __attribute__((ext_vector_type(4)));
 
@@ -340,9 +342,96 @@ TNC_HD inline void phase_forms(char* base, uint32_t rbase, const DevPhase& P, co
   else phase_exec<R, N, MF, 2>(base, rbase, P, po, c, tt, tmask);
 }
 
-template <int R, bool MF>
+#if defined(__HIP_DEVICE_COMPILE__)
+// A fused phase (three staircase updates as one complex 8x8 U_c per value c
+// of op 0's control) on v_mfma_f32_16x16x4f32.  Lane l = 16 g + j holds,
+// for each of its 2^(R-1) groups, the entries b0 = 0, 1 (register bit 0)
+// of vector j with (b1, b2) = g: four floats, MFMA steps s = 0..3 in the
+// order (re, im) of b0 = 0, then of b0 = 1.  Step s takes A[j'][4 s + g]
+// from lane 16 g + j' and B[4 s + g][j] from lane 16 g + j; the result
+// D[4 g + r][j] lands in lane 16 g + j as component r, the same layout.
+// Groups with register bit R-1 set use U_1 (op 0's control sits there; an
+// uncontrolled op 0 has U_1 = U_0).  Thread bit t of the tile adds tile bit
+// tpos[t], whose LDS offset is po[kPhaseEntries + t].  Updates 3..N-1 then
+// go on on the vector ALUs: update 3 on register bit 1 under lane bit 5
+// (b2), update b > 3 on register bit b - 2 under register bit b - 3.
+template <int R, int N, bool MF>
+__device__ __attribute__((always_inline)) inline void phase_tri(char* base, uint32_t rbase, const DevPhase& P,
+                                                                const TNC_TBL uint32_t* po, const float4* __restrict__ F,
+                                                                const PhaseCtx<R, MF>& c, uint32_t tt, int TB) {
+  constexpr int E = 1 << R;
+  constexpr int G = E / 2;
+  const int lane = (int)(tt & 63u);
+  const float4 a0 = F[lane];
+  const float4 a1 = F[64 + lane];
+  uint32_t vb = rbase;
+#pragma unroll
+  for (int t = 0; t < kMaxThreadBitsDev; ++t)
+    if (t < TB) {
+      const uint32_t w = po[kPhaseEntries + t];  // wave-uniform: a scalar load
+      vb ^= (0u - ((tt >> t) & 1u)) & w;
+    }
+  uint32_t off[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) off[i] = vb ^ po[i];
+  Regs<R> v;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const float2 t = *reinterpret_cast<const float2*>(base + off[i]);
+    v.x[i] = t.x;
+    v.y[i] = t.y;
+  }
+  // every LDS read in flight before the first product (the scheduler would
+  // otherwise wait on each read in turn)
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    const float4 a = j >= G / 2 ? a1 : a0;
+    tnc_floatx4 d = {0.f, 0.f, 0.f, 0.f};
+    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, v.x[2 * j], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, v.y[2 * j], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, v.x[2 * j + 1], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, v.y[2 * j + 1], d, 0, 0, 0);
+    v.x[2 * j] = d[0];
+    v.y[2 * j] = d[1];
+    v.x[2 * j + 1] = d[2];
+    v.y[2 * j + 1] = d[3];
+  }
+  if constexpr (N >= 4) {
+    const TNC_TBL float* m = c.rm + (size_t)(P.op_begin + 3) * 16;
+    const bool hi = (lane >> 5) & 1;
+    float lo[8], up[8], k[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      lo[e] = uniform_value(m[e]);
+      up[e] = uniform_value(m[8 + e]);
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) k[e] = hi ? up[e] : lo[e];
+    v = op_sel<R, 1>(v, static_cast<const float*>(k));
+  }
+  if constexpr (N >= 5) v = op_reg<R, 2, 1>(v, c.rm + (size_t)(P.op_begin + 4) * 16);
+#pragma unroll
+  for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(base + off[i]) = make_float2(v.x[i], v.y[i]);
+}
+#endif
+
+// TRI: the kernel runs fused phases (P.pad = 1); the host plans them only for
+// kernels whose waves each lie inside one tile.
+template <int R, bool MF, bool TRI = false>
 TNC_HD inline void phase_dispatch(char* base, uint32_t rbase, const DevPhase& P, const TNC_TBL uint32_t* po,
-                                  const PhaseCtx<R, MF>& c, uint32_t tt, uint32_t tmask) {
+                                  const PhaseCtx<R, MF>& c, uint32_t tt, uint32_t tmask, const float4* fm = nullptr,
+                                  int TB = 0) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (TRI && R >= 3) {
+    if (P.pad) {
+      if (P.n_ops == 3) phase_tri<R, 3, MF>(base, rbase, P, po, fm, c, tt, TB);
+      else if (P.n_ops == 4) { if constexpr (R >= 4) phase_tri<R, 4, MF>(base, rbase, P, po, fm, c, tt, TB); }
+      else { if constexpr (R >= 5) phase_tri<R, 5, MF>(base, rbase, P, po, fm, c, tt, TB); }
+      return;
+    }
+  }
+#endif
   switch (P.n_ops) {
     case 1: phase_forms<R, 1, MF>(base, rbase, P, po, c, tt, tmask); break;
     case 2: if constexpr (R >= 2) phase_forms<R, 2, MF>(base, rbase, P, po, c, tt, tmask); break;

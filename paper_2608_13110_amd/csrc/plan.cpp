@@ -560,6 +560,23 @@ bool op_fits(const SweepOp& op, const Window& w) {
   return true;
 }
 
+// Fill a phase's register bits up to R with bits next to the targets, never
+// op 0's control ctl0.
+void pad_regs(std::vector<int>& regs, int ctl0, int T, int R) {
+  auto usable = [&](int c) {
+    return c >= 0 && c < T && c != ctl0 && std::find(regs.begin(), regs.end(), c) == regs.end();
+  };
+  for (int dist = 1; int(regs.size()) < R && dist <= T; ++dist)
+    for (int base : std::vector<int>(regs)) {
+      for (int c : {base + dist, base - dist}) {
+        if (int(regs.size()) >= R) break;
+        if (usable(c)) regs.push_back(c);
+      }
+    }
+  for (int c = 0; int(regs.size()) < R && c < T; ++c)
+    if (usable(c)) regs.push_back(c);
+}
+
 // Register phases in canonical staircase form: op b of a phase targets
 // register bit b and, for b >= 1, is controlled by register bit b-1; op 0 is
 // either a DUP or an update whose control is not a register bit (or absent).
@@ -583,22 +600,61 @@ void plan_phases(Pass& ps, const std::vector<SweepOp>& ops, int R) {
       regs.push_back(t);
     }
     ph.op_end = j;
-    // pad with bits next to the targets, never op 0's control
-    auto usable = [&](int c) {
-      return c >= 0 && c < T && c != ctl0 && std::find(regs.begin(), regs.end(), c) == regs.end();
-    };
-    for (int dist = 1; int(regs.size()) < Reff && dist <= T; ++dist)
-      for (int base : std::vector<int>(regs)) {
-        for (int c : {base + dist, base - dist}) {
-          if (int(regs.size()) >= Reff) break;
-          if (usable(c)) regs.push_back(c);
-        }
-      }
-    for (int c = 0; int(regs.size()) < Reff && c < T; ++c)
-      if (usable(c)) regs.push_back(c);
+    pad_regs(regs, ctl0, T, Reff);
     for (int q = 0; q < kMaxReg; ++q) ph.reg[q] = q < int(regs.size()) ? regs[q] : -1;
     ps.phases.push_back(ph);
     i = j;
+  }
+}
+
+// Matrix-core phases (math = 2).  A staircase phase whose first three
+// updates carry no output-bit variants runs those three as one fused 8x8
+// product per value of op 0's control (targets b0 > register bit 0, b1, b2
+// > lane bits 4, 5), then the rest of its staircase on the vector ALUs:
+// update 3 targets register bit 1 under lane bit 5 (b2), update b > 3
+// register bit b - 2 under register bit b - 3.  Op 0's control, if any, is
+// the top register bit.  Needs six lane bits in the tile (T - R >= 6) and
+// R >= 3.
+void split_triples(Pass& ps, const std::vector<SweepOp>& ops) {
+  const int T = ps.w.tile_bits();
+  const int R = ps.R;
+  const int TB = T - R;
+  if (R < 3 || TB < 6 || TB > kMaxThreadBits) return;
+  for (Phase& ph : ps.phases) {
+    const int o = ph.op_begin;
+    const int nops = ph.op_end - o;
+    bool ok = nops >= 3;
+    for (int b = 0; ok && b < 3; ++b) {
+      const SweepOp& op = ops[o + b];
+      if (op.kind != OP_CU || op.xrow[0] >= 0 || op.xrow[1] >= 0) ok = false;
+    }
+    if (!ok) continue;
+    const int b0 = ph.reg[0], b1 = ph.reg[1], b2 = ph.reg[2];
+    const int ctl0 = ops[o].control >= 0 ? ps.w.local(ops[o].control) : -1;
+    std::vector<int> regs = {b0};
+    for (int b = 3; b < nops; ++b) regs.push_back(ph.reg[b]);
+    if (int(regs.size()) + (ctl0 >= 0 ? 1 : 0) > R) continue;
+    auto used = [&](int c) {
+      return c == b1 || c == b2 || c == ctl0 || std::find(regs.begin(), regs.end(), c) != regs.end();
+    };
+    std::vector<int> rest;
+    for (int c = 0; c < T; ++c)
+      if (!used(c)) rest.push_back(c);
+    // lanes 0..3: the four lowest free bits (adjacent LDS entries), then
+    // the filler register bits, then the wave bits
+    Phase mp;
+    mp.op_begin = o;
+    mp.op_end = ph.op_end;
+    mp.mf = 1;
+    size_t q = 0;
+    for (int t = 0; t < 4; ++t) mp.tpos[t] = rest[q++];
+    mp.tpos[4] = b1;
+    mp.tpos[5] = b2;
+    while (int(regs.size()) < R - (ctl0 >= 0 ? 1 : 0)) regs.push_back(rest[q++]);
+    if (ctl0 >= 0) regs.push_back(ctl0);
+    for (int r = 0; r < kMaxReg; ++r) mp.reg[r] = r < int(regs.size()) ? regs[r] : -1;
+    for (int t = 6; t < TB; ++t) mp.tpos[t] = rest[q++];
+    ph = mp;
   }
 }
 
@@ -633,6 +689,7 @@ std::vector<Pass> plan_passes(const Plan& p, const std::vector<SweepOp>& ops, in
       plan_phases(alt, ops, alt.R);
       if (alt.phases.size() == ps.phases.size()) ps = alt;
     }
+    if (p.opt.math == 2) split_triples(ps, ops);
     passes.push_back(ps);
     i += best_len;
   }

@@ -101,9 +101,20 @@ constexpr int kMaxReg = 8;
 // bit left for the thread part so that op 0's control is never a register.
 inline int pass_reg_bits(int R, int T) { return T <= 1 ? 1 : (R < T - 1 ? R : T - 1); }
 
+constexpr int kMaxThreadBits = 9;
+
+// A register phase.  mf = 0: the canonical staircase on the vector ALUs.
+// mf = 1: its first three updates fused into one complex 8x8 per value of
+// op 0's control, on the matrix cores, with targets reg[0] (a register bit)
+// and tpos[4], tpos[5] (lane bits 4 and 5); op 0's control, if any, is
+// reg[R-1]; the staircase goes on on the vector ALUs: update 3 targets
+// reg[1] under tpos[5], update b > 3 reg[b-2] under reg[b-3].  tpos[t] is
+// the tile bit of thread bit t.
 struct Phase {
   int op_begin = 0, op_end = 0;
   int reg[kMaxReg] = {0};  // local tile bits held in registers, in register-bit order
+  int mf = 0;
+  int tpos[kMaxThreadBits] = {0};
 };
 
 struct Pass {
@@ -117,7 +128,8 @@ struct Options {
   int max_tile_bits = 13;   // tile of one pass: 2^max_tile_bits entries
   int reg_bits = 5;         // entries per thread = 2^reg_bits
   int low_bits = 4;         // contiguous low slots kept in every non-bottom tile
-  int math = 0;             // 0: vector ALU updates; 1: register-controlled updates on the matrix cores
+  int math = 0;             // 0: vector ALU updates; 1: register-controlled updates on the matrix cores;
+                            // 2: runs of three updates fused into 8x8 products on the matrix cores
   int pipeline = 0;         // 1: persistent, prefetching pass blocks where a block holds one tile
   int late_fold = 0;        // removals folded into the join launch (0 auto, -1 none, 1..3)
   int reg_adapt = 0;        // 1: a pass uses reg_bits - 1 when that needs no more phases; 0: never

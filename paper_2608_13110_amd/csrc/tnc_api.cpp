@@ -53,6 +53,7 @@ struct HostTables {
   std::vector<float4> mrows;
   std::vector<DevPhase> phases;
   std::vector<uint32_t> poffs;  // kPhaseOffs per phase
+  std::vector<float4> fmats;    // kFusedWords per phase (fused phases only; empty without them)
   std::vector<PassHost> passes;
   std::vector<double2> seg;
   LatePlan late;
@@ -71,12 +72,12 @@ struct HostTables {
 // each picks the neighbour that brings the running sum `acc` (rho - 1 of
 // the sweep's earlier updates, plus this matrix's terms so far) closer to
 // zero: error diffusion over the sweep.  Returns this matrix's rho - 1.
-cd round_matrix(const M2& K, const cd& acc, float* out) {
+cd round_entries(const cd* K, int n, const cd& acc, float* out) {
   double nk = 0;
-  for (int e = 0; e < 4; ++e) nk += std::norm(K.a[e]);
+  for (int e = 0; e < n; ++e) nk += std::norm(K[e]);
   cd run = acc, rho = 0;
-  for (int q = 0; q < 8; ++q) {
-    const cd ke = K.a[q >> 1];
+  for (int q = 0; q < 2 * n; ++q) {
+    const cd ke = K[q >> 1];
     const double v = (q & 1) ? ke.imag() : ke.real();
     const float f = (float)v;
     out[q] = f;
@@ -93,18 +94,100 @@ cd round_matrix(const M2& K, const cd& acc, float* out) {
   return rho;
 }
 
+cd round_matrix(const M2& K, const cd& acc, float* out) { return round_entries(K.a, 4, acc, out); }
+
+// A fused phase's three updates as one complex 8x8 U_c per value c of op 0's
+// control, on entry index e = b0 + 2 b1 + 4 b2 (b0, b1, b2 = the targets of
+// ops 0, 1, 2; op 1 is controlled by b0, op 2 by b1).  U[e' * 8 + e].
+void fused_matrix(const SweepOp* op, int c, cd* U) {
+  for (int e = 0; e < 8; ++e) {
+    cd z[8] = {};
+    z[e] = 1;
+    auto apply = [&](int bit, const M2& m0, const M2& m1, int cbit) {
+      for (int i = 0; i < 8; ++i) {
+        if (i >> bit & 1) continue;
+        const int j = i | (1 << bit);
+        const M2& m = (cbit >= 0 && (i >> cbit & 1)) ? m1 : m0;
+        const cd a0 = z[i], a1 = z[j];
+        z[i] = m.a[0] * a0 + m.a[1] * a1;
+        z[j] = m.a[2] * a0 + m.a[3] * a1;
+      }
+    };
+    apply(0, op[0].mat[0][c], op[0].mat[0][c], -1);
+    apply(1, op[1].mat[0][0], op[1].mat[0][1], 0);
+    apply(2, op[2].mat[0][0], op[2].mat[0][1], 1);
+    for (int eo = 0; eo < 8; ++eo) U[eo * 8 + e] = z[eo];
+  }
+}
+
+// Matrix-core operand of a fused phase for one control value: lane l holds,
+// at MFMA step s, A[l % 16][4 s + l / 16] of the real 16x16 form of U32.
+// Real index 4 g + t (rows) / 4 t + g (columns) stands for entry
+// e = 2 g + (t >> 1), component t & 1 (re, im), so lane group g = l / 16
+// keeps entries 2g and 2g + 1 from input to output.
+void fused_operand(const float* U32, float4* lanes) {
+  auto comp = [&](int eo, int po, int ei, int pi) -> float {
+    const float re = U32[2 * (eo * 8 + ei)], im = U32[2 * (eo * 8 + ei) + 1];
+    if (po == pi) return re;
+    return po == 0 ? -im : im;
+  };
+  for (int l = 0; l < 64; ++l) {
+    float v[4];
+    for (int st = 0; st < 4; ++st) {
+      const int i = l % 16, k = 4 * st + l / 16;
+      const int go = i >> 2, to = i & 3, gi = k & 3, ti = k >> 2;
+      v[st] = comp(2 * go + (to >> 1), to & 1, 2 * gi + (ti >> 1), ti & 1);
+    }
+    lanes[l] = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
 int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
   const size_t nops = s.ops.size();
   t->ops.resize(nops);
   t->mats.assign(nops * 4 * 16, 0.f);
   t->mrows.assign(nops * 4 * 8, make_float4(0.f, 0.f, 0.f, 0.f));
+  // fused phases: first op -> global phase index
+  std::vector<int> fused_at(nops, -1);
+  {
+    int gp = 0;
+    for (const Pass& ps : s.passes)
+      for (const Phase& pp : ps.phases) {
+        if (pp.mf) {
+          if (pp.op_end - pp.op_begin < 3) {
+            if (err) *err = "fused phase of fewer than three updates";
+            return TNC_E_INVALID;
+          }
+          fused_at[pp.op_begin] = gp;
+        }
+        ++gp;
+      }
+    if (std::find_if(fused_at.begin(), fused_at.end(), [](int v) { return v >= 0; }) != fused_at.end())
+      t->fmats.assign((size_t)gp * kFusedWords, make_float4(0.f, 0.f, 0.f, 0.f));
+  }
   cd acc = 0;  // running rounding bias of the sweep (sum of rho - 1)
+  size_t fused_left = 0;
   for (size_t o = 0; o < nops; ++o) {
     const SweepOp& op = s.ops[o];
+    if (fused_at[o] >= 0) {
+      // the three updates run as one product: its rounding carries the bias
+      cd U[64];
+      float U32[128];
+      for (int c = 0; c < 2; ++c) {
+        fused_matrix(&s.ops[o], c, U);
+        const cd r = round_entries(U, 64, acc, U32);
+        fused_operand(U32, t->fmats.data() + (size_t)fused_at[o] * kFusedWords + c * 64);
+        if (c == 0) acc += r;
+      }
+      fused_left = 3;
+    }
+    // updates inside a fused product keep their own tables (unused by the
+    // matrix cores) out of the running bias
+    const cd acc_op = fused_left > 0 ? cd(0) : acc;
     cd step = 0;
     for (int var = 0; var < 4; ++var)
       for (int c = 0; c < 2; ++c) {
-        const cd r = round_matrix(op.mat[var][c], acc, t->mats.data() + (o * 4 + var) * 16 + c * 8);
+        const cd r = round_matrix(op.mat[var][c], acc_op, t->mats.data() + (o * 4 + var) * 16 + c * 8);
         if (var == 0 && c == 0) step = r;
         // real form on (re b0, im b0, re b1, im b1): rows (re o0, im o0, re o1, im o1),
         // from the same rounded values
@@ -117,7 +200,8 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
               make_float4((float)k0.imag(), (float)k0.real(), (float)k1.imag(), (float)k1.real());
         }
       }
-    acc += step;
+    if (fused_left > 0) --fused_left;
+    else acc += step;
   }
   for (const Pass& ps : s.passes) {
     PassHost ph;
@@ -133,7 +217,7 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
       return TNC_E_INVALID;
     };
     // 256 threads per tile (T - R = 8), or 512 with the prefetching kernel
-    if (ps.w.tile_bits() - R > (p.opt.math == 0 ? 9 : 8))
+    if (ps.w.tile_bits() - R > (p.opt.math != 1 ? 9 : 8))
       return fail_t("pass tile too large for the thread block");
     if (!(ps.w.lo_bits >= 1 || ps.w.win_lo == 0)) return fail_t("pass tile lacks slot 0");
     for (const Phase& pp : ps.phases) {
@@ -152,6 +236,58 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
         dp.reg[b] = (int8_t)pp.reg[b];
       }
       t->phases.push_back(dp);
+      const int T = ps.w.tile_bits();
+      if (pp.mf) {
+        // fused phase: targets reg[0], tpos[4], tpos[5]; op 0's control (if
+        // any) reg[R-1]; every tile bit exactly once among registers and
+        // thread bits
+        const int TB = T - R;
+        if (nops < 3 || nops > R || R < 3 || TB < 6 || TB > kMaxThreadBits) return fail_t("bad fused phase shape");
+        uint32_t seen = 0;
+        for (int b = 0; b < R; ++b) seen |= 1u << pp.reg[b];
+        for (int q = 0; q < TB; ++q) {
+          if (pp.tpos[q] < 0 || pp.tpos[q] >= T || (seen >> pp.tpos[q] & 1u)) return fail_t("bad fused thread map");
+          seen |= 1u << pp.tpos[q];
+        }
+        const int tg[3] = {pp.reg[0], pp.tpos[4], pp.tpos[5]};
+        for (int b = 0; b < 3; ++b) {
+          const SweepOp& op = s.ops[pp.op_begin + b];
+          if (op.kind != OP_CU || op.xrow[0] >= 0 || op.xrow[1] >= 0) return fail_t("fused update with variants");
+          if (!ps.w.contains(op.target) || ps.w.local(op.target) != tg[b]) return fail_t("fused target not canonical");
+          if (b > 0 && (op.control < 0 || !ps.w.contains(op.control) || ps.w.local(op.control) != tg[b - 1]))
+            return fail_t("fused control not canonical");
+          if (b == 0 && op.control >= 0 && (!ps.w.contains(op.control) || ps.w.local(op.control) != pp.reg[R - 1]))
+            return fail_t("fused op 0 control not in the top register bit");
+        }
+        // the staircase tail on the vector ALUs
+        for (int b = 3; b < nops; ++b) {
+          const SweepOp& op = s.ops[pp.op_begin + b];
+          const int ctl = b == 3 ? pp.tpos[5] : pp.reg[b - 3];
+          if (op.kind != OP_CU || !ps.w.contains(op.target) || ps.w.local(op.target) != pp.reg[b - 2] ||
+              op.control < 0 || !ps.w.contains(op.control) || ps.w.local(op.control) != ctl)
+            return fail_t("fused phase tail not canonical");
+          if (pp.reg[b - 2] == pp.reg[R - 1] && s.ops[pp.op_begin].control >= 0)
+            return fail_t("fused phase tail on op 0's control bit");
+        }
+        t->phases.back().pad = 1;
+        for (int i = 0; i < kPhaseOffs; ++i) {
+          uint32_t w = 0;
+          if (i < (1 << R)) w = phase_entry_offset(dp, R, i);
+          else if (i >= kPhaseEntries && i - kPhaseEntries < TB) w = swz(1u << pp.tpos[i - kPhaseEntries]) << 3;
+          t->poffs.push_back(w);
+        }
+        for (int b = 0; b < nops; ++b) {
+          const int o = pp.op_begin + b;
+          DevOp d;
+          std::memset(&d, 0, sizeof(d));
+          d.cloc = -1;
+          d.xrow0 = (int16_t)s.ops[o].xrow[0];
+          d.xrow1 = (int16_t)s.ops[o].xrow[1];
+          d.mat = o;
+          t->ops[o] = d;
+        }
+        continue;
+      }
       for (int i = 0; i < kPhaseOffs; ++i) t->poffs.push_back(i < (1 << R) ? phase_entry_offset(dp, R, i) : 0u);
       for (int b = 0; b < nops; ++b) {
         const int o = pp.op_begin + b;
@@ -253,6 +389,8 @@ BatchLayout batch_layout(const Plan& p, const HostTables& t, int storage) {
 // with a split window must keep at least 2 contiguous low slots.
 int check_storage(const HostTables& t, int storage) {
   if (storage != TNC_STORE_C64 && !is_s16(storage)) return set_err(TNC_E_INVALID, "unknown storage mode");
+  if (is_s16(storage) && !t.fmats.empty())
+    return set_err(TNC_E_INVALID, "16-bit storage runs no fused matrix-core phases (math = 2)");
   if (is_s16(storage))
     for (const PassHost& ph : t.passes) {
       if (ph.w.lo_bits == 1) return set_err(TNC_E_INVALID, "16-bit storage needs low_bits >= 2");
@@ -271,6 +409,7 @@ struct DevSched {
   float4* d_mrows = nullptr;
   DevPhase* d_phases = nullptr;
   uint32_t* d_poffs = nullptr;
+  float4* d_fmats = nullptr;
   double2* d_seg = nullptr;
   double2* d_J = nullptr;
   LateOpDev* d_prog = nullptr;
@@ -278,7 +417,7 @@ struct DevSched {
     int prev = 0;
     if (device >= 0 && hipGetDevice(&prev) == hipSuccess) {
       (void)hipSetDevice(device);
-      void* ptrs[] = {d_ops, d_mats, d_mrows, d_phases, d_poffs, d_seg, d_J, d_prog};
+      void* ptrs[] = {d_ops, d_mats, d_mrows, d_phases, d_poffs, d_fmats, d_seg, d_J, d_prog};
       for (void* q : ptrs)
         if (q) (void)hipFree(q);
       (void)hipSetDevice(prev);
@@ -336,6 +475,7 @@ int get_dev_sched(Plan& p, int k, std::shared_ptr<DevSched>* out) {
   if ((rc = upload(&ds->d_ops, ds->host.ops)) || (rc = upload(&ds->d_mats, ds->host.mats)) ||
       (rc = upload(&ds->d_mrows, ds->host.mrows)) ||
       (rc = upload(&ds->d_phases, ds->host.phases)) || (rc = upload(&ds->d_poffs, ds->host.poffs)) ||
+      (rc = upload(&ds->d_fmats, ds->host.fmats)) ||
       (rc = upload(&ds->d_seg, ds->host.seg)) ||
       (rc = upload(&ds->d_J, J)) || (rc = upload(&ds->d_prog, ds->host.prog)))
     return rc;
@@ -398,12 +538,14 @@ InitArgs init_args(const Plan& p, const HostTables& t, float2* B, const uint8_t*
   return a;
 }
 
-PassArgs pass_args(const Plan& p, const PassHost& ph, const DevPhase* phases, const uint32_t* poffs, const DevOp* ops,
-                   const float* mats, const float4* mrows, float2* B, const uint8_t* bits, int nb) {
+PassArgs pass_args(const Plan& p, const PassHost& ph, const DevPhase* phases, const uint32_t* poffs,
+                   const float4* fmats, const DevOp* ops, const float* mats, const float4* mrows, float2* B,
+                   const uint8_t* bits, int nb) {
   PassArgs a;
   std::memset(&a, 0, sizeof(a));
   a.phases = phases + ph.phase_off;
   a.poffs = poffs + (size_t)ph.phase_off * kPhaseOffs;
+  a.fmats = fmats ? fmats + (size_t)ph.phase_off * kFusedWords : nullptr;
   a.ops = ops;
   a.mats = mats;
   a.mrows = mrows;
@@ -533,7 +675,7 @@ int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k
     int cur = 0;
     ScaleMap map = init_map(p);
     for (const PassHost& ph : t.passes) {
-      PassArgs a = pass_args(p, ph, ds.d_phases, ds.d_poffs, ds.d_ops, ds.d_mats, ds.d_mrows, B, bits, nb);
+      PassArgs a = pass_args(p, ph, ds.d_phases, ds.d_poffs, ds.d_fmats, ds.d_ops, ds.d_mats, ds.d_mrows, B, bits, nb);
       a.rmats = rmats;
       a.rstride = rstride;
       a.rmrows = rmrows;
@@ -643,7 +785,7 @@ int emulate(Plan& p, int k, int nb, const uint8_t* bits, int storage, cd* out) {
   int cur = 0;
   ScaleMap map = init_map(p);
   for (const PassHost& ph : t.passes) {
-    PassArgs a = pass_args(p, ph, t.phases.data(), t.poffs.data(), t.ops.data(), t.mats.data(), t.mrows.data(), B.data(), bits, nb);
+    PassArgs a = pass_args(p, ph, t.phases.data(), t.poffs.data(), t.fmats.empty() ? nullptr : t.fmats.data(), t.ops.data(), t.mats.data(), t.mrows.data(), B.data(), bits, nb);
     a.rmats = rmats.data();
     a.rstride = rstride;
     if (s16) {
@@ -770,10 +912,12 @@ int tnc_plan(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, c
     o.reg_adapt = opt->reg_adapt;
   }
   if (o.max_tile_bits < 6 || o.max_tile_bits > 14 || o.reg_bits < 1 || o.reg_bits > 5 || o.low_bits < 1 ||
-      o.low_bits > o.max_tile_bits - 2 || o.math < 0 || o.math > 1 || o.pipeline < 0 || o.pipeline > 2 ||
+      o.low_bits > o.max_tile_bits - 2 || o.math < 0 || o.math > 2 || o.pipeline < 0 || o.pipeline > 2 ||
       o.late_fold < -1 || o.late_fold > 3 || o.reg_adapt < 0 || o.reg_adapt > 1 ||
-      o.max_tile_bits - o.reg_bits > (o.math == 0 && o.pipeline != 2 ? 9 : 8))
+      o.max_tile_bits - o.reg_bits > (o.math != 1 ? 9 : 8))
     return set_err(TNC_E_INVALID, "tile options out of range");
+  if (o.math == 2 && o.pipeline == 1)
+    return set_err(TNC_E_INVALID, "fused matrix-core phases (math = 2) need pipeline 0 or 2");
   if (n < 2 || d < 2 || (int64_t)n * (d + 1) > (1 << 24)) return set_err(TNC_E_DOMAIN, "need n >= 2, d >= 2");
   std::vector<cd> one((size_t)(d + 1) * n * 4);
   for (size_t i = 0; i < one.size(); ++i) one[i] = cd(one_qubit[i].re, one_qubit[i].im);

@@ -92,6 +92,13 @@ SMALL = [
     # persistent blocks prefetching into registers
     (16, 30, 1, 0.3, 4, 8, dict(pipeline=2, reg_bits=4, max_tile_bits=12)),
     (15, 29, 0, 0.3, 3, 8, dict(pipeline=2, reg_bits=3, max_tile_bits=11)),
+    # runs of three updates fused into 8x8 products on the matrix cores:
+    # 128-thread tiles (two per block), 64-thread tiles (four per block),
+    # 256-thread tiles, and the prefetching blocks
+    (14, 28, 1, 0.3, 4, 6, dict(math=2, max_tile_bits=11, low_bits=4, reg_bits=4)),
+    (12, 24, 0, 0.3, 3, 5, dict(math=2, max_tile_bits=9, low_bits=3, reg_bits=3)),
+    (13, 26, 1, 0.0, 6, 4, dict(math=2, max_tile_bits=12, low_bits=4, reg_bits=4)),
+    (16, 30, 0, 0.3, 4, 8, dict(math=2, pipeline=2, max_tile_bits=12, reg_bits=4)),
 ]
 
 
@@ -107,7 +114,7 @@ def test_small_circuits(n, d, fp, dense, k, nb, opts):
 
 @pytest.mark.parametrize("opts", [None, dict(pipeline=1), dict(pipeline=1, reg_bits=4),
                                   dict(pipeline=2, reg_bits=4, max_tile_bits=12),
-                                  dict(max_tile_bits=14, low_bits=3)])
+                                  dict(max_tile_bits=14, low_bits=3), dict(math=2)])
 def test_medium_config_restriction(opts):
     # medium workload (d = 40, w = 20), restricted to 24 qubits, 64 batches,
     # k = 6: 8192 tiles per pass, so persistent blocks loop over many tiles
@@ -144,7 +151,8 @@ def test_precision_config_restriction():
     assert_close(got, ref, c.n)
 
 
-@pytest.mark.parametrize("opts", [None, dict(max_tile_bits=12), dict(max_tile_bits=14, low_bits=3)])
+@pytest.mark.parametrize("opts", [None, dict(max_tile_bits=12), dict(max_tile_bits=14, low_bits=3),
+                                  dict(max_tile_bits=12, math=2)])
 def test_full_width_restriction(opts):
     # full-width shape (d = 66, w = 33: a 2^33 complex64 boundary tensor)
     # restricted to 22 qubits, k = 8, in the tile configurations the
@@ -160,7 +168,8 @@ def test_full_width_restriction(opts):
 @pytest.mark.parametrize("n,d,k,opts", [(70, 20, 0, None), (70, 21, 4, None), (40, 33, 8, None),
                                          # the full-width shape itself (2^33-entry tensor, 81 GiB
                                          # of workspace) in the benchmark's tile configuration
-                                         (70, 66, 8, dict(max_tile_bits=12))])
+                                         (70, 66, 8, dict(max_tile_bits=12)),
+                                         (70, 66, 8, dict(max_tile_bits=12, math=2))])
 def test_full_size_clifford_matches_tableau(n, d, k, opts):
     from paper_2608_13110_amd import Plan
     c = W.brickwork_circuit(n, d, 0, W.rng_for(402, n, d))

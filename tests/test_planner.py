@@ -111,7 +111,10 @@ TILES = [dict(max_tile_bits=6, low_bits=2, reg_bits=3), dict(max_tile_bits=6, lo
          # late removals folded into the join launch (the default for large tensors)
          dict(late_fold=3), dict(late_fold=1, max_tile_bits=8, low_bits=3, reg_bits=4),
          # passes narrowed to reg_bits - 1 where that costs no phase
-         dict(reg_adapt=1, max_tile_bits=8, low_bits=4, reg_bits=5)]
+         dict(reg_adapt=1, max_tile_bits=8, low_bits=4, reg_bits=5),
+         # runs of three updates fused into 8x8 products on the matrix cores
+         dict(math=2, max_tile_bits=9, low_bits=3, reg_bits=3), dict(math=2, max_tile_bits=10, low_bits=4, reg_bits=4),
+         dict(math=2, max_tile_bits=11, low_bits=4, reg_bits=5, late_fold=3)]
 
 
 @pytest.mark.parametrize("opts", TILES)
@@ -183,6 +186,27 @@ def test_block_scaled_storage_is_rejected_with_one_low_slot():
     p = Plan.from_circuit(c, dict(max_tile_bits=8, low_bits=1, reg_bits=3))
     with pytest.raises(TncError):
         p.debug_emulate_device(W.random_bitstrings(14, 1, W.rng_for(310)), 2, 1)
+
+
+def test_fused_phases_restrictions():
+    # fused 8x8 phases run only in the plain pass kernel on complex64 storage
+    c = H.mixed_circuit(14, 28, 98)
+    with pytest.raises(TncError):
+        Plan.from_circuit(c, dict(math=2, max_tile_bits=10, reg_bits=4, pipeline=1))
+    p = Plan.from_circuit(c, dict(math=2, max_tile_bits=10, low_bits=4, reg_bits=4))
+    with pytest.raises(TncError):
+        p.debug_emulate_device(W.random_bitstrings(14, 1, W.rng_for(312)), 2, 1)
+    # fused phases take over the first three updates of staircases of three
+    # or more: the same phases and updates as the vector-ALU plan, different
+    # FP32 rounding (so the fused path did run), the same amplitudes
+    q = Plan.from_circuit(c, dict(max_tile_bits=10, low_bits=4, reg_bits=4))
+    base = q.info(2)
+    assert p.info(2)["n_ops"] == base["n_ops"] and p.info(2)["n_phases"] == base["n_phases"]
+    bits = W.random_bitstrings(14, 2, W.rng_for(313))
+    a, b = p.debug_emulate_device(bits, 2), q.debug_emulate_device(bits, 2)
+    assert not np.array_equal(a, b)
+    per, l2 = H.amp_errors(a, b, 14)
+    assert per < H.TOL_C64 and l2 < H.TOL_C64
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
