@@ -132,6 +132,55 @@ def run_workload(name, steps, warmup, torch, W, Plan, profile_begin, profile_end
     )
 
 
+def sampling_bench(torch, W, Plan, batches=16, M=10.0):
+    """Samplers on the precision workload's batches (Sec. 4.1, Sec. 4.2):
+    one batched sample per contraction (uniform prefix, suffix from p(b|a))
+    and frugal rejection on the same amplitudes.  Reports samples per second
+    of the whole path, the sampler kernel's time, and two Porter-Thomas
+    checks: the mean |A Q_a - 1| against sqrt(2/(pi B)), and the frugal
+    acceptance against (1 - e^-M)/M."""
+    import math
+    import numpy as np
+    from paper_2608_13110_amd import frugal_accept, sample_batched
+    spec = WORKLOADS["precision"]
+    k = spec["k"]
+    circ = W.config_circuit(spec["cid"])
+    bits = torch.from_numpy(W.config_bitstrings(spec["cid"])[:batches]).cuda()
+    rng = np.random.default_rng(707)
+    u = torch.from_numpy(rng.random(batches)).cuda()
+    uf = torch.from_numpy(rng.random(batches << k)).cuda()
+    plan = Plan.from_circuit(circ)
+    plan.prepare(k)
+    ws = torch.empty(plan.workspace_bytes(k, 1), dtype=torch.uint8, device="cuda")
+    out = torch.empty((batches, 1 << k), dtype=torch.complex128, device="cuda")
+    stream = torch.cuda.current_stream()
+    plan.amplitudes(bits[:1], k, out=out[:1], workspace=ws, stream=stream)
+    sample_batched(out[:1], u[:1])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.time()
+    sampler_ms = 0.0
+    for i in range(batches):
+        plan.amplitudes(bits[i:i + 1], k, out=out[i:i + 1], workspace=ws, stream=stream)
+        e0.record(stream)
+        b, q = sample_batched(out[i:i + 1], u[i:i + 1])
+        e1.record(stream)
+        e1.synchronize()
+        sampler_ms += e0.elapsed_time(e1)
+    wall = time.time() - t0
+    b, q = sample_batched(out, u)
+    acc, _ = frugal_accept(out, circ.n, M, uf)
+    torch.cuda.synchronize()
+    A_dev = np.abs(q.cpu().numpy() * 2.0 ** (circ.n - k) - 1.0)
+    return {"workload": spec["desc"] + f", {batches} uniform prefixes",
+            "batched_samples_per_s": round(batches / wall, 3),
+            "sampler_kernel_us": round(1e3 * sampler_ms / batches, 2),
+            "mean_abs_AQ_minus_1": round(float(A_dev.mean()), 4),
+            "porter_thomas_mean_abs_AQ_minus_1": round(math.sqrt(2.0 / (math.pi * (1 << k))), 4),
+            "frugal_M": M, "frugal_acceptance": round(float(acc.float().mean().item()), 4),
+            "porter_thomas_acceptance": round((1.0 - math.exp(-M)) / M, 4)}
+
+
 def storage_modes(torch, W, Plan, profile_begin, profile_end, batches=16):
     """The precision workload's batches with complex64 storage and with the
     FP16 / BF16 block-scaled storage modes: throughput, pass bandwidth
@@ -352,6 +401,13 @@ def main():
         except Exception as e:  # noqa: BLE001
             storage = {"error": f"{type(e).__name__}: {e}"}
         torch.cuda.empty_cache()
+    sampling = None
+    if not args.no_secondary:
+        try:
+            sampling = sampling_bench(torch, W, Plan)
+        except Exception as e:  # noqa: BLE001
+            sampling = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.empty_cache()
     serving = None
     if not args.no_serving:
         try:
@@ -391,6 +447,8 @@ def main():
         line["secondary"]["hbm_frac"] = round(secondary["pass_gbs"] / HBM_PEAK_GBS, 4)
     if storage is not None:
         line["storage_modes"] = storage
+    if sampling is not None:
+        line["sampling"] = sampling
     if serving is not None:
         line["serving"] = serving
     if not args.no_cpu_baseline:

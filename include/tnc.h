@@ -177,6 +177,36 @@ int tnc_logxeb(const tnc_c128* d_amp, int32_t n_batches, int32_t k, const int32_
                double* d_result, void* stream);
 
 /*
+ * Batched sampling, Sec. 4.2 (steps 3-4 of the batched sampler): for each
+ * batch (one prefix a, its 2^k amplitudes from tnc_amplitudes) the
+ * probabilities p(a, b) = |Z[b]|^2 and Q_a = sum_b p(a, b) in FP64, and one
+ * suffix b drawn from p(b | a) = p(a, b) / Q_a: the smallest b whose prefix
+ * sum p(a, 0) + ... + p(a, b) exceeds u Q_a (2^k - 1 if rounding leaves
+ * none).  The prefix a itself is the caller's uniform draw.
+ *   d_amp: device, n_batches * 2^k amplitudes (index b as in tnc_amplitudes).
+ *   d_u:   device, n_batches uniforms in [0, 1) (the caller's random numbers).
+ *   d_b:   device, n_batches sampled suffixes (out).
+ *   d_q:   device, n_batches marginals Q_a (out).
+ *   0 <= k <= 10; n_batches = 0 does nothing.  Asynchronous on `stream`.
+ */
+int tnc_sample_batched(const tnc_c128* d_amp, int32_t n_batches, int32_t k, const double* d_u, int32_t* d_b,
+                       double* d_q, void* stream);
+
+/*
+ * Frugal rejection, Sec. 4.1 (steps 2-3): for each candidate amplitude,
+ * z = 2^n |amp|^2 and acceptance when u < min(1, z / M).  Candidates are the
+ * caller's uniform draws (their amplitudes from tnc_amplitudes with k = 0, or
+ * the entries of batches).
+ *   d_amp:    device, count amplitudes.
+ *   d_u:      device, count uniforms in [0, 1).
+ *   d_accept: device, count bytes, 1 = accepted (out).
+ *   d_z:      device, count rescaled probabilities z (out).
+ *   1 <= n_qubits <= 1000; M > 0 finite.  Asynchronous on `stream`.
+ */
+int tnc_frugal_accept(const tnc_c128* d_amp, int64_t count, int32_t n_qubits, double M, const double* d_u,
+                      uint8_t* d_accept, double* d_z, void* stream);
+
+/*
  * Kernel timing with HIP events recorded on the launch stream around every
  * launch of tnc_amplitudes while profiling is on (process-wide).
  * tnc_profile_end waits for the recorded events and returns the summed

@@ -18,6 +18,14 @@ Contents
                  with its empirical standard error and 95 % interval.
 ``tv_conditional`` total-variation distance of the conditional
                  distributions p(b|a), the accuracy metric of Sec. 5.1.
+``batched_sample`` the batched sampler of Sec. 4.2: one suffix b per batch
+                 from p(b|a) = p(a, b) / Q_a, by inverse CDF of a given
+                 uniform; with ``batched_distribution`` (q_k and its TV).
+``frugal_accept`` frugal rejection of Sec. 4.1: accept x with probability
+                 min(1, z_x / M), z_x = 2^n p(x), for a given uniform; with
+                 ``frugal_distribution`` (q_M and its TV) and the
+                 Porter-Thomas closed forms ``frugal_alpha``, ``frugal_tv``,
+                 ``batched_tv``.
 
 Every function here has pins in ``tests/test_oracle.py`` (brute-force
 Kronecker products, a stabilizer tableau for T-free Cliffords, the closed
@@ -134,3 +142,79 @@ def tv_conditional(za: np.ndarray, zb: np.ndarray) -> np.ndarray:
     pa = pa / pa.sum(axis=1, keepdims=True)
     pb = pb / pb.sum(axis=1, keepdims=True)
     return 0.5 * np.abs(pa - pb).sum(axis=1)
+
+
+# ---------------------------------------------------------------------------
+# Samplers on top of the amplitudes (Sec. 4.1, Sec. 4.2).  The random numbers
+# are inputs (uniforms in [0, 1)), so a sample is a function of its inputs.
+
+def batched_sample(amps: np.ndarray, u: np.ndarray):
+    """Batched sampling, Sec. 4.2, steps 3-4: for each batch (prefix a) the
+    probabilities p(a, b) = |Z[b]|^2, their sum Q_a, and the suffix b drawn
+    from p(b | a) = p(a, b) / Q_a by inverse CDF: the smallest b with
+    p(a, 0) + ... + p(a, b) > u Q_a (b = 2^k - 1 if rounding leaves none).
+
+    amps: (batches, 2^k) complex; u: (batches,) uniforms.  FP64 throughout,
+    the prefix sums taken left to right.  Returns (b int64, Q float64).
+    """
+    p = np.abs(np.asarray(amps, dtype=np.complex128)) ** 2
+    q = p.sum(axis=1)
+    out = np.empty(p.shape[0], dtype=np.int64)
+    for i in range(p.shape[0]):
+        target = float(u[i]) * q[i]
+        acc = 0.0
+        b = p.shape[1] - 1
+        for j in range(p.shape[1]):
+            acc += p[i, j]
+            if acc > target:
+                b = j
+                break
+        out[i] = b
+    return out, q
+
+
+def batched_distribution(p_full: np.ndarray, k: int):
+    """The output distribution of the batched sampler with uniform prefixes
+    (Sec. 4.2): q_k(a, b) = p(a, b) / (A Q_a), A = 2^(n-k); returns (q_k,
+    TV(q_k, p)) with the TV summed over all (a, b) by its definition."""
+    p = np.asarray(p_full, dtype=np.float64)
+    B = 1 << k
+    A = p.size // B
+    pa = p.reshape(A, B)
+    qa = pa.sum(axis=1, keepdims=True)
+    q = (pa / (A * qa)).reshape(-1)
+    return q, 0.5 * float(np.abs(q - p).sum())
+
+
+def frugal_accept(amps: np.ndarray, n: int, M: float, u: np.ndarray):
+    """Frugal rejection, Sec. 4.1, steps 2-3: z_x = 2^n |amp_x|^2 and the
+    candidate is accepted when u < min(1, z_x / M).  Returns (accept bool,
+    z float64)."""
+    z = np.ldexp(np.abs(np.asarray(amps, dtype=np.complex128)) ** 2, n)
+    return np.asarray(u, dtype=np.float64) < np.minimum(1.0, z / M), z
+
+
+def frugal_distribution(p_full: np.ndarray, M: float):
+    """The distribution q_M of accepted candidates (uniform candidates,
+    acceptance min(1, z_x / M), Sec. 4.1), its acceptance probability and
+    TV(q_M, p)."""
+    p = np.asarray(p_full, dtype=np.float64)
+    acc = np.minimum(1.0, p * p.size / M)
+    alpha = float(acc.mean())
+    q = acc / acc.sum()
+    return q, alpha, 0.5 * float(np.abs(q - p).sum())
+
+
+def frugal_alpha(M: float) -> float:
+    """Mean acceptance under Porter-Thomas z ~ Exp(1): (1 - e^-M) / M."""
+    return (1.0 - math.exp(-M)) / M
+
+
+def frugal_tv(M: float) -> float:
+    """TV of frugal rejection under Porter-Thomas: exp(-M / (1 - e^-M))."""
+    return math.exp(-M / (1.0 - math.exp(-M)))
+
+
+def batched_tv(k: int) -> float:
+    """Expected TV of batched sampling under Porter-Thomas: 1/sqrt(2 pi 2^k)."""
+    return 1.0 / math.sqrt(2.0 * math.pi * (1 << k))

@@ -38,7 +38,7 @@ EXPORTED = [
     "tnc_amplitudes_host", "tnc_logxeb", "tnc_release", "tnc_strerror", "tnc_last_error",
     "tnc_debug_execute_host", "tnc_debug_emulate_device", "tnc_profile_begin", "tnc_profile_end",
     "tnc_autotune", "tnc_server_create", "tnc_server_destroy", "tnc_server_set_tuning", "tnc_server_submit",
-    "tnc_server_wait", "tnc_server_summary", "tnc_debug_arena_check",
+    "tnc_server_wait", "tnc_server_summary", "tnc_debug_arena_check", "tnc_sample_batched", "tnc_frugal_accept",
 ]
 
 
@@ -130,6 +130,8 @@ def lib() -> ctypes.CDLL:
     L.tnc_amplitudes.argtypes = [vp, i32, vp, i32, i32, vp, vp, u64, vp]
     L.tnc_amplitudes_host.argtypes = [vp, i32, vp, i32, i32, vp]
     L.tnc_logxeb.argtypes = [vp, i32, i32, vp, i32, vp, vp]
+    L.tnc_sample_batched.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    L.tnc_frugal_accept.argtypes = [vp, ctypes.c_int64, i32, ctypes.c_double, vp, vp, vp, vp]
     L.tnc_release.argtypes = [vp]
     L.tnc_release.restype = None
     L.tnc_strerror.argtypes = [ctypes.c_int]
@@ -308,6 +310,43 @@ def logxeb(amps, k: int, n_qubits: int, select=None, stream=None):
                             select.data_ptr() if select is not None else None, int(n_qubits),
                             res.data_ptr(), ctypes.c_void_p(s.cuda_stream)))
     return res
+
+
+def sample_batched(amps, u, stream=None):
+    """Batched sampling (Sec. 4.2, ``tnc_sample_batched``) on the GPU.
+
+    amps: torch complex128 (batches, 2^k) on the device; u: torch float64
+    (batches,) uniforms in [0, 1) on the device (the caller's random
+    numbers).  Returns (b int32, Q float64) device tensors: the suffix drawn
+    from p(b | a) and the prefix marginal Q_a of each batch.
+    """
+    import torch
+    nb, B = int(amps.shape[0]), int(amps.shape[1])
+    k = B.bit_length() - 1
+    if B != 1 << k:
+        raise ValueError("batches must hold 2^k amplitudes")
+    b = torch.empty(nb, dtype=torch.int32, device=amps.device)
+    q = torch.empty(nb, dtype=torch.float64, device=amps.device)
+    s = stream if stream is not None else torch.cuda.current_stream(amps.device)
+    _check(lib().tnc_sample_batched(amps.data_ptr(), nb, k, u.data_ptr(), b.data_ptr(), q.data_ptr(),
+                                    ctypes.c_void_p(s.cuda_stream)))
+    return b, q
+
+
+def frugal_accept(amps, n_qubits: int, M: float, u, stream=None):
+    """Frugal rejection (Sec. 4.1, ``tnc_frugal_accept``) on the GPU.
+
+    amps: torch complex128 device tensor of candidate amplitudes (any shape);
+    u: torch float64 device uniforms of the same size.  Returns (accept uint8,
+    z float64) device tensors of that shape.
+    """
+    import torch
+    accept = torch.empty(amps.shape, dtype=torch.uint8, device=amps.device)
+    z = torch.empty(amps.shape, dtype=torch.float64, device=amps.device)
+    s = stream if stream is not None else torch.cuda.current_stream(amps.device)
+    _check(lib().tnc_frugal_accept(amps.data_ptr(), int(amps.numel()), int(n_qubits), float(M), u.data_ptr(),
+                                   accept.data_ptr(), z.data_ptr(), ctypes.c_void_p(s.cuda_stream)))
+    return accept, z
 
 
 def autotune(n: int, d: int, k: int, candidates: Sequence[dict], storage: int = STORE_C64, reps: int = 3):

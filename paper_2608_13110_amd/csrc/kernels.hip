@@ -1139,6 +1139,89 @@ hipError_t launch_late_ops(const LateOpsArgs& a, hipStream_t s) {
 // log-XEB (Sec. 5.2): F = gamma + n ln 2 + mean_i ln p_i with p_i = |amp|^2
 // of the selected component of each batch (sel == nullptr: every component).
 // One block, FP64 throughout.  result = {F, SE, F - 1.96 SE, F + 1.96 SE, N}.
+// Batched sampling (Sec. 4.2, steps 3-4): one block per batch.  Thread t
+// holds entries [t E, t E + E) of the batch's 2^k (E = 2^k / 256 or 1),
+// their probabilities |Z|^2 in FP64 and their sum; a block scan of those
+// sums gives every entry's inclusive prefix; the suffix is the smallest b
+// whose prefix exceeds u Q_a (the last suffix if rounding leaves none).
+__global__ __launch_bounds__(kBlock) void k_sample_batched(const double2* amps, int k, const double* u, int32_t* bout,
+                                                           double* qout) {
+  __shared__ double scan[kBlock];
+  __shared__ int best;
+  const long long batch = blockIdx.x;
+  const int B = 1 << k;
+  const int E = B > kBlock ? B / kBlock : 1;
+  const int t = threadIdx.x;
+  const int first = t * E;
+  const double2* z = amps + batch * (long long)B;
+  double p[kMaxSampleEntries];
+  double local = 0.0;
+#pragma unroll
+  for (int e = 0; e < kMaxSampleEntries; ++e) {
+    p[e] = 0.0;
+    if (e < E && first + e < B) {
+      const double2 v = z[first + e];
+      p[e] = v.x * v.x + v.y * v.y;
+      local += p[e];
+    }
+  }
+  if (t == 0) best = B - 1;
+  scan[t] = local;
+  __syncthreads();
+  // inclusive Hillis-Steele scan over the thread sums
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const double add = t >= off ? scan[t - off] : 0.0;
+    __syncthreads();
+    scan[t] += add;
+    __syncthreads();
+  }
+  const double q = scan[kBlock - 1];
+  const double target = u[batch] * q;
+  double run = scan[t] - local;  // exclusive prefix of this thread's entries
+#pragma unroll
+  for (int e = 0; e < kMaxSampleEntries; ++e) {
+    if (e < E && first + e < B) {
+      run += p[e];
+      if (run > target) {
+        atomicMin(&best, first + e);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    bout[batch] = best;
+    qout[batch] = q;
+  }
+}
+
+// Frugal rejection (Sec. 4.1, steps 2-3): z = 2^n |amp|^2, accepted when
+// u < min(1, z / M).
+__global__ __launch_bounds__(kBlock) void k_frugal_accept(const double2* amps, long long count, int n, double M,
+                                                          const double* u, uint8_t* accept, double* zout) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const double2 v = amps[i];
+  const double z = ldexp(v.x * v.x + v.y * v.y, n);
+  zout[i] = z;
+  accept[i] = u[i] < fmin(1.0, z / M) ? 1 : 0;
+}
+
+hipError_t launch_sample_batched(const double2* amps, int n_batches, int k, const double* u, int32_t* b, double* q,
+                                 hipStream_t s) {
+  if (n_batches <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sample_batched, dim3((unsigned)n_batches), dim3(kBlock), 0, s, amps, k, u, b, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_frugal_accept(const double2* amps, long long count, int n, double M, const double* u,
+                                uint8_t* accept, double* z, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const long long blocks = (count + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_frugal_accept, dim3((unsigned)blocks), dim3(kBlock), 0, s, amps, count, n, M, u, accept, z);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kBlock) void k_logxeb(const double2* amps, int n_batches, int k,
                                                    const int32_t* sel, int n_qubits, double* result) {
   __shared__ double s1[kBlock], s2[kBlock];

@@ -459,6 +459,12 @@ hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int R, hipStream_t s);
 hipError_t launch_late(const LateArgs& a, bool in_c64, hipStream_t s);
 hipError_t launch_late_ops(const LateOpsArgs& a, hipStream_t s);
+// Batched sampling handles up to 2^10 suffixes per batch: 4 per thread.
+constexpr int kMaxSampleEntries = 4;
+hipError_t launch_sample_batched(const double2* amps, int n_batches, int k, const double* u, int32_t* b, double* q,
+                                 hipStream_t s);
+hipError_t launch_frugal_accept(const double2* amps, long long count, int n, double M, const double* u,
+                                uint8_t* accept, double* z, hipStream_t s);
 hipError_t launch_logxeb(const double2* amps, int n_batches, int k, const int32_t* sel, int n_qubits,
                          double* result, hipStream_t s);
 

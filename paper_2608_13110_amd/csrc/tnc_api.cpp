@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -1042,6 +1043,29 @@ int tnc_logxeb(const tnc_c128* d_amp, int32_t n_batches, int32_t k, const int32_
   hipError_t e = launch_logxeb(reinterpret_cast<const double2*>(d_amp), n_batches, k, d_select, n_qubits, d_result,
                                static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_err(e, "logxeb launch");
+  return TNC_OK;
+}
+
+int tnc_sample_batched(const tnc_c128* d_amp, int32_t n_batches, int32_t k, const double* d_u, int32_t* d_b,
+                       double* d_q, void* stream) {
+  if (n_batches < 0 || k < 0 || k > 10) return set_err(TNC_E_INVALID, "need n_batches >= 0 and 0 <= k <= 10");
+  if (n_batches == 0) return TNC_OK;
+  if (!d_amp || !d_u || !d_b || !d_q) return set_err(TNC_E_INVALID, "null argument");
+  hipError_t e = launch_sample_batched(reinterpret_cast<const double2*>(d_amp), n_batches, k, d_u, d_b, d_q,
+                                       static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_err(e, "batched sampling launch");
+  return TNC_OK;
+}
+
+int tnc_frugal_accept(const tnc_c128* d_amp, int64_t count, int32_t n_qubits, double M, const double* d_u,
+                      uint8_t* d_accept, double* d_z, void* stream) {
+  if (count < 0 || n_qubits < 1 || n_qubits > 1000 || !(M > 0.0) || !std::isfinite(M))
+    return set_err(TNC_E_INVALID, "need count >= 0, 1 <= n_qubits <= 1000 and a finite M > 0");
+  if (count == 0) return TNC_OK;
+  if (!d_amp || !d_u || !d_accept || !d_z) return set_err(TNC_E_INVALID, "null argument");
+  hipError_t e = launch_frugal_accept(reinterpret_cast<const double2*>(d_amp), (long long)count, n_qubits, M, d_u,
+                                      d_accept, d_z, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_err(e, "frugal rejection launch");
   return TNC_OK;
 }
 

@@ -177,3 +177,96 @@ def test_unmutated_oracle_passes_pins():
 @pytest.mark.parametrize("mutation", [1, 2, 3, 4, 5])
 def test_planted_mistakes_are_caught(mutation):
     assert not _pins_pass(mutation)
+
+
+# ---------------------------------------------------------------------------
+# Samplers (Sec. 4.1, Sec. 4.2)
+
+def _paper_pin(key):
+    with open(os.path.join(GOLD, "paper_pins.txt")) as f:
+        for line in f:
+            if line.startswith(key + " "):
+                return line.split()[1:]
+    raise KeyError(key)
+
+
+def test_batched_sample_is_the_inverse_cdf():
+    # uniforms on a fine grid land on every b in proportion to p(b|a), to
+    # within one grid step: the sampler draws from the conditional
+    rng = np.random.default_rng(501)
+    k, N = 4, 4096
+    amps = rng.standard_normal((3, 1 << k)) + 1j * rng.standard_normal((3, 1 << k))
+    amps[1, 5] = 0.0  # a zero-probability suffix is never drawn
+    u = (np.arange(N) + 0.5) / N
+    for i in range(3):
+        b, q = oracle.batched_sample(np.repeat(amps[i:i + 1], N, axis=0), u)
+        p = np.abs(amps[i]) ** 2
+        assert np.allclose(q, p.sum(), rtol=1e-15, atol=0)
+        counts = np.bincount(b, minlength=1 << k)
+        assert np.all(np.abs(counts - N * p / p.sum()) <= 1.0)
+        if i == 1:
+            assert counts[5] == 0
+    # u just below 1 takes the last suffix with p > 0; u = 0 the first
+    b, _ = oracle.batched_sample(amps[:1], np.array([np.nextafter(1.0, 0.0)]))
+    assert b[0] == np.flatnonzero(np.abs(amps[0]) > 0)[-1]
+    b, _ = oracle.batched_sample(amps[:1], np.array([0.0]))
+    assert b[0] == np.flatnonzero(np.abs(amps[0]) > 0)[0]
+
+
+def test_batched_tv_equals_prefix_marginal_form():
+    # Sec. 4.2, Eq. tv_norm: summing |q_k - p| over (a, b) equals
+    # (1/2) sum_a |Q_a - 1/A|, for any distribution
+    rng = np.random.default_rng(502)
+    for k in (1, 3, 6):
+        p = rng.random(1 << 12) ** 3
+        p /= p.sum()
+        q, tv = oracle.batched_distribution(p, k)
+        A = p.size >> k
+        qa = p.reshape(A, -1).sum(axis=1)
+        assert abs(q.sum() - 1.0) < 1e-12
+        assert abs(tv - 0.5 * np.abs(qa - 1.0 / A).sum()) < 1e-12
+
+
+def test_batched_tv_porter_thomas():
+    # Porter-Thomas probabilities: E TV = 1/sqrt(2 pi 2^k) (Sec. 4.2); the
+    # paper prints 2.5e-2 for k = 8
+    k = 8
+    printed = float(_paper_pin("BATCHED_TV")[1])
+    assert abs(oracle.batched_tv(k) - printed) < 0.05e-2
+    rng = np.random.default_rng(503)
+    p = rng.exponential(size=1 << 21)
+    p /= p.sum()
+    _, tv = oracle.batched_distribution(p, k)
+    # 2^13 prefixes: the mean of |N(0, s)| over them is within ~1 % (3 sd)
+    assert abs(tv / oracle.batched_tv(k) - 1.0) < 0.03
+
+
+def test_frugal_rejection_closed_forms():
+    # Sec. 4.1: acceptance (1 - e^-M)/M and TV exp(-M/(1 - e^-M)) under
+    # Porter-Thomas; the paper prints TV ~ 4.5e-5 at M = 10
+    printed = float(_paper_pin("FRUGAL_TV")[1])
+    assert abs(oracle.frugal_tv(10.0) / printed - 1.0) < 0.02
+    assert abs(oracle.frugal_alpha(10.0) - (1 - math.exp(-10)) / 10) < 1e-15
+    rng = np.random.default_rng(504)
+    p = rng.exponential(size=1 << 22)
+    p /= p.sum()
+    for M in (2.0, 3.0, 5.0):
+        _, alpha, tv = oracle.frugal_distribution(p, M)
+        assert abs(alpha / oracle.frugal_alpha(M) - 1.0) < 0.005
+        assert abs(tv / oracle.frugal_tv(M) - 1.0) < 0.05
+    # M -> 0 accepts every candidate (q_M = uniform); a huge M reproduces p
+    _, alpha, _ = oracle.frugal_distribution(p, 1e-9)
+    assert alpha == 1.0
+    q, _, tv = oracle.frugal_distribution(p, 1e9)
+    assert tv < 1e-12
+
+
+def test_frugal_accept_rate_on_a_grid():
+    rng = np.random.default_rng(505)
+    n, M, N = 10, 4.0, 2048
+    amps = (rng.standard_normal(6) + 1j * rng.standard_normal(6)) * 2.0 ** (-n / 2)
+    u = (np.arange(N) + 0.5) / N
+    for a in amps:
+        acc, z = oracle.frugal_accept(np.full(N, a), n, M, u)
+        assert np.allclose(z, 2.0 ** n * abs(a) ** 2, rtol=1e-15, atol=0)
+        assert abs(acc.mean() - min(1.0, z[0] / M)) <= 1.0 / N

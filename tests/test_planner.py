@@ -214,3 +214,15 @@ def test_serving_arena_allocator(seed):
     # the serving loop's first-fit device-arena allocator, on the host
     from paper_2608_13110_amd import _check
     _check(lib().tnc_debug_arena_check(seed, 5000))
+
+
+def test_sampler_entry_points_validate_on_the_host():
+    # argument errors come back as status codes before any device work
+    L = lib()
+    assert L.tnc_sample_batched(None, 0, 3, None, None, None, None) == 0
+    assert L.tnc_sample_batched(None, 4, 11, None, None, None, None) == TNC_E_INVALID
+    assert L.tnc_sample_batched(None, 4, 3, None, None, None, None) == TNC_E_INVALID
+    assert L.tnc_frugal_accept(None, 0, 10, 2.0, None, None, None, None) == 0
+    assert L.tnc_frugal_accept(None, 8, 10, 0.0, None, None, None, None) == TNC_E_INVALID
+    assert L.tnc_frugal_accept(None, 8, 10, float("inf"), None, None, None, None) == TNC_E_INVALID
+    assert L.tnc_frugal_accept(None, 8, 0, 2.0, None, None, None, None) == TNC_E_INVALID
