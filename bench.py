@@ -37,6 +37,8 @@ METRIC = "amplitudes/s and boundary-tensor HBM GB/s (% of peak) at w=28/33; p99 
 WORKLOADS = {
     "full_width": dict(cid=4, k=8, desc="full_width n=70 d=66 w=33 T=468 k=8 (2^33 c64 boundary), 1 batch/step"),
     "precision": dict(cid=2, k=8, desc="precision n=70 d=56 w=28 T=400 k=8 (2^28 c64 boundary), 1 batch/step"),
+    # not the default: one batch needs 279 GB of the 288 GB of HBM
+    "width35": dict(cid=5, k=8, desc="width35 n=70 d=70 w=35 T=468 k=8 (2^35 c64 boundary, 256 GiB), 1 batch/step"),
 }
 
 
@@ -179,6 +181,47 @@ def sampling_bench(torch, W, Plan, batches=16, M=10.0):
             "porter_thomas_mean_abs_AQ_minus_1": round(math.sqrt(2.0 / (math.pi * (1 << k))), 4),
             "frugal_M": M, "frugal_acceptance": round(float(acc.float().mean().item()), 4),
             "porter_thomas_acceptance": round((1.0 - math.exp(-M)) / M, 4)}
+
+
+# The paper's steady-state time per contraction at this shape (n = d = 70,
+# w = 35, k = 8) on one node of 8 H100s, the tensor sharded over them (Sec. 5.3)
+PAPER_W35_S_PER_CONTRACTION_8XH100 = 32.16
+
+
+def width35_bench(torch, W, Plan, profile_begin, profile_end):
+    """One batch of the width-35 shape on this one GPU: the 2^35-entry
+    complex64 tensor (256 GiB) in place, the join output shrunk by folding
+    seven late removals.  No warmup step (a second batch would double the
+    time); the plan and its tables are prepared before the timed region."""
+    spec = WORKLOADS["width35"]
+    k = spec["k"]
+    circ = W.config_circuit(spec["cid"])
+    bits = torch.from_numpy(W.config_bitstrings(spec["cid"])[:1]).cuda()
+    opts = dict(max_tile_bits=12, math=2)
+    t0 = time.time()
+    plan = Plan.from_circuit(circ, opts)
+    plan.prepare(k)
+    prep_s = time.time() - t0
+    info = plan.info(k)
+    torch.cuda.empty_cache()
+    ws = torch.empty(plan.workspace_bytes(k, 1), dtype=torch.uint8, device="cuda")
+    out = torch.empty((1, 1 << k), dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+    profile_begin()
+    t0 = time.time()
+    plan.amplitudes(bits, k, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    prof = profile_end()
+    del ws
+    torch.cuda.empty_cache()
+    return {"workload": spec["desc"], "tile_options": opts, "s_per_batch": round(wall, 3),
+            "amplitudes_per_s": round((1 << k) / wall, 3), "passes": info["n_passes"],
+            "workspace_gb": round(info["workspace_per_batch"] / 1e9, 1), "prepare_s": round(prep_s, 1),
+            "pass_gbs": round(prof["pass_bytes"] / (prof["pass_ms"] / 1e3) / 1e9, 1),
+            "late_ms": round(prof["late_ms"], 1),
+            "paper_s_per_contraction_8xH100": PAPER_W35_S_PER_CONTRACTION_8XH100,
+            "paper_amplitudes_per_s_8xH100": round((1 << k) / PAPER_W35_S_PER_CONTRACTION_8XH100, 3)}
 
 
 def storage_modes(torch, W, Plan, profile_begin, profile_end, batches=16):
@@ -357,6 +400,7 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-storage", action="store_true", help="skip the 16-bit storage comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--no-width35", action="store_true", help="skip the width-35 batch (279 GB of HBM)")
     ap.add_argument("--options", default=None,
                     help="tile options as JSON (e.g. '{\"max_tile_bits\": 12}') instead of autotuning "
                          "(profiling runs fix them so that only the timed configuration launches)")
@@ -415,6 +459,13 @@ def main():
         except Exception as e:  # noqa: BLE001
             serving = {"error": f"{type(e).__name__}: {e}"}
         torch.cuda.empty_cache()
+    width35 = None
+    if not args.no_width35 and args.workload != "width35":
+        try:
+            width35 = width35_bench(torch, W, Plan, profile_begin, profile_end)
+        except Exception as e:  # noqa: BLE001
+            width35 = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.empty_cache()
     traffic = recorded_traffic(args.workload)
     roofline = {
         "bound": "hbm", "achieved": round(main_r["pass_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -449,6 +500,8 @@ def main():
         line["storage_modes"] = storage
     if sampling is not None:
         line["sampling"] = sampling
+    if width35 is not None:
+        line["width35"] = width35
     if serving is not None:
         line["serving"] = serving
     if not args.no_cpu_baseline:

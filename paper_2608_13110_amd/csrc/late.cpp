@@ -76,8 +76,11 @@ int build_late(const Plan& p, const Schedule& s, LatePlan* out, std::string* err
   if (k == 0) {
     j1 = std::min(nrem, 12);
   } else {
-    const int want = p.opt.late_fold == 0 ? (s.m_fix >= 26 ? 3 : 0) : std::max(0, p.opt.late_fold);
-    j1 = std::min(nrem, std::min(want, k <= 8 ? 3 : 1));
+    // 2^35-entry tensors (256 GiB of complex64) leave room for a join output
+    // of 2^(h-j) x 16 B only with j = 7 (4 GiB; the fold takes ~10 s)
+    const int want =
+        p.opt.late_fold == 0 ? (s.m_fix >= 35 ? 7 : s.m_fix >= 26 ? 3 : 0) : std::max(0, p.opt.late_fold);
+    j1 = std::min(nrem, std::min(want, k <= 8 ? 8 : 1));
   }
   const bool first_final = j1 == nrem;
   const int first_end = first_final ? nbody : (j1 == 0 ? 0 : rpos[j1 - 1] + 1);

@@ -131,7 +131,7 @@ struct Options {
   int math = 0;             // 0: vector ALU updates; 1: register-controlled updates on the matrix cores;
                             // 2: runs of three updates fused into 8x8 products on the matrix cores
   int pipeline = 0;         // 1: persistent, prefetching pass blocks where a block holds one tile
-  int late_fold = 0;        // removals folded into the join launch (0 auto, -1 none, 1..3)
+  int late_fold = 0;        // removals folded into the join launch (0 auto, -1 none, 1..8)
   int reg_adapt = 0;        // 1: a pass uses reg_bits - 1 when that needs no more phases; 0: never
 };
 

@@ -914,7 +914,7 @@ int tnc_plan(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, c
   }
   if (o.max_tile_bits < 6 || o.max_tile_bits > 14 || o.reg_bits < 1 || o.reg_bits > 5 || o.low_bits < 1 ||
       o.low_bits > o.max_tile_bits - 2 || o.math < 0 || o.math > 2 || o.pipeline < 0 || o.pipeline > 2 ||
-      o.late_fold < -1 || o.late_fold > 3 || o.reg_adapt < 0 || o.reg_adapt > 1 ||
+      o.late_fold < -1 || o.late_fold > 8 || o.reg_adapt < 0 || o.reg_adapt > 1 ||
       o.max_tile_bits - o.reg_bits > (o.math != 1 ? 9 : 8))
     return set_err(TNC_E_INVALID, "tile options out of range");
   if (o.math == 2 && o.pipeline == 1)

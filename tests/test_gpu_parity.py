@@ -169,7 +169,10 @@ def test_full_width_restriction(opts):
                                          # the full-width shape itself (2^33-entry tensor, 81 GiB
                                          # of workspace) in the benchmark's tile configuration
                                          (70, 66, 8, dict(max_tile_bits=12)),
-                                         (70, 66, 8, dict(max_tile_bits=12, math=2))])
+                                         (70, 66, 8, dict(max_tile_bits=12, math=2)),
+                                         # the paper's production width on one device: a 2^35-entry
+                                         # tensor (256 GiB) and 279 GB of workspace
+                                         (70, 70, 8, dict(max_tile_bits=12, math=2))])
 def test_full_size_clifford_matches_tableau(n, d, k, opts):
     from paper_2608_13110_amd import Plan
     c = W.brickwork_circuit(n, d, 0, W.rng_for(402, n, d))
@@ -181,8 +184,13 @@ def test_full_size_clifford_matches_tableau(n, d, k, opts):
     p = Plan.from_circuit(c, opts)
     kw = {}
     if big:  # one batch of workspace at a time (the batches run in groups)
+        torch.cuda.empty_cache()
+        print(f"  [gpu] n={n} d={d} k={k} {opts}: {p.workspace_bytes(k, 1) / 1e9:.1f} GB of workspace", flush=True)
         kw["workspace"] = torch.empty(p.workspace_bytes(k, 1), dtype=torch.uint8, device="cuda")
     got = gpu_amps(p, bits, k, **kw)
+    if big:
+        del kw
+        torch.cuda.empty_cache()
     for row, amps in zip(bits, got):
         for b in range(0, 1 << k, max(1, (1 << k) // 8)):
             x = row.copy()

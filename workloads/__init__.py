@@ -248,6 +248,9 @@ CONFIGS = {
     2: dict(name="precision", n=70, d=56, n_t=400, k=8, batches=16, restrict_n=22),
     3: dict(name="serving", requests=512),
     4: dict(name="full_width", n=70, d=66, n_t=468, k=8, batches=8, restrict_n=24),
+    # the paper's production shape on one device: n = d = 70, w = 35, the
+    # IBM instance's T density (468 T, 0.096 per qubit-layer site)
+    5: dict(name="width35", n=70, d=70, n_t=468, k=8, batches=2, restrict_n=22),
 }
 
 
