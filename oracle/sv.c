@@ -16,7 +16,9 @@
  * x_0 x_1 ... x_{n-1} read MSB-first is its index.  Complex numbers are
  * interleaved (re, im) doubles.  one_qubit[((l*n + q)*4 + 2*r + c)] is
  * entry [r][c] (row = out, column = in) of L_l on qubit q.  A dense 4x4
- * acts on basis index 2*x_q + x_{q+1}.
+ * acts on basis index 2*x_q + x_{q+1}.  A gate with q = n-1 acts on the
+ * ring's wrap pair (n-1, 0) (periodic geometry of Sec. 7), basis index
+ * 2*x_{n-1} + x_0.
  *
  * `mutation` plants a deliberate mistake; it exists so that the oracle's
  * own tests can show that their pins catch such mistakes.  0 = none.
@@ -62,9 +64,13 @@ static void apply_1q(cplx *psi, int n, int q, const cplx m_in[4], int mutation) 
     }
 }
 
+/* The pair of a gate with upper qubit q is (q, q+1); q = n-1 is the ring's
+ * wrap pair (n-1, 0). */
+static int partner(int n, int q) { return q + 1 < n ? q + 1 : 0; }
+
 static void apply_cz(cplx *psi, int n, int q, int mutation) {
-    const int64_t s1 = (int64_t)1 << bit_of(n, q, mutation);      /* qubit q   */
-    const int64_t s2 = (int64_t)1 << bit_of(n, q + 1, mutation);  /* qubit q+1 */
+    const int64_t s1 = (int64_t)1 << bit_of(n, q, mutation);               /* qubit q   */
+    const int64_t s2 = (int64_t)1 << bit_of(n, partner(n, q), mutation);   /* its partner */
     const int64_t dim = (int64_t)1 << n;
     #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < dim; ++i) {
@@ -75,7 +81,7 @@ static void apply_cz(cplx *psi, int n, int q, int mutation) {
 
 static void apply_dense4(cplx *psi, int n, int q, const cplx m[16], int mutation) {
     const int64_t s1 = (int64_t)1 << bit_of(n, q, mutation);
-    const int64_t s2 = (int64_t)1 << bit_of(n, q + 1, mutation);
+    const int64_t s2 = (int64_t)1 << bit_of(n, partner(n, q), mutation);
     const int64_t dim = (int64_t)1 << n;
     #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < dim; ++i) {
@@ -109,7 +115,8 @@ int oracle_statevector(int n, int d, const double *one_qubit, int n_g,
                        const double *g_mat, int mutation, double *psi_out) {
     if (n < 1 || n > 34 || d < 0) return -1;
     for (int g = 0; g < n_g; ++g)
-        if (g_layer[g] < 1 || g_layer[g] > d || g_q[g] < 0 || g_q[g] + 1 >= n) return -1;
+        if (g_layer[g] < 1 || g_layer[g] > d || g_q[g] < 0 || g_q[g] >= n || (g_q[g] == n - 1 && n < 3))
+            return -1;
     cplx *psi = (cplx *)psi_out;
     const cplx *L = (const cplx *)one_qubit;
     const cplx *M = (const cplx *)g_mat;

@@ -17,9 +17,24 @@ def _kron_all(mats):
 
 
 def _two_qubit_full(n, q, g4):
+    if q == n - 1:
+        return _wrap_full(n, g4)
     left = np.eye(1 << q, dtype=np.complex128)
     right = np.eye(1 << (n - q - 2), dtype=np.complex128)
     return np.kron(np.kron(left, g4), right)
+
+
+def _wrap_full(n, g4):
+    # the ring's wrap pair (n-1, 0): a permutation that brings qubit n-1 to
+    # the front, the gate on the first two qubits, and the permutation back
+    dim = 1 << n
+    perm = np.zeros((dim, dim))
+    for i in range(dim):
+        bits = [(i >> (n - 1 - j)) & 1 for j in range(n)]
+        moved = [bits[n - 1]] + bits[: n - 1]  # new order: q_{n-1}, q_0, ..., q_{n-2}
+        perm[sum(b << (n - 1 - j) for j, b in enumerate(moved)), i] = 1.0
+    inner = np.kron(g4, np.eye(dim >> 2, dtype=np.complex128))
+    return perm.T @ inner @ perm
 
 
 def unitary(circ):

@@ -46,6 +46,16 @@ def test_matches_bruteforce(n, d, seed):
     assert np.max(np.abs(got - ref)) < 1e-13
 
 
+@pytest.mark.parametrize("n,d", [(4, 4), (4, 7), (6, 5), (6, 8)])
+def test_ring_matches_bruteforce(n, d):
+    # the ring's wrap pair (n-1, 0) (Sec. 7), doped Cliffords and random
+    # one-qubit unitaries, against Kronecker products with a qubit permutation
+    c = W.ring_circuit(n, d, 3, W.rng_for(120, n, d))
+    assert sum(1 for g in c.gates if g[1] == n - 1) == d // 2 + (d % 2)
+    for cc in (c, W.with_gate_values(c, W.rng_for(121, n, d))):
+        assert np.max(np.abs(oracle.statevector(cc) - brute.all_amplitudes(cc))) < 1e-13
+
+
 @pytest.mark.parametrize("first_parity", [0, 1])
 def test_doped_clifford_bruteforce(first_parity):
     c = W.brickwork_circuit(6, 8, 5, W.rng_for(102, first_parity), first_parity=first_parity)

@@ -32,7 +32,7 @@ __all__ = [
     "GATE_CZ", "GATE_DENSE4", "Circuit", "clifford_table", "T_GATE",
     "brickwork_circuit", "restrict", "random_bitstrings", "rng_for",
     "config_circuit", "CONFIGS", "serving_requests", "random_rank2_gate",
-    "random_unitary_2x2", "with_gate_values",
+    "random_unitary_2x2", "with_gate_values", "ring_circuit",
 ]
 
 GATE_CZ = 0
@@ -112,6 +112,7 @@ class Circuit:
     gates:     list of (layer, q, kind, matrix) with layer in 1..d acting on
                (q, q+1); ``matrix`` is a 4x4 complex128 for DENSE4 (basis
                index 2*x_q + x_{q+1}, row-major [out][in]) and None for CZ.
+               On a ring, q = n-1 is the wrap pair (n-1, 0).
     cliff:     optional (d+1, n) Clifford indices used to build one_qubit.
     t_mask:    optional (d+1, n) bool, True where a T follows the Clifford.
     """
@@ -184,6 +185,21 @@ def brickwork_circuit(n: int, d: int, n_t: int, rng: np.random.Generator,
             gates.append((layer, q, GATE_CZ, None))
     return Circuit(n=n, d=d, one_qubit=one, gates=gates, cliff=cliff,
                    t_mask=t_mask, first_parity=first_parity, label=label)
+
+
+def ring_circuit(n: int, d: int, n_t: int, rng: np.random.Generator, label: str = "") -> Circuit:
+    """Doped-Clifford brickwork circuit on a ring of even n >= 4: the
+    open-chain pattern plus a CZ on the wrap pair (n-1, 0) in every layer
+    whose pairs start at qubit 1 (the layers that leave qubits 0 and n-1
+    free), d/2 of them for even d.  The wrap gate is listed with q = n-1."""
+    if n < 4 or n % 2:
+        raise ValueError("the ring needs an even n >= 4")
+    c = brickwork_circuit(n, d, n_t, rng, first_parity=1, label=label)
+    gates = list(c.gates)
+    for layer in range(1, d + 1):
+        if brickwork_pairs(n, layer, 1)[:1] == [1]:
+            gates.append((layer, n - 1, GATE_CZ, None))
+    return dataclasses.replace(c, gates=sorted(gates, key=lambda g: (g[0], g[1])))
 
 
 def restrict(c: Circuit, n2: int) -> Circuit:
