@@ -183,6 +183,32 @@ def sampling_bench(torch, W, Plan, batches=16, M=10.0):
             "porter_thomas_acceptance": round((1.0 - math.exp(-M)) / M, 4)}
 
 
+def ring_bench(torch, W, n=20, d=20, k=4):
+    """A ring of n = d = 20 (Sec. 7) by slicing its d/2 wrap-pair CZ bonds:
+    2^10 open-chain slices of width 10, summed on the device; one batch of
+    2^k amplitudes after a warmup batch."""
+    from paper_2608_13110_amd import RingPlan
+    c = W.ring_circuit(n, d, n * d // 10, W.rng_for(150, n, d))
+    bits = torch.from_numpy(W.random_bitstrings(n, 1, W.rng_for(151, n, d))).cuda()
+    t0 = time.time()
+    rp = RingPlan.from_circuit(c)
+    plan_s = time.time() - t0
+    info = rp.info(k, 1)
+    ws = torch.empty(info["workspace_bytes"], dtype=torch.uint8, device="cuda")
+    out = torch.empty((1, 1 << k), dtype=torch.complex128, device="cuda")
+    rp.amplitudes(bits, k, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    rp.amplitudes(bits, k, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    rp.close()
+    return {"workload": f"ring n={n} d={d} T={n * d // 10} k={k}, 1 batch",
+            "slices": info["slices"], "slice_width": info["width"], "plan_s": round(plan_s, 2),
+            "s_per_batch": round(wall, 4), "amplitudes_per_s": round((1 << k) / wall, 2),
+            "slices_per_s": round(info["slices"] / wall, 1)}
+
+
 # The paper's steady-state time per contraction at this shape (n = d = 70,
 # w = 35, k = 8) on one node of 8 H100s, the tensor sharded over them (Sec. 5.3)
 PAPER_W35_S_PER_CONTRACTION_8XH100 = 32.16
@@ -459,6 +485,13 @@ def main():
         except Exception as e:  # noqa: BLE001
             serving = {"error": f"{type(e).__name__}: {e}"}
         torch.cuda.empty_cache()
+    ring = None
+    if not args.no_secondary:
+        try:
+            ring = ring_bench(torch, W)
+        except Exception as e:  # noqa: BLE001
+            ring = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.empty_cache()
     width35 = None
     if not args.no_width35 and args.workload != "width35":
         try:
@@ -500,6 +533,8 @@ def main():
         line["storage_modes"] = storage
     if sampling is not None:
         line["sampling"] = sampling
+    if ring is not None:
+        line["ring"] = ring
     if width35 is not None:
         line["width35"] = width35
     if serving is not None:

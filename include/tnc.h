@@ -208,6 +208,35 @@ int tnc_frugal_accept(const tnc_c128* d_amp, int64_t count, int32_t n_qubits, do
                       uint8_t* d_accept, double* d_z, void* stream);
 
 /*
+ * Ring geometry by structure-aware slicing (Sec. 7).  Gates as in tnc_plan,
+ * plus CZ gates listed at q = n-1, which act on the wrap pair (n-1, 0); in
+ * their layers qubits n-1 and 0 must be idle in the chain pattern.  Each
+ * wrap CZ is cut as sum_a P_a (x) Z^a (P_a = |a><a| on qubit n-1, Z^a on
+ * qubit 0, both folded into the one-qubit layer that follows); each of the
+ * 2^m assignments of the m cut bonds is an open-chain plan of width
+ * ceil(d/2), and the ring's amplitudes are the sum over all slices.
+ *   m <= 12 (else TNC_E_DOMAIN); wrap gates other than CZ: TNC_E_INVALID.
+ * The ring plan owns its 2^m slice plans until tnc_ring_release.
+ */
+typedef struct tnc_ring_plan_s* tnc_ring_plan_t;
+int tnc_plan_ring(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, const tnc_gate2* gates,
+                  const tnc_options* opt, tnc_ring_plan_t* out);
+/* Slice count, width of each slice, and device workspace for n_batches
+ * batches (one slice's workspace plus a slice result buffer). */
+int tnc_ring_info(tnc_ring_plan_t ring, int32_t k, int32_t n_batches, int32_t* n_slices, int32_t* width,
+                  uint64_t* workspace_bytes);
+/* Ring amplitudes, with the arguments of tnc_amplitudes (complex64 storage):
+ * the slices run in index order on `stream`, each result added to d_out in
+ * FP64.  The workspace must hold what tnc_ring_info reports. */
+int tnc_ring_amplitudes(tnc_ring_plan_t ring, int32_t n_batches, const uint8_t* d_bits, int32_t k, tnc_c128* d_out,
+                        void* d_workspace, uint64_t workspace_bytes, void* stream);
+/* Host emulation of every slice (tnc_debug_emulate_device) summed on the
+ * host: a CPU check of the slicing. */
+int tnc_debug_ring_emulate(tnc_ring_plan_t ring, int32_t n_batches, const uint8_t* bits, int32_t k, tnc_c128* out);
+/* NULL-safe. */
+void tnc_ring_release(tnc_ring_plan_t ring);
+
+/*
  * Kernel timing with HIP events recorded on the launch stream around every
  * launch of tnc_amplitudes while profiling is on (process-wide).
  * tnc_profile_end waits for the recorded events and returns the summed

@@ -39,6 +39,7 @@ EXPORTED = [
     "tnc_debug_execute_host", "tnc_debug_emulate_device", "tnc_profile_begin", "tnc_profile_end",
     "tnc_autotune", "tnc_server_create", "tnc_server_destroy", "tnc_server_set_tuning", "tnc_server_submit",
     "tnc_server_wait", "tnc_server_summary", "tnc_debug_arena_check", "tnc_sample_batched", "tnc_frugal_accept",
+    "tnc_plan_ring", "tnc_ring_info", "tnc_ring_amplitudes", "tnc_debug_ring_emulate", "tnc_ring_release",
 ]
 
 
@@ -131,6 +132,11 @@ def lib() -> ctypes.CDLL:
     L.tnc_amplitudes_host.argtypes = [vp, i32, vp, i32, i32, vp]
     L.tnc_logxeb.argtypes = [vp, i32, i32, vp, i32, vp, vp]
     L.tnc_sample_batched.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    L.tnc_plan_ring.argtypes = [i32, i32, vp, i32, vp, vp, vp]
+    L.tnc_ring_info.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.tnc_ring_amplitudes.argtypes = [vp, i32, vp, i32, vp, vp, u64, vp]
+    L.tnc_debug_ring_emulate.argtypes = [vp, i32, vp, i32, vp]
+    L.tnc_ring_release.argtypes = [vp]
     L.tnc_frugal_accept.argtypes = [vp, ctypes.c_int64, i32, ctypes.c_double, vp, vp, vp, vp]
     L.tnc_release.argtypes = [vp]
     L.tnc_release.restype = None
@@ -152,7 +158,7 @@ def lib() -> ctypes.CDLL:
     L.tnc_server_summary.argtypes = [vp, ctypes.POINTER(ServerStats)]
     L.tnc_debug_arena_check.argtypes = [u64, i32]
     for name in EXPORTED:
-        if name not in ("tnc_release", "tnc_strerror", "tnc_last_error", "tnc_server_destroy"):
+        if name not in ("tnc_release", "tnc_strerror", "tnc_last_error", "tnc_server_destroy", "tnc_ring_release"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -281,6 +287,67 @@ class Plan:
         out = np.empty((bits.shape[0], 1 << k), dtype=np.complex128)
         _check(lib().tnc_debug_emulate_device(self._h, bits.shape[0], bits.ctypes.data, int(k), int(storage),
                                               out.ctypes.data))
+        return out
+
+
+class RingPlan:
+    """A ring circuit planned by slicing its wrap-pair CZ bonds
+    (``tnc_plan_ring``, Sec. 7): gates listed at q = n-1 act on (n-1, 0)."""
+
+    def __init__(self, n: int, d: int, one_qubit: np.ndarray, gates: Sequence, options: Optional[dict] = None):
+        L = lib()
+        self.n, self.d = int(n), int(d)
+        one = np.ascontiguousarray(np.asarray(one_qubit, dtype=np.complex128).reshape(-1))
+        if one.size != (self.d + 1) * self.n * 4:
+            raise ValueError("one_qubit must hold (d+1)*n 2x2 gates")
+        garr = _gate_array(gates)
+        opt = _options(options) if options else None
+        h = ctypes.c_void_p()
+        _check(L.tnc_plan_ring(self.n, self.d, one.ctypes.data, len(gates), ctypes.addressof(garr),
+                               ctypes.byref(opt) if opt is not None else None, ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_circuit(cls, circ, options: Optional[dict] = None) -> "RingPlan":
+        return cls(circ.n, circ.d, circ.one_qubit, circ.gates, options)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().tnc_ring_release(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self, k: int, n_batches: int = 1) -> dict:
+        ns, w, ws = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_uint64()
+        _check(lib().tnc_ring_info(self._h, int(k), int(n_batches), ctypes.byref(ns), ctypes.byref(w),
+                                   ctypes.byref(ws)))
+        return {"slices": ns.value, "width": w.value, "workspace_bytes": ws.value}
+
+    def amplitudes(self, bits, k: int, out=None, workspace=None, stream=None):
+        """Ring amplitude batches on the GPU (``tnc_ring_amplitudes``); bits
+        as for ``Plan.amplitudes``."""
+        import torch
+        if bits.device.type != "cuda" or bits.dtype != torch.uint8 or not bits.is_contiguous():
+            raise ValueError("bits must be a contiguous uint8 CUDA tensor")
+        nb = int(bits.shape[0])
+        if out is None:
+            out = torch.empty((nb, 1 << k), dtype=torch.complex128, device=bits.device)
+        if workspace is None:
+            workspace = torch.empty(self.info(k, nb)["workspace_bytes"], dtype=torch.uint8, device=bits.device)
+        s = stream if stream is not None else torch.cuda.current_stream(bits.device)
+        _check(lib().tnc_ring_amplitudes(self._h, nb, bits.data_ptr(), int(k), out.data_ptr(), workspace.data_ptr(),
+                                         workspace.numel(), ctypes.c_void_p(s.cuda_stream)))
+        return out
+
+    def debug_emulate_device(self, bits: np.ndarray, k: int) -> np.ndarray:
+        bits = np.ascontiguousarray(bits, dtype=np.uint8)
+        out = np.empty((bits.shape[0], 1 << k), dtype=np.complex128)
+        _check(lib().tnc_debug_ring_emulate(self._h, bits.shape[0], bits.ctypes.data, int(k), out.ctypes.data))
         return out
 
 

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtnc.so")
 
-HIP_SOURCES = ["kernels.hip", "tnc_api.cpp", "serve.cpp", "autotune.cpp"]
+HIP_SOURCES = ["kernels.hip", "tnc_api.cpp", "serve.cpp", "autotune.cpp", "ring.cpp"]
 CXX_SOURCES = ["plan.cpp", "late.cpp"]
 ARCH = os.environ.get("TNC_OFFLOAD_ARCH", "gfx950")
 

@@ -1139,6 +1139,33 @@ hipError_t launch_late_ops(const LateOpsArgs& a, hipStream_t s) {
 // log-XEB (Sec. 5.2): F = gamma + n ln 2 + mean_i ln p_i with p_i = |amp|^2
 // of the selected component of each batch (sel == nullptr: every component).
 // One block, FP64 throughout.  result = {F, SE, F - 1.96 SE, F + 1.96 SE, N}.
+// FP64 complex fill and sum (the ring's sum over slices).
+__global__ __launch_bounds__(kBlock) void k_fill_zero(double2* out, long long count) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = make_double2(0.0, 0.0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_accumulate(double2* out, const double2* in, long long count) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) {
+    const double2 a = out[i], b = in[i];
+    out[i] = make_double2(a.x + b.x, a.y + b.y);
+  }
+}
+
+hipError_t launch_fill_zero(double2* out, long long count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, out, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate(double2* out, const double2* in, long long count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_accumulate, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, out, in,
+                     count);
+  return hipGetLastError();
+}
+
 // Batched sampling (Sec. 4.2, steps 3-4): one block per batch.  Thread t
 // holds entries [t E, t E + E) of the batch's 2^k (E = 2^k / 256 or 1),
 // their probabilities |Z|^2 in FP64 and their sum; a block scan of those

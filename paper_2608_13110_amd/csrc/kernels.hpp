@@ -459,6 +459,8 @@ hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int R, hipStream_t s);
 hipError_t launch_late(const LateArgs& a, bool in_c64, hipStream_t s);
 hipError_t launch_late_ops(const LateOpsArgs& a, hipStream_t s);
+hipError_t launch_fill_zero(double2* out, long long count, hipStream_t s);
+hipError_t launch_accumulate(double2* out, const double2* in, long long count, hipStream_t s);
 // Batched sampling handles up to 2^10 suffixes per batch: 4 per thread.
 constexpr int kMaxSampleEntries = 4;
 hipError_t launch_sample_batched(const double2* amps, int n_batches, int k, const double* u, int32_t* b, double* q,

@@ -226,3 +226,30 @@ def test_sampler_entry_points_validate_on_the_host():
     assert L.tnc_frugal_accept(None, 8, 10, 0.0, None, None, None, None) == TNC_E_INVALID
     assert L.tnc_frugal_accept(None, 8, 10, float("inf"), None, None, None, None) == TNC_E_INVALID
     assert L.tnc_frugal_accept(None, 8, 0, 2.0, None, None, None, None) == TNC_E_INVALID
+
+
+def test_ring_slicing_matches_oracle_in_emulation():
+    # the ring (Sec. 7) as the sum of its 2^m open-chain slices, emulated on
+    # the host, against the oracle's ring state vector; and the slice count
+    import oracle as O
+    from paper_2608_13110_amd import RingPlan
+    for n, d, k in [(6, 6, 0), (8, 8, 2), (10, 9, 2)]:
+        c = W.ring_circuit(n, d, 4, W.rng_for(130, n, d))
+        for cc in (c, W.with_gate_values(c, W.rng_for(131, n, d))):
+            rp = RingPlan.from_circuit(cc, dict(max_tile_bits=6, low_bits=2, reg_bits=3))
+            assert rp.info(k)["slices"] == 1 << sum(1 for g in cc.gates if g[1] == n - 1)
+            bits = W.random_bitstrings(n, 3, W.rng_for(132, n))
+            per, l2 = H.amp_errors(rp.debug_emulate_device(bits, k), O.amplitudes(cc, bits, k), n)
+            assert per < H.TOL_C64 and l2 < H.TOL_C64, (n, d, k, per, l2)
+
+
+def test_ring_rejects_bad_wrap_gates():
+    from paper_2608_13110_amd import RingPlan
+    c = W.ring_circuit(8, 8, 0, W.rng_for(133, 1))
+    dense = [(l, q, W.GATE_DENSE4 if q == 7 else kind, np.eye(4, dtype=complex) if q == 7 else m)
+             for (l, q, kind, m) in c.gates]
+    with pytest.raises(TncError):
+        RingPlan(c.n, c.d, c.one_qubit, dense)
+    clash = list(c.gates) + [(2, 7, W.GATE_CZ, None)]  # layer 2 uses qubit 0 in the chain
+    with pytest.raises(TncError):
+        RingPlan(c.n, c.d, c.one_qubit, clash)
