@@ -102,3 +102,29 @@ def test_autotune_picks_a_candidate():
     best, times = autotune(24, 36, 4, cands, reps=2)
     assert 0 <= best < len(cands)
     assert np.all(np.isfinite(times)) and times[best] == times.min()
+
+
+def test_served_with_tuned_option_forms():
+    # the tuner's table may pick fused matrix-core phases or the prefetching
+    # blocks per width: served results still equal the same plan options run
+    # alone (bit for bit) and the oracle
+    from paper_2608_13110_amd import Plan, Server
+    reqs = W.serving_requests(count=6, seed=17, n_range=(16, 20), d_range=(24, 30), k_max=4)
+    tuning = {}
+    for r in reqs:
+        h = (r["circuit"].d + 1) // 2
+        tuning[h] = dict(math=2) if h % 2 == 0 else dict(max_tile_bits=12, reg_bits=4, math=2)
+    with Server(arena_bytes=1 << 30, n_streams=2, n_planners=2, small_bits=16) as srv:
+        for h, o in tuning.items():
+            srv.set_tuning(h, o)
+        ids = [srv.submit(r["circuit"], r["bits"], r["k"]) for r in reqs]
+        for r, rid in zip(reqs, ids):
+            got, _ = srv.wait(rid)
+            h = (r["circuit"].d + 1) // 2
+            bits = torch.from_numpy(np.ascontiguousarray(r["bits"], dtype=np.uint8)).cuda()
+            alone_z = Plan.from_circuit(r["circuit"], tuning[h]).amplitudes(bits, r["k"])
+            torch.cuda.synchronize()
+            assert np.array_equal(got, alone_z.cpu().numpy()), r["id"]
+            o = oracle.amplitudes(r["circuit"], r["bits"], r["k"])
+            per, _ = H.amp_errors(got, o, r["circuit"].n)
+            assert per < H.TOL_C64, (r["id"], per)
