@@ -88,7 +88,7 @@ typedef struct {
                             (v_mfma_f32_4x4x1_16b_f32) where a block holds one tile;
                             2: runs of three updates without output-bit variants fused into
                             one complex 8x8 per control value, on v_mfma_f32_16x16x4f32
-                            (tiles of 64 threads or more; pipeline 0 or 2; complex64 storage) */
+                            (tiles of 64 threads or more; pipeline 0 or 2) */
   int32_t pipeline;      /* 0: one tile per block (default); 1: persistent blocks that prefetch
                             the next tile into LDS while updating the current one; 2: persistent
                             blocks that prefetch the next tile into registers */

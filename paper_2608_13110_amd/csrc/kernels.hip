@@ -337,8 +337,9 @@ __global__ __launch_bounds__(kBlock) void k_pass16(PassArgs a) {
   ctx.uniform = WU;
   for (int p = 0; p < a.n_phases; ++p) {
     const DevPhase P = load_phase(a.phases, p);
-    phase_dispatch<R, false>(reinterpret_cast<char*>(lds), (uint32_t)tile_in_block << (T + 3), P,
-                             (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, tmask);
+    phase_dispatch<R, false, WU>(reinterpret_cast<char*>(lds), (uint32_t)tile_in_block << (T + 3), P,
+                                 (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, tmask,
+                                 a.fmats + (size_t)p * kFusedWords, TB);
     __syncthreads();
   }
 

@@ -390,8 +390,6 @@ BatchLayout batch_layout(const Plan& p, const HostTables& t, int storage) {
 // with a split window must keep at least 2 contiguous low slots.
 int check_storage(const HostTables& t, int storage) {
   if (storage != TNC_STORE_C64 && !is_s16(storage)) return set_err(TNC_E_INVALID, "unknown storage mode");
-  if (is_s16(storage) && !t.fmats.empty())
-    return set_err(TNC_E_INVALID, "16-bit storage runs no fused matrix-core phases (math = 2)");
   if (is_s16(storage))
     for (const PassHost& ph : t.passes) {
       if (ph.w.lo_bits == 1) return set_err(TNC_E_INVALID, "16-bit storage needs low_bits >= 2");

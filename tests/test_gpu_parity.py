@@ -259,13 +259,16 @@ STORAGE_BOUNDS = {1: (1.5e-2, 6e-3), 2: (1.2e-1, 5e-2)}
 
 
 @pytest.mark.parametrize("storage", [1, 2])
-@pytest.mark.parametrize("cid,m,k,nb", [(1, 24, 6, 16), (2, 22, 8, 2), (4, 22, 8, 1)])
-def test_block_scaled_storage_vs_oracle(storage, cid, m, k, nb):
+@pytest.mark.parametrize("cid,m,k,nb,opts", [(1, 24, 6, 16, None), (2, 22, 8, 2, None), (4, 22, 8, 1, None),
+                                             # fused matrix-core phases on the decoded tile
+                                             (2, 22, 8, 2, dict(math=2)),
+                                             (4, 22, 8, 1, dict(max_tile_bits=12, math=2))])
+def test_block_scaled_storage_vs_oracle(storage, cid, m, k, nb, opts):
     from paper_2608_13110_amd import Plan
     c = W.restrict(W.config_circuit(cid), m)
     bits = W.config_bitstrings(cid)[:nb, :m]
     ref = oracle.amplitudes(c, bits, k)
-    p = Plan.from_circuit(c)
+    p = Plan.from_circuit(c, opts)
     got = gpu_amps(p, bits, k, storage=storage)
     per, l2 = H.amp_errors(got, ref, c.n)
     print(f"  storage {storage} cid {cid}: per-amplitude {per:.2e}, l2 {l2:.2e}", flush=True)
