@@ -975,22 +975,33 @@ __global__ __launch_bounds__(kBlock) void k_late_mf(LateArgs a) {
       cr[i][j] = tnc_d4{0.0, 0.0, 0.0, 0.0};
       ci[i][j] = tnc_d4{0.0, 0.0, 0.0, 0.0};
     }
-  for (int k0 = 0; k0 < a.K; k0 += 16) {
-    for (int e = tid; e < 1024; e += kBlock) {
+  // the next k-slice of A and B is loaded into registers while the current
+  // one is multiplied from LDS (kBlock = 256 threads: 4 elements each)
+  double2 pa[4], pb[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * kBlock;
       const int r = e >> 4, kk = e & 15;
       const int row = row0 + r;
-      double2 val = make_double2(0.0, 0.0);
-      if (row < a.M && k0 + kk < a.K) val = late_in<TIn, S>(a, in, b, (uint64_t)row * a.K + k0 + kk);
-      As[kk][r] = val;
-    }
-    for (int e = tid; e < 1024; e += kBlock) {
-      const int kk = e >> 6, c = e & 63;
+      pa[q] = make_double2(0.0, 0.0);
+      if (row < a.M && k0 + kk < a.K) pa[q] = late_in<TIn, S>(a, in, b, (uint64_t)row * a.K + k0 + kk);
+      const int kb = e >> 6, c = e & 63;
       const int col = col0 + c;
-      double2 val = make_double2(0.0, 0.0);
-      if (col < a.N && k0 + kk < a.K) val = J[(size_t)(k0 + kk) * a.N + col];
-      Bs[kk][c] = val;
+      pb[q] = make_double2(0.0, 0.0);
+      if (col < a.N && k0 + kb < a.K) pb[q] = J[(size_t)(k0 + kb) * a.N + col];
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < a.K; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * kBlock;
+      As[e & 15][e >> 4] = pa[q];
+      Bs[e >> 6][e & 63] = pb[q];
     }
     __syncthreads();
+    if (k0 + 16 < a.K) fetch(k0 + 16);
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) {
       const int kk = kc * 4 + lk;
