@@ -73,7 +73,8 @@ def pct(xs, q):
 
 
 # tile candidates the autotuner times for the large workloads
-MAIN_CANDIDATES = [dict(), dict(max_tile_bits=12), dict(math=2), dict(max_tile_bits=12, math=2)]
+MAIN_CANDIDATES = [dict(), dict(max_tile_bits=12), dict(math=2), dict(max_tile_bits=12, math=2),
+                   dict(reg_bits=4, math=2)]
 
 
 def run_workload(name, steps, warmup, torch, W, Plan, profile_begin, profile_end, fixed=None):

@@ -735,11 +735,13 @@ static void emulate_tri(char* region, const DevPhase& P, const uint32_t* po, con
         v.x[i] = vx[l][i];
         v.y[i] = vy[l][i];
       }
+      if (P.n_ops >= 4) v = op_sel<R, 1>(v, rm + (size_t)(P.op_begin + 3) * 16 + 8 * ((l >> 5) & 1));
+      if (P.n_ops >= 5) v = op_reg<R, 2, 1>(v, (const TNC_TBL float*)(rm + (size_t)(P.op_begin + 4) * 16));
       if constexpr (R >= 4) {
-        if (P.n_ops >= 4) v = op_sel<R, 1>(v, rm + (size_t)(P.op_begin + 3) * 16 + 8 * ((l >> 5) & 1));
+        if (P.n_ops >= 6) v = op_reg<R, 3, 2>(v, (const TNC_TBL float*)(rm + (size_t)(P.op_begin + 5) * 16));
       }
       if constexpr (R >= 5) {
-        if (P.n_ops >= 5) v = op_reg<R, 2, 1>(v, (const TNC_TBL float*)(rm + (size_t)(P.op_begin + 4) * 16));
+        if (P.n_ops >= 7) v = op_reg<R, 4, 3>(v, (const TNC_TBL float*)(rm + (size_t)(P.op_begin + 6) * 16));
       }
       for (int i = 0; i < E; ++i) {
         vx[l][i] = v.x[i];

@@ -411,6 +411,8 @@ __device__ __attribute__((always_inline)) inline void phase_tri(char* base, uint
     v = op_sel<R, 1>(v, static_cast<const float*>(k));
   }
   if constexpr (N >= 5) v = op_reg<R, 2, 1>(v, c.rm + (size_t)(P.op_begin + 4) * 16);
+  if constexpr (N >= 6) v = op_reg<R, 3, 2>(v, c.rm + (size_t)(P.op_begin + 5) * 16);
+  if constexpr (N >= 7) v = op_reg<R, 4, 3>(v, c.rm + (size_t)(P.op_begin + 6) * 16);
 #pragma unroll
   for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(base + off[i]) = make_float2(v.x[i], v.y[i]);
 }
@@ -425,9 +427,15 @@ TNC_HD inline void phase_dispatch(char* base, uint32_t rbase, const DevPhase& P,
 #if defined(__HIP_DEVICE_COMPILE__)
   if constexpr (TRI && R >= 3) {
     if (P.pad) {
-      if (P.n_ops == 3) phase_tri<R, 3, MF>(base, rbase, P, po, fm, c, tt, TB);
-      else if (P.n_ops == 4) { if constexpr (R >= 4) phase_tri<R, 4, MF>(base, rbase, P, po, fm, c, tt, TB); }
-      else { if constexpr (R >= 5) phase_tri<R, 5, MF>(base, rbase, P, po, fm, c, tt, TB); }
+      // update b > 2 targets register bit b - 2: up to R + 2 updates
+      switch (P.n_ops) {
+        case 3: phase_tri<R, 3, MF>(base, rbase, P, po, fm, c, tt, TB); break;
+        case 4: phase_tri<R, 4, MF>(base, rbase, P, po, fm, c, tt, TB); break;
+        case 5: phase_tri<R, 5, MF>(base, rbase, P, po, fm, c, tt, TB); break;
+        case 6: if constexpr (R >= 4) phase_tri<R, 6, MF>(base, rbase, P, po, fm, c, tt, TB); break;
+        case 7: if constexpr (R >= 5) phase_tri<R, 7, MF>(base, rbase, P, po, fm, c, tt, TB); break;
+        default: break;
+      }
       return;
     }
   }

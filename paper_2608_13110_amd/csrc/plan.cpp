@@ -577,21 +577,38 @@ void pad_regs(std::vector<int>& regs, int ctl0, int T, int R) {
     if (usable(c)) regs.push_back(c);
 }
 
+// The first three updates from op i can run as one fused product: plain
+// updates with no output-bit variants.
+bool fusable_start(const std::vector<SweepOp>& ops, int i, int end) {
+  if (i + 3 > end) return false;
+  for (int b = 0; b < 3; ++b) {
+    const SweepOp& op = ops[i + b];
+    if (op.kind != OP_CU || op.xrow[0] >= 0 || op.xrow[1] >= 0) return false;
+  }
+  return true;
+}
+
 // Register phases in canonical staircase form: op b of a phase targets
 // register bit b and, for b >= 1, is controlled by register bit b-1; op 0 is
 // either a DUP or an update whose control is not a register bit (or absent).
 // Every row of the sweep is such a staircase; turns start a new phase.
-void plan_phases(Pass& ps, const std::vector<SweepOp>& ops, int R) {
+// fuse: the phases will be given to split_triples.  A phase that it will
+// fuse keeps two of its targets in lane bits, so its staircase may run two
+// updates past the register bits (one when op 0's control takes the top
+// register bit).
+void plan_phases(Pass& ps, const std::vector<SweepOp>& ops, int R, bool fuse) {
   const int T = ps.w.tile_bits();
   const int Reff = pass_reg_bits(R, T);
+  fuse = fuse && Reff >= 3 && T - Reff >= 6 && T - Reff <= kMaxThreadBits;
   int i = ps.op_begin;
   while (i < ps.op_end) {
     Phase ph;
     ph.op_begin = i;
     std::vector<int> regs = {ps.w.local(ops[i].target)};
     const int ctl0 = ops[i].kind == OP_CU && ops[i].control >= 0 ? ps.w.local(ops[i].control) : -1;
+    const int limit = fuse && fusable_start(ops, i, ps.op_end) ? Reff + 2 - (ctl0 >= 0 ? 1 : 0) : Reff;
     int j = i + 1;
-    for (; j < ps.op_end && int(regs.size()) < Reff; ++j) {
+    for (; j < ps.op_end && int(regs.size()) < limit; ++j) {
       const SweepOp& op = ops[j];
       const int t = ps.w.local(op.target);
       if (op.kind != OP_CU || op.control < 0) break;
@@ -678,7 +695,7 @@ std::vector<Pass> plan_passes(const Plan& p, const std::vector<SweepOp>& ops, in
     ps.op_end = i + best_len;
     const int T = ps.w.tile_bits();
     ps.R = pass_reg_bits(R, T);
-    plan_phases(ps, ops, ps.R);
+    plan_phases(ps, ops, ps.R, p.opt.math == 2);
     // Fewer entries per thread leave registers for more resident waves:
     // take one register bit less when the pass needs no more phases with
     // it and a tile still fits one 256-thread block.
@@ -686,7 +703,7 @@ std::vector<Pass> plan_passes(const Plan& p, const std::vector<SweepOp>& ops, in
       Pass alt = ps;
       alt.R = ps.R - 1;
       alt.phases.clear();
-      plan_phases(alt, ops, alt.R);
+      plan_phases(alt, ops, alt.R, p.opt.math == 2);
       if (alt.phases.size() == ps.phases.size()) ps = alt;
     }
     if (p.opt.math == 2) split_triples(ps, ops);

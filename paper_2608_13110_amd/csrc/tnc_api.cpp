@@ -223,7 +223,8 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
     if (!(ps.w.lo_bits >= 1 || ps.w.win_lo == 0)) return fail_t("pass tile lacks slot 0");
     for (const Phase& pp : ps.phases) {
       const int nops = pp.op_end - pp.op_begin;
-      if (nops < 1 || nops > R) return fail_t("phase size out of range");
+      // a fused phase holds two targets in lane bits: up to R + 2 updates
+      if (nops < 1 || nops > (pp.mf ? R + 2 : R)) return fail_t("phase size out of range");
       DevPhase dp;
       std::memset(&dp, 0, sizeof(dp));
       dp.op_begin = pp.op_begin;
@@ -243,7 +244,9 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
         // any) reg[R-1]; every tile bit exactly once among registers and
         // thread bits
         const int TB = T - R;
-        if (nops < 3 || nops > R || R < 3 || TB < 6 || TB > kMaxThreadBits) return fail_t("bad fused phase shape");
+        const int ctl_regs = s.ops[pp.op_begin].control >= 0 ? 1 : 0;
+        if (nops < 3 || nops - 2 + ctl_regs > R || R < 3 || TB < 6 || TB > kMaxThreadBits)
+          return fail_t("bad fused phase shape");
         uint32_t seen = 0;
         for (int b = 0; b < R; ++b) seen |= 1u << pp.reg[b];
         for (int q = 0; q < TB; ++q) {
