@@ -73,8 +73,8 @@ def pct(xs, q):
 
 
 # tile candidates the autotuner times for the large workloads
-MAIN_CANDIDATES = [dict(), dict(max_tile_bits=12), dict(math=2), dict(max_tile_bits=12, math=2),
-                   dict(reg_bits=4, math=2)]
+MAIN_CANDIDATES = [dict(), dict(max_tile_bits=12, math=2), dict(reg_bits=4, math=2),
+                   dict(max_tile_bits=13, low_bits=5, reg_bits=4, math=2)]
 
 
 def run_workload(name, steps, warmup, torch, W, Plan, profile_begin, profile_end, fixed=None):
@@ -224,7 +224,7 @@ def width35_bench(torch, W, Plan, profile_begin, profile_end):
     k = spec["k"]
     circ = W.config_circuit(spec["cid"])
     bits = torch.from_numpy(W.config_bitstrings(spec["cid"])[:1]).cuda()
-    opts = dict(max_tile_bits=12, math=2)
+    opts = dict(max_tile_bits=13, low_bits=5, reg_bits=4, math=2)
     t0 = time.time()
     plan = Plan.from_circuit(circ, opts)
     plan.prepare(k)
@@ -300,7 +300,8 @@ def storage_modes(torch, W, Plan, profile_begin, profile_end, batches=16):
 
 
 TUNE_CANDIDATES = [dict(), dict(max_tile_bits=12), dict(max_tile_bits=12, reg_adapt=1),
-                   dict(max_tile_bits=12, reg_bits=4), dict(max_tile_bits=11, reg_bits=4), dict(math=2)]
+                   dict(max_tile_bits=12, reg_bits=4), dict(max_tile_bits=11, reg_bits=4), dict(math=2),
+                   dict(reg_bits=4, math=2)]
 
 
 def serving_bench(torch, W, count=512, load=0.8):

@@ -152,7 +152,8 @@ def test_precision_config_restriction():
 
 
 @pytest.mark.parametrize("opts", [None, dict(max_tile_bits=12), dict(max_tile_bits=14, low_bits=3),
-                                  dict(max_tile_bits=12, math=2)])
+                                  dict(max_tile_bits=12, math=2), dict(reg_bits=4, math=2),
+                                  dict(max_tile_bits=13, low_bits=5, reg_bits=4, math=2)])
 def test_full_width_restriction(opts):
     # full-width shape (d = 66, w = 33: a 2^33 complex64 boundary tensor)
     # restricted to 22 qubits, k = 8, in the tile configurations the
@@ -170,9 +171,10 @@ def test_full_width_restriction(opts):
                                          # of workspace) in the benchmark's tile configuration
                                          (70, 66, 8, dict(max_tile_bits=12)),
                                          (70, 66, 8, dict(max_tile_bits=12, math=2)),
+                                         (70, 66, 8, dict(max_tile_bits=13, low_bits=5, reg_bits=4, math=2)),
                                          # the paper's production width on one device: a 2^35-entry
                                          # tensor (256 GiB) and 279 GB of workspace
-                                         (70, 70, 8, dict(max_tile_bits=12, math=2))])
+                                         (70, 70, 8, dict(max_tile_bits=13, low_bits=5, reg_bits=4, math=2))])
 def test_full_size_clifford_matches_tableau(n, d, k, opts):
     from paper_2608_13110_amd import Plan
     c = W.brickwork_circuit(n, d, 0, W.rng_for(402, n, d))
