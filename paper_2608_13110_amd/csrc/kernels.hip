@@ -201,8 +201,17 @@ hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s) {
 // WU: every wave lies inside one tile (one tile per block, or T - R >= 6),
 // so the batch and everything read through it are wave-uniform.
 // NT: threads per block (256; 512 for one 2^(R+9)-entry tile per block).
+// Resident waves per SIMD the register allocation must allow: LDS admits
+// five 2^12-entry (32 KiB) single-tile blocks per CU, so 16-entry phases in
+// 256-thread blocks ask for five.
+template <int R, bool MF, int NT>
+constexpr int pass_waves_per_eu() {
+  return MF ? 2 : (R == 4 && NT == 256 ? 5 : 1);
+}
+
 template <int R, bool MULTI, bool MF, bool WU, int NT = kBlock>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MF ? 2 : 1))) void k_pass(PassArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_per_eu<R, MF, NT>()))) void k_pass(
+    PassArgs a) {
   extern __shared__ float2 lds[];
   constexpr int E = 1 << R;
   const int T = a.T;
