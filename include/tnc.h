@@ -83,12 +83,15 @@ typedef struct {
   int32_t reg_bits;      /* entries per thread = 2^reg_bits (default 5, 1..5); at most 512
                             threads per tile: max_tile_bits - reg_bits <= 9 (<= 8 with
                             math = 1) */
-  int32_t low_bits;      /* contiguous low slots in every non-bottom tile (default 4) */
+  int32_t low_bits;      /* contiguous low slots in every non-bottom tile (default 4):
+                            HBM runs of 2^low_bits * 8 bytes */
   int32_t math;          /* 0: vector-ALU updates (default); 1: matrix-core updates
                             (v_mfma_f32_4x4x1_16b_f32) where a block holds one tile;
                             2: runs of three updates without output-bit variants fused into
                             one complex 8x8 per control value, on v_mfma_f32_16x16x4f32
-                            (tiles of 64 threads or more; pipeline 0 or 2) */
+                            (tiles of 64 threads or more; pipeline 0 or 2); two of the three
+                            targets sit in lane bits, so such a phase carries up to
+                            reg_bits + 2 updates */
   int32_t pipeline;      /* 0: one tile per block (default); 1: persistent blocks that prefetch
                             the next tile into LDS while updating the current one; 2: persistent
                             blocks that prefetch the next tile into registers */
