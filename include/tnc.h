@@ -96,9 +96,9 @@ typedef struct {
                             the next tile into LDS while updating the current one; 2: persistent
                             blocks that prefetch the next tile into registers */
   int32_t late_fold;     /* k >= 1: late removals folded on the host into the join launch
-                            (0: automatic, 7 for boundary tensors of 2^35 entries, 3 for
-                            2^26 or more, else none; -1: none; 1..8: that many; the host
-                            fold costs O(2^(3k + late_fold))) */
+                            (0: automatic, 7 for boundary tensors of 2^35 entries, 5 for
+                            2^30 or more, 3 for 2^26 or more, else none; -1: none; 1..8:
+                            that many; the host fold costs O(2^(3k + late_fold))) */
   int32_t reg_adapt;     /* 1: a pass takes reg_bits - 1 when that needs no more register
                             phases and its tile fits 256 threads (more resident waves);
                             0: every pass uses reg_bits (default) */

@@ -77,9 +77,11 @@ int build_late(const Plan& p, const Schedule& s, LatePlan* out, std::string* err
     j1 = std::min(nrem, 12);
   } else {
     // 2^35-entry tensors (256 GiB of complex64) leave room for a join output
-    // of 2^(h-j) x 16 B only with j = 7 (4 GiB; the fold takes ~10 s)
-    const int want =
-        p.opt.late_fold == 0 ? (s.m_fix >= 35 ? 7 : s.m_fix >= 26 ? 3 : 0) : std::max(0, p.opt.late_fold);
+    // of 2^(h-j) x 16 B only with j = 7 (4 GiB; the fold takes ~4 s).  From
+    // 2^30 entries on, j = 5 shrinks the late launches' input 32-fold for a
+    // host fold of about a second; the join's flops do not depend on j.
+    const int want = p.opt.late_fold == 0 ? (s.m_fix >= 35 ? 7 : s.m_fix >= 30 ? 5 : s.m_fix >= 26 ? 3 : 0)
+                                          : std::max(0, p.opt.late_fold);
     j1 = std::min(nrem, std::min(want, k <= 8 ? 8 : 1));
   }
   const bool first_final = j1 == nrem;
