@@ -48,7 +48,7 @@ def test_matches_bruteforce(n, d, seed):
 
 @pytest.mark.parametrize("n,d", [(4, 4), (4, 7), (6, 5), (6, 8)])
 def test_ring_matches_bruteforce(n, d):
-    # the ring's wrap pair (n-1, 0) (Sec. 7), doped Cliffords and random
+    # the ring's wrap pair (n-1, 0) (Sec. 6.3), doped Cliffords and random
     # one-qubit unitaries, against Kronecker products with a qubit permutation
     c = W.ring_circuit(n, d, 3, W.rng_for(120, n, d))
     assert sum(1 for g in c.gates if g[1] == n - 1) == d // 2 + (d % 2)
@@ -159,10 +159,46 @@ def test_logxeb_closed_forms():
     assert abs(f - 1.0) < 5 * se
 
 
+def test_logxeb_standard_error_worked_example():
+    # ln p = -1, -2, -3, -4: mean -5/2, sample variance (ddof = 1)
+    # (1.5^2 + 0.5^2 + 0.5^2 + 1.5^2) / 3 = 5/3, so SE = sqrt(5/3) / sqrt(4)
+    # (Sec. 5.2: the standard error of the mean of ln p over N draws)
+    n = 7
+    f, se, lo, hi = oracle.logxeb(np.exp(-np.arange(1.0, 5.0)), n)
+    assert abs(se - math.sqrt(5.0 / 3.0) / 2.0) < 1e-12
+    assert abs(f - (oracle.EULER_GAMMA + n * math.log(2.0) - 2.5)) < 1e-12
+    assert abs(lo - (f - 1.96 * se)) < 1e-12 and abs(hi - (f + 1.96 * se)) < 1e-12
+
+
+def test_logxeb_standard_error_matches_repetition_spread():
+    # Porter-Thomas draws z ~ Exp(1) (uniform bitstrings, Sec. 4.1): ln z has
+    # variance pi^2 / 6, so the estimate over N draws spreads by
+    # sqrt(pi^2 / (6 N)) across independent repetitions; the reported SE of
+    # each repetition must match that spread (an SE without its 1/sqrt(N)
+    # would be sqrt(N) = 7 times too large)
+    n, N, reps = 16, 49, 4000
+    z = W.rng_for(108, 3).exponential(size=(reps, N))
+    est = [oracle.logxeb(row * 2.0 ** -n, n) for row in z]
+    fs = np.array([e[0] for e in est])
+    ses = np.array([e[1] for e in est])
+    closed = math.sqrt(math.pi ** 2 / 6.0 / N)
+    assert abs(fs.std(ddof=1) / closed - 1.0) < 0.05
+    assert abs(ses.mean() / closed - 1.0) < 0.05
+
+
 def test_tv_conditional():
     z = np.array([[1.0, 0.0], [1.0, 1.0]], dtype=np.complex128)
     w = np.array([[0.0, 1.0], [1.0, 1.0j]], dtype=np.complex128)
     assert np.allclose(oracle.tv_conditional(z, w), [1.0, 0.0])
+
+
+def test_tv_conditional_normalises_each_row():
+    # p(b|a) divides by the row's own marginal Q_a (Sec. 5.1): rows that
+    # differ only by a scale have TV 0, and |Z| = (3, 0) against (3, 3)
+    # gives p(b|a) = (1, 0) against (1/2, 1/2), TV 1/2
+    z = np.array([[3.0, 0.0], [0.5, 0.25j], [2.0, 1.0]], dtype=np.complex128)
+    w = np.array([[3.0, 3.0], [5.0, 2.5j], [2e-6, 1e-6j]], dtype=np.complex128)
+    assert np.allclose(oracle.tv_conditional(z, w), [0.5, 0.0, 0.0], atol=1e-12)
 
 
 def _pins_pass(mutation):
