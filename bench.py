@@ -185,7 +185,7 @@ def sampling_bench(torch, W, Plan, batches=16, M=10.0):
 
 
 def ring_bench(torch, W, n=20, d=20, k=4):
-    """A ring of n = d = 20 (Sec. 7) by slicing its d/2 wrap-pair CZ bonds:
+    """A ring of n = d = 20 (Sec. 6.3) by slicing its d/2 wrap-pair CZ bonds:
     2^10 open-chain slices of width 10, summed on the device; one batch of
     2^k amplitudes after a warmup batch."""
     from paper_2608_13110_amd import RingPlan
@@ -211,7 +211,7 @@ def ring_bench(torch, W, n=20, d=20, k=4):
 
 
 # The paper's steady-state time per contraction at this shape (n = d = 70,
-# w = 35, k = 8) on one node of 8 H100s, the tensor sharded over them (Sec. 5.3)
+# w = 35, k = 8) on one node of 8 H100s, the tensor sharded over them (Sec. 5.2)
 PAPER_W35_S_PER_CONTRACTION_8XH100 = 32.16
 
 
@@ -308,11 +308,11 @@ def serving_bench(torch, W, count=512, load=0.8):
     """The serving stream: Poisson arrivals of mixed-shape requests.
 
     Autotunes the tile options per width, measures sequential plain launches
-    (one request at a time on one stream, no graphs: the capacity C), then
-    replays the same stream with arrival rate load x C into the server.
-    Planning is warmed up for both (plans cached); latency is submit -> done.
-    The sequential latency under the same arrivals is FIFO queueing over the
-    measured per-request service times.
+    back to back (one request at a time on one stream, no graphs, no groups:
+    the capacity C), then runs the same stream at arrival rate load x C twice:
+    through the sequential path (a request starts when it has arrived and the
+    previous one is done) and through the server.  Plans are prepared before
+    either run (the server's by a warm-up pass); latency is arrival -> done.
     """
     import threading
     import numpy as np
@@ -328,12 +328,16 @@ def serving_bench(torch, W, count=512, load=0.8):
     for p_, r in zip(plans, reqs):
         p_.prepare(r["k"])
     stream = torch.cuda.current_stream()
+
+    def run_one(p_, r):
+        bits = torch.from_numpy(np.ascontiguousarray(r["bits"], dtype=np.uint8)).cuda()
+        out = p_.amplitudes(bits, r["k"], stream=stream)
+        return out.cpu()
+
     service = []
     for p_, r in zip(plans, reqs):
         t0 = time.perf_counter()
-        bits = torch.from_numpy(np.ascontiguousarray(r["bits"], dtype=np.uint8)).cuda()
-        out = p_.amplitudes(bits, r["k"], stream=stream)
-        z = out.cpu()
+        run_one(p_, r)
         service.append(time.perf_counter() - t0)
     seq_total = sum(service)
     amps = sum(1 << r["k"] for r in reqs)
@@ -341,10 +345,16 @@ def serving_bench(torch, W, count=512, load=0.8):
     rate = load * capacity
     gaps = np.array([r["arrival"] for r in reqs])
     arrivals = gaps / gaps[-1] * (count / rate)
-    done, seq_lat = 0.0, []
-    for a, sv in zip(arrivals, service):
-        done = max(done, a) + sv
-        seq_lat.append(1e3 * (done - a))
+    # the sequential path under the same arrivals, measured
+    seq_lat = []
+    t0 = time.perf_counter()
+    for p_, r, a in zip(plans, reqs, arrivals):
+        dt = a - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        run_one(p_, r)
+        seq_lat.append(1e3 * (time.perf_counter() - t0 - a))
+    seq_arr_s = time.perf_counter() - t0
     del plans
     torch.cuda.empty_cache()
     with Server(arena_bytes=16 << 30, n_streams=8, n_planners=8, small_bits=20) as srv:
@@ -355,24 +365,26 @@ def serving_bench(torch, W, count=512, load=0.8):
             srv.wait(i)
         warm = srv.summary()
         res = [None] * count
+        submit_t = [0.0] * count
 
-        def producer():
-            t0 = time.perf_counter()
+        def producer(t0):
             for i, (r, a) in enumerate(zip(reqs, arrivals)):
                 dt = a - (time.perf_counter() - t0)
                 if dt > 0:
                     time.sleep(dt)
+                submit_t[i] = time.perf_counter() - t0 - a
                 res[i] = srv.submit(r["circuit"], r["bits"], r["k"])
 
         t0 = time.perf_counter()
-        th = threading.Thread(target=producer)
+        th = threading.Thread(target=producer, args=(t0,))
         th.start()
         lat = []
         for i in range(count):
             while res[i] is None:
                 time.sleep(1e-4)
             _, st = srv.wait(res[i])
-            lat.append(st["total_ms"])
+            # arrival -> done: the producer's own lateness plus submit -> done
+            lat.append(1e3 * submit_t[i] + st["total_ms"])
         th.join()
         served_s = time.perf_counter() - t0
         summ = srv.summary()
@@ -382,19 +394,29 @@ def serving_bench(torch, W, count=512, load=0.8):
         for i in ids:
             srv.wait(i)
         sat_s = time.perf_counter() - t1
+        sat = srv.summary()
+
+    def delta(a, b, key):
+        return b[key] - a[key]
+
     return {
         "workload": f"{count} Poisson requests, n in 24..56, even d in 20..48 (w 10..24), k in 0..8, "
                     f"1 bitstring each; arrival rate {load} x sequential capacity",
         "amplitudes": amps,
-        "sequential": {"amplitudes_per_s": round(amps / seq_total, 1), "requests_per_s": round(capacity, 1),
+        "sequential": {"amplitudes_per_s": round(amps / seq_arr_s, 1), "requests_per_s": round(count / seq_arr_s, 1),
+                       "capacity_requests_per_s": round(capacity, 1),
                        "latency_ms_p50": round(pct(seq_lat, 50), 3), "latency_ms_p99": round(pct(seq_lat, 99), 3)},
         "served": {"amplitudes_per_s": round(amps / served_s, 1), "requests_per_s": round(count / served_s, 1),
                    "latency_ms_p50": round(pct(lat, 50), 3), "latency_ms_p99": round(pct(lat, 99), 3),
-                   "max_inflight": summ["max_inflight"], "capture_failures": summ["capture_failures"],
-                   "graph_launches": summ["graph_launches"] - warm["graph_launches"],
-                   "plain_launches": summ["plain_launches"] - warm["plain_launches"]},
+                   "max_inflight": summ["max_inflight"], "graph_failures": summ["graph_failures"],
+                   "graph_launches": delta(warm, summ, "graph_launches"),
+                   "plain_launches": delta(warm, summ, "plain_launches"),
+                   "groups": delta(warm, summ, "groups"), "grouped_requests": delta(warm, summ, "grouped_requests")},
         "saturated": {"amplitudes_per_s": round(amps / sat_s, 1), "requests_per_s": round(count / sat_s, 1),
-                      "vs_sequential": round(seq_total / sat_s, 3)},
+                      "vs_sequential": round(seq_total / sat_s, 3),
+                      "groups": delta(summ, sat, "groups"), "grouped_requests": delta(summ, sat, "grouped_requests"),
+                      "grouped_launches": delta(summ, sat, "grouped_launches"),
+                      "graph_launches": delta(summ, sat, "graph_launches")},
         "tuning": {str(h): o for h, o in tuning.items()},
     }
 

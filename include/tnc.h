@@ -81,20 +81,14 @@ typedef struct {
 typedef struct {
   int32_t max_tile_bits; /* entries per pass tile = 2^max_tile_bits (default 13, 6..14) */
   int32_t reg_bits;      /* entries per thread = 2^reg_bits (default 5, 1..5); at most 512
-                            threads per tile: max_tile_bits - reg_bits <= 9 (<= 8 with
-                            math = 1) */
+                            threads per tile: max_tile_bits - reg_bits <= 9 */
   int32_t low_bits;      /* contiguous low slots in every non-bottom tile (default 4):
                             HBM runs of 2^low_bits * 8 bytes */
-  int32_t math;          /* 0: vector-ALU updates (default); 1: matrix-core updates
-                            (v_mfma_f32_4x4x1_16b_f32) where a block holds one tile;
-                            2: runs of three updates without output-bit variants fused into
-                            one complex 8x8 per control value, on v_mfma_f32_16x16x4f32
-                            (tiles of 64 threads or more; pipeline 0 or 2); two of the three
-                            targets sit in lane bits, so such a phase carries up to
-                            reg_bits + 2 updates */
-  int32_t pipeline;      /* 0: one tile per block (default); 1: persistent blocks that prefetch
-                            the next tile into LDS while updating the current one; 2: persistent
-                            blocks that prefetch the next tile into registers */
+  int32_t math;          /* 0: vector-ALU updates (default); 2: runs of three updates without
+                            output-bit variants fused into one complex 8x8 per control value,
+                            on v_mfma_f32_16x16x4f32 (tiles of 64 threads or more); two of the
+                            three targets sit in lane bits, so such a phase carries up to
+                            reg_bits + 2 updates.  Other values: TNC_E_INVALID */
   int32_t late_fold;     /* k >= 1: late removals folded on the host into the join launch
                             (0: automatic, 7 for boundary tensors of 2^35 entries, 5 for
                             2^30 or more, 3 for 2^26 or more, else none; -1: none; 1..8:
@@ -102,7 +96,7 @@ typedef struct {
   int32_t reg_adapt;     /* 1: a pass takes reg_bits - 1 when that needs no more register
                             phases and its tile fits 256 threads (more resident waves);
                             0: every pass uses reg_bits (default) */
-  int32_t reserved[1];
+  int32_t reserved[2];
 } tnc_options;
 
 typedef struct {
@@ -211,7 +205,7 @@ int tnc_frugal_accept(const tnc_c128* d_amp, int64_t count, int32_t n_qubits, do
                       uint8_t* d_accept, double* d_z, void* stream);
 
 /*
- * Ring geometry by structure-aware slicing (Sec. 7).  Gates as in tnc_plan,
+ * Ring geometry by structure-aware slicing (Sec. 6.3).  Gates as in tnc_plan,
  * plus CZ gates listed at q = n-1, which act on the wrap pair (n-1, 0); in
  * their layers qubits n-1 and 0 must be idle in the chain pattern.  Each
  * wrap CZ is cut as sum_a P_a (x) Z^a (P_a = |a><a| on qubit n-1, Z^a on
@@ -262,7 +256,7 @@ int tnc_profile_end(tnc_profile* out);
  * Tile autotuner.  Times each candidate tile option set on the current
  * device for an n-qubit, d-layer brickwork CZ circuit with seeded random
  * one-qubit unitaries (width and pass structure depend only on n, d and k,
- * never on the gate values: Sec. 6, the invariance of width and cost) and
+ * never on the gate values: the invariance of width and cost stated in Sec. 1 and Sec. 7) and
  * reports the fastest.
  *   candidates: n_candidates option sets (NULL entries not allowed);
  *   reps:       timed batches per candidate (after one untimed warm-up);
@@ -276,28 +270,36 @@ int tnc_autotune(int32_t n, int32_t d, int32_t k, int32_t storage, const tnc_opt
 
 /*
  * Serving: a continuous-batching request loop on the current device
- * (batches of one circuit share its plan: Sec. 5.3).  Requests of any shape
+ * (batches of one circuit share its plan: Sec. 5.2).  Requests of any shape
  * are submitted at any time from any thread; planner threads build (or find
  * in the plan cache, keyed by the circuit's contents) the plan and upload
  * its tables; the dispatcher admits a prepared request as soon as one of
  * n_streams HIP streams is free and the device arena has room for its
  * footprint (workspace + bits + output), oldest first, letting younger
  * requests that fit pass an older one that does not at most 16 times.
- * Requests whose boundary tensor has <= small_bits bits run as HIP graphs
- * captured on first use; each cached graph owns its device region (within a
- * quarter of the arena) and is replayed, from any stream, when the same
- * (plan, k, batches, storage) returns while it is idle.
+ * Small requests (boundary tensor of <= small_bits bits) run together: the
+ * ready complex64 requests of the admitted one's width (up to max_group)
+ * form a group whose launches are merged, launch by launch, into grouped
+ * launches of one kernel each (one segment per member).  A small request
+ * whose (plan, k, batches, storage) has been served before runs as a cached
+ * HIP graph, built node by node from its launches (never by stream capture),
+ * which owns its device region (within a quarter of the arena) and is
+ * replayed, from any stream, while idle.  No stream is ever put in capture
+ * mode, so other threads may use the device freely meanwhile.
  * Results are bit-identical to tnc_amplitudes with the same plan options.
  */
 typedef struct tnc_server_s* tnc_server_t;
 
 typedef struct {
   uint64_t arena_bytes;  /* device memory reserved at creation for all requests (> 0) */
-  int32_t n_streams;     /* concurrent requests on the device (default 4, at most 16) */
+  int32_t n_streams;     /* concurrent requests or groups on the device (default 4, at most 16) */
   int32_t n_planners;    /* planner threads (default 4, at most 16) */
-  int32_t small_bits;    /* graph-replayed requests: boundary bits <= small_bits (0: none, at most 24) */
+  int32_t small_bits;    /* grouped / graph-replayed requests: boundary bits <= small_bits (0: none, at most 24) */
   int32_t max_graphs;    /* cached graph executables (default 256) */
-  int32_t reserved[4];
+  int32_t max_group;     /* requests per group (default 16, at most 256; 1: never group) */
+  int32_t group_window_us; /* a ready small complex64 request waits up to this long for max_group
+                            requests of its width to be ready (default 0: no wait) */
+  int32_t reserved[2];
 } tnc_server_options;
 
 typedef struct {
@@ -306,12 +308,13 @@ typedef struct {
   double run_ms;         /* admitted -> results copied back */
   double total_ms;       /* submit -> done */
   int32_t boundary_bits;
-  int32_t graph;         /* 1: ran as a captured graph */
+  int32_t mode;          /* 0: its own launches; 1: a cached graph; 2: in a group */
 } tnc_request_stats;
 
 typedef struct {
   int64_t completed;
-  int64_t graph_launches, graph_captures, capture_failures, plain_launches;
+  int64_t graph_launches, graph_builds, graph_failures, plain_launches;
+  int64_t groups, grouped_requests, grouped_launches;  /* groups of >= 2 requests; their merged launches */
   int64_t plan_cache_hits, plan_cache_misses;
   int32_t max_inflight;  /* most requests seen running at once */
   int32_t reserved;
@@ -361,6 +364,21 @@ const char* tnc_last_error(void);
 int tnc_debug_execute_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, tnc_c128* out);
 int tnc_debug_emulate_device(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, int32_t storage,
                              tnc_c128* out);
+
+/*
+ * Complex128 reference path (tests and the accuracy report; not tuned): the
+ * same plan, with the boundary tensor in complex128 and every update of the
+ * sweep applied in FP64 by its own launch (no fusion, no tiles), then the
+ * same FP64 join and late phase.  The paper measures its complex64 runs
+ * against complex128 ones by the TV of the conditional distributions
+ * (Sec. 5.1).  Arguments as for tnc_amplitudes (complex64 storage modes do
+ * not apply); the workspace holds the complex128 tensor and the late
+ * buffers per batch (tnc_debug_workspace_c128), and the update tables are
+ * uploaded on first use (synchronous).
+ */
+int tnc_debug_workspace_c128(tnc_plan_t plan, int32_t k, int32_t n_batches, uint64_t* bytes);
+int tnc_debug_amplitudes_c128(tnc_plan_t plan, int32_t n_batches, const uint8_t* d_bits, int32_t k, tnc_c128* d_out,
+                              void* d_workspace, uint64_t workspace_bytes, void* stream);
 
 /* Host self-check of the serving loop's device-arena allocator: n_ops
  * seeded random allocations and releases, checked for overlap, bounds and

@@ -11,7 +11,7 @@ Contents
 ``statevector``  full 2^n FP64 state of U|0^n> (C, ``sv.c``), following the
                  amplitude definition psi(x) = <x|U|0^n> of Sec. 2.2 with
                  U = L_d E_d ... E_1 L_0 (Sec. 2.1); a gate listed at
-                 q = n-1 acts on the ring's wrap pair (n-1, 0) (Sec. 7).
+                 q = n-1 acts on the ring's wrap pair (n-1, 0) (Sec. 6.3).
 ``amplitudes``   the batch tensor Z[b] = <a, b|U|0^n> of the batched
                  contraction (Sec. 4.3, its Require/Ensure lines): b are the
                  last k qubits, index b read MSB-first over qubits n-k..n-1.

@@ -17,7 +17,7 @@
  * interleaved (re, im) doubles.  one_qubit[((l*n + q)*4 + 2*r + c)] is
  * entry [r][c] (row = out, column = in) of L_l on qubit q.  A dense 4x4
  * acts on basis index 2*x_q + x_{q+1}.  A gate with q = n-1 acts on the
- * ring's wrap pair (n-1, 0) (periodic geometry of Sec. 7), basis index
+ * ring's wrap pair (n-1, 0) (periodic geometry of Sec. 6.3), basis index
  * 2*x_{n-1} + x_0.
  *
  * `mutation` plants a deliberate mistake; it exists so that the oracle's

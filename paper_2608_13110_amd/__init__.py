@@ -40,6 +40,7 @@ EXPORTED = [
     "tnc_autotune", "tnc_server_create", "tnc_server_destroy", "tnc_server_set_tuning", "tnc_server_submit",
     "tnc_server_wait", "tnc_server_summary", "tnc_debug_arena_check", "tnc_sample_batched", "tnc_frugal_accept",
     "tnc_plan_ring", "tnc_ring_info", "tnc_ring_amplitudes", "tnc_debug_ring_emulate", "tnc_ring_release",
+    "tnc_debug_workspace_c128", "tnc_debug_amplitudes_c128",
 ]
 
 
@@ -61,8 +62,8 @@ class Gate2(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("max_tile_bits", ctypes.c_int32), ("reg_bits", ctypes.c_int32),
                 ("low_bits", ctypes.c_int32), ("math", ctypes.c_int32),
-                ("pipeline", ctypes.c_int32), ("late_fold", ctypes.c_int32), ("reg_adapt", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("late_fold", ctypes.c_int32), ("reg_adapt", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Info(ctypes.Structure):
@@ -88,12 +89,13 @@ class Profile(ctypes.Structure):
 
 class ServerOptions(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_uint64), ("n_streams", ctypes.c_int32), ("n_planners", ctypes.c_int32),
-                ("small_bits", ctypes.c_int32), ("max_graphs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("small_bits", ctypes.c_int32), ("max_graphs", ctypes.c_int32), ("max_group", ctypes.c_int32),
+                ("group_window_us", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class RequestStats(ctypes.Structure):
     _fields_ = [("plan_ms", ctypes.c_double), ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double), ("boundary_bits", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("total_ms", ctypes.c_double), ("boundary_bits", ctypes.c_int32), ("mode", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -101,8 +103,9 @@ class RequestStats(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("graph_launches", ctypes.c_int64),
-                ("graph_captures", ctypes.c_int64), ("capture_failures", ctypes.c_int64),
-                ("plain_launches", ctypes.c_int64),
+                ("graph_builds", ctypes.c_int64), ("graph_failures", ctypes.c_int64),
+                ("plain_launches", ctypes.c_int64), ("groups", ctypes.c_int64),
+                ("grouped_requests", ctypes.c_int64), ("grouped_launches", ctypes.c_int64),
                 ("plan_cache_hits", ctypes.c_int64), ("plan_cache_misses", ctypes.c_int64),
                 ("max_inflight", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("latency_ms_p50", ctypes.c_double), ("latency_ms_p99", ctypes.c_double),
@@ -130,6 +133,8 @@ def lib() -> ctypes.CDLL:
     L.tnc_workspace_bytes.argtypes = [vp, i32, i32, i32, ctypes.POINTER(u64)]
     L.tnc_amplitudes.argtypes = [vp, i32, vp, i32, i32, vp, vp, u64, vp]
     L.tnc_amplitudes_host.argtypes = [vp, i32, vp, i32, i32, vp]
+    L.tnc_debug_workspace_c128.argtypes = [vp, i32, i32, ctypes.POINTER(u64)]
+    L.tnc_debug_amplitudes_c128.argtypes = [vp, i32, vp, i32, vp, vp, u64, vp]
     L.tnc_logxeb.argtypes = [vp, i32, i32, vp, i32, vp, vp]
     L.tnc_sample_batched.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     L.tnc_plan_ring.argtypes = [i32, i32, vp, i32, vp, vp, vp]
@@ -188,10 +193,14 @@ def _gate_array(gates: Sequence):
     return garr
 
 
+_OPTION_KEYS = ("max_tile_bits", "reg_bits", "low_bits", "math", "late_fold", "reg_adapt")
+
+
 def _options(options: dict) -> Options:
-    return Options(int(options.get("max_tile_bits", 0)), int(options.get("reg_bits", 0)),
-                   int(options.get("low_bits", 0)), int(options.get("math", 0)), int(options.get("pipeline", 0)),
-                   int(options.get("late_fold", 0)), int(options.get("reg_adapt", 0)))
+    unknown = set(options) - set(_OPTION_KEYS)
+    if unknown:
+        raise ValueError(f"unknown tile options: {sorted(unknown)}")
+    return Options(*[int(options.get(k, 0)) for k in _OPTION_KEYS])
 
 
 class Plan:
@@ -275,6 +284,23 @@ class Plan:
                                          out.ctypes.data))
         return out
 
+    def debug_amplitudes_c128(self, bits, k: int, out=None, workspace=None, stream=None):
+        """The complex128 reference path (``tnc_debug_amplitudes_c128``):
+        unfused FP64 updates on a complex128 tensor, same join and late phase.
+        bits: torch uint8 (batches, n) on the device."""
+        import torch
+        nb = int(bits.shape[0])
+        if out is None:
+            out = torch.empty((nb, 1 << k), dtype=torch.complex128, device=bits.device)
+        if workspace is None:
+            ws = ctypes.c_uint64()
+            _check(lib().tnc_debug_workspace_c128(self._h, int(k), nb, ctypes.byref(ws)))
+            workspace = torch.empty(int(ws.value), dtype=torch.uint8, device=bits.device)
+        s = stream if stream is not None else torch.cuda.current_stream(bits.device)
+        _check(lib().tnc_debug_amplitudes_c128(self._h, nb, bits.data_ptr(), int(k), out.data_ptr(),
+                                               workspace.data_ptr(), workspace.numel(), ctypes.c_void_p(s.cuda_stream)))
+        return out
+
     # ------------------------------------------------------- host self-checks
     def debug_execute_host(self, bits: np.ndarray, k: int) -> np.ndarray:
         bits = np.ascontiguousarray(bits, dtype=np.uint8)
@@ -292,7 +318,7 @@ class Plan:
 
 class RingPlan:
     """A ring circuit planned by slicing its wrap-pair CZ bonds
-    (``tnc_plan_ring``, Sec. 7): gates listed at q = n-1 act on (n-1, 0)."""
+    (``tnc_plan_ring``, Sec. 6.3): gates listed at q = n-1 act on (n-1, 0)."""
 
     def __init__(self, n: int, d: int, one_qubit: np.ndarray, gates: Sequence, options: Optional[dict] = None):
         L = lib()
@@ -436,8 +462,9 @@ class Server:
     """
 
     def __init__(self, arena_bytes: int, n_streams: int = 4, n_planners: int = 4, small_bits: int = 20,
-                 max_graphs: int = 256):
-        o = ServerOptions(int(arena_bytes), int(n_streams), int(n_planners), int(small_bits), int(max_graphs))
+                 max_graphs: int = 256, max_group: int = 16, group_window_us: int = 0):
+        o = ServerOptions(int(arena_bytes), int(n_streams), int(n_planners), int(small_bits), int(max_graphs),
+                          int(max_group), int(group_window_us))
         h = ctypes.c_void_p()
         _check(lib().tnc_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h

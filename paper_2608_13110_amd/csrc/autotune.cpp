@@ -1,7 +1,7 @@
 // Tile autotuner: times candidate pass tilings on the device.
 //
 // The width, the op sequence and hence the pass partition depend only on the
-// circuit's shape (n, d) and k, not on its gate values (Sec. 6: width and
+// circuit's shape (n, d) and k, not on its gate values (Sec. 1 and Sec. 7: width and
 // scheduled cost are independent of the one-qubit gates and of the T
 // placement), so one synthetic circuit of the right shape stands for every
 // circuit of that shape: brickwork CZ layers with seeded random one-qubit

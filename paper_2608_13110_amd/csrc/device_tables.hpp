@@ -61,9 +61,6 @@ static_assert(sizeof(DevPhase) == 16, "DevPhase layout");
 
 // Launch parameters of one pass (a kernel argument).
 //   mats:  per op [var 4][ctl 2][k00 k01 k10 k11 as (re, im)]  (16 floats / var)
-//   mrows: per op [var 4][ctl 2][row 4][4]: the real 4x4 form of the same
-//          2x2, acting on (re b0, im b0, re b1, im b1); row r feeds the
-//          matrix-core update's A operand of lane r (mod 4)
 // A phase's LDS offset table: one word per register entry (up to 2^5), then
 // (fused phases) one per thread bit: the offset of that tile bit alone.
 constexpr int kPhaseEntries = 32;
@@ -80,16 +77,10 @@ struct PassArgs {
   // per phase of the pass: kFusedWords float4, the fused phases' matrix-core
   // operands (null when the pass tables have no fused phase)
   const float4* fmats;
-  const DevOp* ops;
-  const float* mats;
-  const float4* mrows;
   // the batch's own matrices: rmats[b][op][ctl][k00 k01 k10 k11 as (re, im)]
   // (the variant of every op already picked from batch b's output bits)
   const float* rmats;
   long long rstride;     // floats per batch in rmats
-  // the same for the matrix-core form: rmrows[b][op][ctl][row] (8 float4)
-  const float4* rmrows;
-  long long rmstride;    // float4 per batch in rmrows
   float2* B;             // boundary tensors, batch stride 2^h entries
   const uint8_t* bits;   // output bits, batch stride n
   int n_phases;
@@ -98,8 +89,6 @@ struct PassArgs {
   int T;                 // tile bits
   int lo_bits, win_lo, win_len;
   int n_tiles;           // batches << (h - T)
-  int mfma;              // register-controlled updates on the matrix cores
-  int pipeline;          // persistent blocks prefetching the next tile
   int store;             // StoreMode of B
   // 16-bit storage only: scales read (written by the previous writer, laid
   // out by in_map) and written (laid out by this pass's own tiles); batch
@@ -165,13 +154,31 @@ struct LateOpsArgs {
 struct ResolveArgs {
   const DevOp* ops;
   const float* mats;
-  const float4* mrows;
   const uint8_t* bits;
   float* rmats;
   long long rstride;
-  float4* rmrows;        // null: no matrix-core form
-  long long rmstride;
   int n_ops;
+  int n;
+  int n_batches;
+};
+
+// One boundary update of the unfused complex128 reference sweep (a test
+// path, not the hot loop): the pair along `target` of every index becomes
+// m[var][c] * pair (c = the control bit, var = 2 x[xrow0] + x[xrow1]), or
+// (kind 1) the half with target bit 1 becomes a copy of the half with 0.
+struct Op64 {
+  int32_t kind;
+  int32_t target, control;
+  int32_t xrow0, xrow1;
+  int32_t pad[3];
+  double2 m[4][2][4];  // [var][ctl][k00 k01 k10 k11]
+};
+
+struct Op64Args {
+  double2* B;            // complex128 boundary tensors, batch stride 2^h entries
+  const uint8_t* bits;
+  const Op64* op;
+  int h;
   int n;
   int n_batches;
 };

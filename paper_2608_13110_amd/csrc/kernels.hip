@@ -1,20 +1,39 @@
 // HIP kernels for gfx950 (CDNA4) of the temporal-boundary contraction.
 //
-//  k_init   row-0 build-up of the boundary tensor (one write pass)
-//  k_pass   one fused window of staircase updates over every tile of the
-//           boundary tensor (the hot loop); in place, HBM-streaming
-//  k_late   the folded late-phase contraction: the Alg. 2 join and the late
-//           layers, FP64 accumulation
-//  k_logxeb FP64 log-XEB reduction
+//  k_init     row-0 build-up of the boundary tensor (one write pass)
+//  k_resolve  per-batch choice of every update's matrix variant
+//  k_pass     one fused window of staircase updates over every tile of the
+//             boundary tensor (the hot loop); in place, HBM-streaming
+//  k_late     the folded late-phase contraction: the Alg. 2 join and the late
+//             layers, FP64 accumulation (k_late_mf: the same on FP64 matrix
+//             cores), and k_late_ops, the rest of the late program
+//  k_logxeb   FP64 log-XEB reduction; samplers
+//
+// The kernels of the amplitude path are recorded as launches (Launch, see
+// kernels.hpp) before they run.  Each such kernel has a body taking its block
+// index explicitly, a plain entry point, and (complex64 path) a grouped entry
+// point that runs segment blockIdx.z of a table of (argument, grid) segments:
+// launches of one kernel for different requests merged into one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
+#include <cstring>
 #include <vector>
 
 #include "kernels.hpp"
 
 namespace tnc {
+
+// The segment of a grouped launch that this block belongs to, or null when
+// the block lies outside its segment's own grid.
+template <class A>
+__device__ __attribute__((always_inline)) inline const Seg<A>* group_seg(const Seg<A>* segs) {
+  const Seg<A>* s = segs + blockIdx.z;
+  if (blockIdx.x >= s->gx || blockIdx.y >= s->gy) return nullptr;
+  return s;
+}
 
 // ---------------------------------------------------------------------------
 // Row-0 build-up.  The first row only creates slots: its boundary tensor is
@@ -29,13 +48,13 @@ __device__ inline double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-__global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
+__device__ __attribute__((always_inline)) inline void init_body(const InitArgs& a, uint32_t bx) {
   __shared__ double2 seg[4 * 64];
   const int nseg = a.m0 - 1;
   for (int i = threadIdx.x; i < 4 * nseg; i += blockDim.x) seg[i] = a.seg[i];
   __syncthreads();
   const int m = a.m0;
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gid = (long long)bx * blockDim.x + threadIdx.x;
   auto sg = [&](int j, unsigned long long i) {
     return seg[4 * (j - 1) + 2 * (int)((i >> j) & 1ull) + (int)((i >> (j - 1)) & 1ull)];
   };
@@ -84,13 +103,13 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
   }
 }
 
-hipError_t launch_init(const InitArgs& a, hipStream_t s) {
-  if (a.m0 - 1 > 64) return hipErrorInvalidValue;
-  const long long threads = a.h < 11 ? ((long long)a.n_batches << a.h) : (((long long)a.n_batches << a.h) >> 5);
-  const long long blocks = (threads + kBlock - 1) / kBlock;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
+__global__ __launch_bounds__(kBlock) void k_init(InitArgs a) { init_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(kBlock) void k_init_g(const Seg<InitArgs>* __restrict__ segs) {
+  const Seg<InitArgs>* s = group_seg(segs);
+  if (!s) return;
+  const InitArgs a = s->a;
+  init_body(a, blockIdx.x);
 }
 
 // Row-0 build-up into 16-bit block-scaled storage: one workgroup per block
@@ -145,22 +164,12 @@ __global__ __launch_bounds__(kBlock) void k_init16(InitArgs a) {
   if (threadIdx.x == 0) a.scale_out[batch * a.scale_stride + (long long)sblk] = ldexpf(1.f, e);
 }
 
-hipError_t launch_init16(const InitArgs& a, hipStream_t s) {
-  if (a.m0 - 1 > 64 || a.blk_bits > 12 || a.blk_bits < 0 || a.blk_bits > a.h) return hipErrorInvalidValue;
-  const long long blocks = (long long)a.n_batches << (a.h - a.blk_bits);
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (a.store == STORE_F16) hipLaunchKernelGGL(k_init16<STORE_F16>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
-  else if (a.store == STORE_BF16) hipLaunchKernelGGL(k_init16<STORE_BF16>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // Variant resolution: every op's matrix pair for each batch of the group,
 // picked once from the batch's output bits, so the pass kernels read their
 // matrices at addresses that depend on the op only.
-__global__ __launch_bounds__(kBlock) void k_resolve(ResolveArgs a) {
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __attribute__((always_inline)) inline void resolve_body(const ResolveArgs& a, uint32_t bx) {
+  const long long gid = (long long)bx * blockDim.x + threadIdx.x;
   const long long total = (long long)a.n_batches * a.n_ops;
   if (gid >= total) return;
   const int b = (int)(gid / a.n_ops);
@@ -172,47 +181,50 @@ __global__ __launch_bounds__(kBlock) void k_resolve(ResolveArgs a) {
   float4* dst = reinterpret_cast<float4*>(a.rmats + (size_t)b * a.rstride + (size_t)o * 16);
 #pragma unroll
   for (int q = 0; q < 4; ++q) dst[q] = src[q];
-  if (a.rmrows) {
-    const float4* rs = a.mrows + ((size_t)op.mat * 4 + var) * 8;
-    float4* rd = a.rmrows + (size_t)b * a.rmstride + (size_t)o * 8;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) rd[q] = rs[q];
-  }
 }
 
-hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s) {
-  const long long total = (long long)a.n_batches * a.n_ops;
-  if (total <= 0) return hipSuccess;
-  const long long blocks = (total + kBlock - 1) / kBlock;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_resolve, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
+__global__ __launch_bounds__(kBlock) void k_resolve(ResolveArgs a) { resolve_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(kBlock) void k_resolve_g(const Seg<ResolveArgs>* __restrict__ segs) {
+  const Seg<ResolveArgs>* s = group_seg(segs);
+  if (!s) return;
+  const ResolveArgs a = s->a;
+  resolve_body(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // The pass kernel.  A tile is 2^T entries of one batch's boundary tensor: the
 // global slots [0, lo_bits) and [win_lo, win_lo + win_len).  A block holds
-// one tile (T - R >= 8 thread bits) or several small ones.  Data path:
+// one tile (T - R = 8 thread bits with 256 threads, 9 with 512) or several
+// small ones.  Data path:
 //   HBM -> LDS with 16-byte accesses along the contiguous low slots,
 //   per phase: LDS -> registers (2^R entries per thread, the phase's target
 //   slots as register bits), the phase's updates in registers, registers ->
 //   LDS,
 //   LDS -> HBM, in place.
 // WU: every wave lies inside one tile (one tile per block, or T - R >= 6),
-// so the batch and everything read through it are wave-uniform.
+// so the batch and everything read through it are wave-uniform; such
+// kernels also run the fused matrix-core phases.
 // NT: threads per block (256; 512 for one 2^(R+9)-entry tile per block).
 // Resident waves per SIMD the register allocation must allow: LDS admits
 // five 2^12-entry (32 KiB) single-tile blocks per CU, so 16-entry phases in
-// 256-thread blocks ask for five.
-template <int R, bool MF, int NT>
+// 256-thread blocks ask for five; fused phases keep two.
+template <int R, bool WU, int NT>
 constexpr int pass_waves_per_eu() {
-  return MF ? 2 : (R == 4 && NT == 256 ? 5 : 1);
+  return WU ? 2 : (R == 4 && NT == 256 ? 5 : 1);
 }
 
-template <int R, bool MULTI, bool MF, bool WU, int NT = kBlock>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_per_eu<R, MF, NT>()))) void k_pass(
-    PassArgs a) {
-  extern __shared__ float2 lds[];
+// Blocks are dispatched round-robin over the 8 XCDs; each XCD takes a
+// contiguous range of tiles instead, so the blocks in flight on one XCD read
+// and write neighbouring runs (measured: 3.7 % more bandwidth on the loads
+// and stores alone, about 1 % per pass).
+__device__ __attribute__((always_inline)) inline unsigned xcd_block(uint32_t bx, uint32_t gx) {
+  return (gx & 7u) == 0u ? (bx & 7u) * (gx >> 3) + (bx >> 3) : bx;
+}
+
+template <int R, bool MULTI, bool WU, int NT>
+__device__ __attribute__((always_inline)) inline void pass_body(const PassArgs& a, float2* lds, uint32_t bx,
+                                                                uint32_t gx) {
   constexpr int E = 1 << R;
   const int T = a.T;
   const int TB = T - R;
@@ -220,13 +232,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_p
   const int tile_in_block = MULTI ? (tid >> TB) : 0;
   const uint32_t tt = MULTI ? (uint32_t)(tid & ((1 << TB) - 1)) : (uint32_t)tid;
   const int tiles_per_block = MULTI ? (NT >> TB) : 1;
-  // Blocks are dispatched round-robin over the 8 XCDs; each XCD takes a
-  // contiguous range of tiles instead, so the blocks in flight on one XCD
-  // read and write neighbouring runs (measured: 3.7 % more bandwidth on the
-  // loads and stores alone, about 1 % per pass).
-  const unsigned nb = gridDim.x;
-  const unsigned lb = (nb & 7u) == 0u ? (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3) : blockIdx.x;
-  const long long tile = (long long)lb * tiles_per_block + tile_in_block;
+  const long long tile = (long long)xcd_block(bx, gx) * tiles_per_block + tile_in_block;
   const bool active = tile < a.n_tiles;
   const int tbits = a.h - T;
   long long batch = active ? (tile >> tbits) : 0;
@@ -247,20 +253,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_p
   __syncthreads();
 
   const uint32_t tmask = (1u << T) - 1u;
-  PhaseCtx<R, MF> ctx;
+  PhaseCtx<R> ctx;
   ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
-  ctx.rmr = a.rmrows ? a.rmrows + (size_t)batch * a.rmstride : nullptr;
-  ctx.bits = a.bits;
-  ctx.xpos = (size_t)batch * a.n;
   ctx.tb = 0;
-  ctx.lane = tid & 63;
   ctx.uniform = WU;
   const uint32_t rbase = (uint32_t)tile_in_block << (T + 3);
   for (int p = 0; p < a.n_phases; ++p) {
     const DevPhase P = load_phase(a.phases, p);
-    phase_dispatch<R, MF, WU && !MF>(reinterpret_cast<char*>(lds), rbase, P,
-                                     (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, tmask,
-                                     a.fmats + (size_t)p * kFusedWords, TB);
+    phase_dispatch<R, WU>(reinterpret_cast<char*>(lds), rbase, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs,
+                          ctx, tt, tmask, a.fmats + (size_t)p * kFusedWords, TB);
     __syncthreads();
   }
 
@@ -274,14 +275,33 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_p
   }
 }
 
-// The pass kernel on 16-bit block-scaled storage: the same tiles and
-// phases as k_pass, with the entries decoded (value = stored x block scale
-// of the previous writer) on the way into LDS, and re-encoded on the way out
-// with a fresh power-of-two scale per block of this pass's tiles (taken from
-// the block's largest component after the pass).  4 entries (16 bytes) per
-// HBM access, 2 when a thread holds only 2 entries.
-template <int R, bool MULTI, int S, bool WU>
-__global__ __launch_bounds__(kBlock) void k_pass16(PassArgs a) {
+template <int R, bool MULTI, bool WU, int NT = kBlock>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_per_eu<R, WU, NT>()))) void k_pass(
+    PassArgs a) {
+  extern __shared__ float2 lds[];
+  pass_body<R, MULTI, WU, NT>(a, lds, blockIdx.x, gridDim.x);
+}
+
+template <int R, bool MULTI, bool WU, int NT = kBlock>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_per_eu<R, WU, NT>()))) void k_pass_g(
+    const Seg<PassArgs>* __restrict__ segs) {
+  extern __shared__ float2 lds[];
+  const Seg<PassArgs>* s = group_seg(segs);
+  if (!s) return;
+  const PassArgs a = s->a;
+  pass_body<R, MULTI, WU, NT>(a, lds, blockIdx.x, s->gx);
+}
+
+// The pass kernel on 16-bit block-scaled storage: the same tiles, phases,
+// block shapes and XCD-contiguous tile order as k_pass, with the entries
+// decoded (value = stored x block scale of the previous writer) on the way
+// into LDS, and re-encoded on the way out with a fresh power-of-two scale
+// per block of this pass's tiles (taken from the block's largest component
+// after the pass).  4 entries (16 bytes) per HBM access, 2 when a thread
+// holds only 2 entries.
+template <int R, bool MULTI, int S, bool WU, int NT = kBlock>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_per_eu<R, WU, NT>()))) void k_pass16(
+    PassArgs a) {
   extern __shared__ float2 lds[];
   constexpr int E = 1 << R;
   constexpr int U = E >= 4 ? 4 : 2;
@@ -290,8 +310,8 @@ __global__ __launch_bounds__(kBlock) void k_pass16(PassArgs a) {
   const int tid = threadIdx.x;
   const int tile_in_block = MULTI ? (tid >> TB) : 0;
   const uint32_t tt = MULTI ? (uint32_t)(tid & ((1 << TB) - 1)) : (uint32_t)tid;
-  const int tiles_per_block = MULTI ? (kBlock >> TB) : 1;
-  const long long tile = (long long)blockIdx.x * tiles_per_block + tile_in_block;
+  const int tiles_per_block = MULTI ? (NT >> TB) : 1;
+  const long long tile = (long long)xcd_block(blockIdx.x, gridDim.x) * tiles_per_block + tile_in_block;
   const bool active = tile < a.n_tiles;
   const int tbits = a.h - T;
   long long batch = active ? (tile >> tbits) : 0;
@@ -304,8 +324,8 @@ __global__ __launch_bounds__(kBlock) void k_pass16(PassArgs a) {
   uint32_t* smax = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(lds) + ((size_t)tiles_per_block << (T + 3)));
   const int tpt = 1 << TB;
   const int blk_bits = T < 12 ? T : 12;
-  const bool two = T > blk_bits;
-  if (tid < 2 * tiles_per_block) smax[tid] = 0u;
+  const int nblk = 1 << (T - blk_bits);  // scale blocks per tile (1, 2 or 4)
+  if (tid < nblk * tiles_per_block) smax[tid] = 0u;
 
   // A scale slot gathers bit fields of the entry index, and the block part
   // (boff), the thread part (tt) and the iteration part (it) of an entry's
@@ -336,355 +356,220 @@ __global__ __launch_bounds__(kBlock) void k_pass16(PassArgs a) {
   __syncthreads();
 
   const uint32_t tmask = (1u << T) - 1u;
-  PhaseCtx<R, false> ctx;
+  PhaseCtx<R> ctx;
   ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
-  ctx.rmr = a.rmrows ? a.rmrows + (size_t)batch * a.rmstride : nullptr;
-  ctx.bits = a.bits;
-  ctx.xpos = (size_t)batch * a.n;
   ctx.tb = 0;
-  ctx.lane = tid & 63;
   ctx.uniform = WU;
   for (int p = 0; p < a.n_phases; ++p) {
     const DevPhase P = load_phase(a.phases, p);
-    phase_dispatch<R, false, WU>(reinterpret_cast<char*>(lds), (uint32_t)tile_in_block << (T + 3), P,
-                                 (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, tmask,
-                                 a.fmats + (size_t)p * kFusedWords, TB);
+    phase_dispatch<R, WU>(reinterpret_cast<char*>(lds), (uint32_t)tile_in_block << (T + 3), P,
+                          (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, tmask,
+                          a.fmats + (size_t)p * kFusedWords, TB);
     __syncthreads();
   }
 
-  // largest component of each block of the tile
+  // largest component of each scale block of the tile (the blocks are the
+  // tile's highest local bits, so a thread's entries fall in the block of
+  // their iteration part: one running maximum per block)
   if (active) {
-    float m0 = 0.f, m1 = 0.f;
+    float m[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int it = 0; it < E / 2; ++it) {
       const uint32_t i = (uint32_t)(it * tpt + (int)tt) * 2u;
       const float4 v = *reinterpret_cast<const float4*>(region + ((size_t)swz(i) << 3));
       const float am = fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w)));
-      if ((i >> blk_bits) & 1u) m1 = fmaxf(m1, am);
-      else m0 = fmaxf(m0, am);
+      const uint32_t q = (i >> blk_bits) & 3u;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (q == (uint32_t)c) m[c] = fmaxf(m[c], am);
     }
-    if (m0 > 0.f) atomicMax(&smax[2 * tile_in_block], __float_as_uint(m0));
-    if (m1 > 0.f) atomicMax(&smax[2 * tile_in_block + 1], __float_as_uint(m1));
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < nblk && m[c] > 0.f) atomicMax(&smax[nblk * tile_in_block + c], __float_as_uint(m[c]));
   }
   __syncthreads();
   if (active) {
-    const int x0 = block_exponent(__uint_as_float(smax[2 * tile_in_block]));
-    const int x1 = block_exponent(__uint_as_float(smax[2 * tile_in_block + 1]));
-    const float inv0 = ldexpf(1.f, -x0), inv1 = ldexpf(1.f, -x1);
+    float inv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      inv[c] = c < nblk ? ldexpf(1.f, -block_exponent(__uint_as_float(smax[nblk * tile_in_block + c]))) : 1.f;
 #pragma unroll
     for (int it = 0; it < E / U; ++it) {
       const uint32_t i = (uint32_t)(it * tpt + (int)tt) * (uint32_t)U;
       const uint64_t g = boff + tile_offset(i, a.lo_bits, a.win_lo);
-      const float inv = ((i >> blk_bits) & 1u) ? inv1 : inv0;
+      const uint32_t q = (i >> blk_bits) & 3u;
+      const float iv = q == 0 ? inv[0] : q == 1 ? inv[1] : q == 2 ? inv[2] : inv[3];
       const float4 v0 = *reinterpret_cast<const float4*>(region + ((size_t)swz(i) << 3));
       if constexpr (U == 4) {
         const float4 v1 = *reinterpret_cast<const float4*>(region + ((size_t)swz(i + 2u) << 3));
-        *reinterpret_cast<uint4*>(Bw + g) = make_uint4(pack16<S>(v0.x, v0.y, inv), pack16<S>(v0.z, v0.w, inv),
-                                                       pack16<S>(v1.x, v1.y, inv), pack16<S>(v1.z, v1.w, inv));
+        *reinterpret_cast<uint4*>(Bw + g) = make_uint4(pack16<S>(v0.x, v0.y, iv), pack16<S>(v0.z, v0.w, iv),
+                                                       pack16<S>(v1.x, v1.y, iv), pack16<S>(v1.z, v1.w, iv));
       } else {
-        *reinterpret_cast<uint2*>(Bw + g) = make_uint2(pack16<S>(v0.x, v0.y, inv), pack16<S>(v0.z, v0.w, inv));
+        *reinterpret_cast<uint2*>(Bw + g) = make_uint2(pack16<S>(v0.x, v0.y, iv), pack16<S>(v0.z, v0.w, iv));
       }
     }
-    if (tt == 0) {
+    if (tt < (uint32_t)nblk) {
       float* sout = a.scale_out + batch * a.scale_stride + ((long long)blk << (T - blk_bits));
-      sout[0] = ldexpf(1.f, x0);
-      if (two) sout[1] = ldexpf(1.f, x1);
+      sout[tt] = ldexpf(1.f, block_exponent(__uint_as_float(smax[nblk * tile_in_block + tt])));
     }
   }
 }
 
-// Waits for outstanding vector-memory operations only (vmcnt <= n; gfx9
-// encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at
-// their maxima), and the LDS-only wait used before raw barriers.
-#define TNC_WAIT_VMCNT0() __builtin_amdgcn_s_waitcnt(0x0F70)
-// vmcnt <= n for n < 16 (vector-memory operations retire in issue order)
-#define TNC_WAIT_VMCNT(n) __builtin_amdgcn_s_waitcnt(0x0F70 | ((n) & 15))
-#define TNC_WAIT_LGKM0() __builtin_amdgcn_s_waitcnt(0xC07F)
+// ---------------------------------------------------------------------------
+// Launch records.
 
-// Workgroup barrier for LDS only: waits for this wave's LDS operations,
-// not for vector-memory ones (a prefetch in flight stays in flight; the
-// plain __syncthreads() would wait for it).  The empty asm statements keep
-// the compiler from moving memory accesses across.
-__device__ __attribute__((always_inline)) inline void tnc_lds_barrier() {
-  asm volatile("" ::: "memory");
-  TNC_WAIT_LGKM0();
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
+template <class A>
+static void set_arg(Launch* L, const A& a) {
+  static_assert(sizeof(A) <= kMaxArgBytes, "kernel argument too large for a launch record");
+  std::memset(L->arg, 0, sizeof(L->arg));
+  std::memcpy(L->arg, &a, sizeof(A));
+  L->arg_bytes = (uint32_t)sizeof(A);
+  L->seg_stride = (uint32_t)sizeof(Seg<A>);
 }
 
-// Persistent, software-pipelined form of the pass for one 2^T-entry tile
-// per NT-thread block (T - R = 8 with 256 threads, 9 with 512): each block
-// walks tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's HBM
-// loads are issued right after the current tile has been staged in LDS, so
-// they are in flight while the current tile's register phases run (the
-// phase barriers wait for LDS only).
-template <int R, bool MF, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_pass_pipe(PassArgs a) {
-  extern __shared__ float2 lds[];
-  constexpr int E = 1 << R;
-  constexpr int HALF = E / 2;
-  const int T = a.T;
-  const int tid = threadIdx.x;
-  const uint32_t tt = (uint32_t)tid;
-  const int tbits = a.h - T;
-  char* region = reinterpret_cast<char*>(lds);
-  const uint32_t tmask = (1u << T) - 1u;
-  auto tile_base = [&](long long tile) -> float2* {
-    const long long batch = tile >> tbits;
-    const unsigned long long blk = (unsigned long long)tile & ((1ull << tbits) - 1ull);
-    return a.B + (batch << a.h) + block_offset(blk, a.lo_bits, a.win_lo, a.win_len);
-  };
-  // prefetch buffer as plain floats (arrays of HIP vector types can be kept
-  // out of registers)
-  float p0[HALF], p1[HALF], p2[HALF], p3[HALF];
-  auto prefetch = [&](long long t) {
-    const float2* src = tile_base(t);
-#pragma unroll
-    for (int it = 0; it < HALF; ++it) {
-      const uint32_t i = (uint32_t)(it * NT + tid) * 2u;
-      const float4 q = *reinterpret_cast<const float4*>(src + tile_offset(i, a.lo_bits, a.win_lo));
-      p0[it] = q.x;
-      p1[it] = q.y;
-      p2[it] = q.z;
-      p3[it] = q.w;
-    }
-  };
-  long long tile = blockIdx.x;
-  if (tile < a.n_tiles) prefetch(tile);
-  for (; tile < a.n_tiles; tile += gridDim.x) {
-    const long long batch = tile >> tbits;
-#pragma unroll
-    for (int it = 0; it < HALF; ++it) {
-      const uint32_t i = (uint32_t)(it * NT + tid) * 2u;
-      *reinterpret_cast<float4*>(region + ((size_t)swz(i) << 3)) = make_float4(p0[it], p1[it], p2[it], p3[it]);
-    }
-    tnc_lds_barrier();
-    const long long next = tile + gridDim.x;
-    if (next < a.n_tiles) prefetch(next);
-    PhaseCtx<R, MF> ctx;
-    ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
-    ctx.rmr = a.rmrows ? a.rmrows + (size_t)batch * a.rmstride : nullptr;
-    ctx.bits = a.bits;
-    ctx.xpos = (size_t)batch * a.n;
-    ctx.tb = 0;
-    ctx.lane = tid & 63;
-    ctx.uniform = true;
-    for (int p = 0; p < a.n_phases; ++p) {
-      const DevPhase P = load_phase(a.phases, p);
-      phase_dispatch<R, MF, !MF>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, tmask,
-                                 a.fmats + (size_t)p * kFusedWords, T - R);
-      tnc_lds_barrier();
-    }
-    float2* dst = tile_base(tile);
-#pragma unroll
-    for (int it = 0; it < HALF; ++it) {
-      const uint32_t i = (uint32_t)(it * NT + tid) * 2u;
-      const float4 val = *reinterpret_cast<const float4*>(region + ((size_t)swz(i) << 3));
-      *reinterpret_cast<float4*>(dst + tile_offset(i, a.lo_bits, a.win_lo)) = val;
-    }
-    tnc_lds_barrier();
+static hipError_t set_shape(Launch* L, long long blocks_x, unsigned blocks_y, unsigned threads, size_t shmem) {
+  if (blocks_x <= 0 || blocks_x > 0x7fffffffLL || blocks_y == 0 || blocks_y > 65535) return hipErrorInvalidValue;
+  L->grid = dim3((unsigned)blocks_x, blocks_y, 1);
+  L->block = dim3(threads, 1, 1);
+  L->shmem = (uint32_t)shmem;
+  return hipSuccess;
+}
+
+hipError_t record_init(const InitArgs& a, Launch* L) {
+  *L = Launch();
+  L->cls = 0;
+  if (a.store == STORE_C64) {
+    if (a.m0 - 1 > 64) return hipErrorInvalidValue;
+    const long long threads = a.h < 11 ? ((long long)a.n_batches << a.h) : (((long long)a.n_batches << a.h) >> 5);
+    L->fn = reinterpret_cast<const void*>(&k_init);
+    L->gfn = reinterpret_cast<const void*>(&k_init_g);
+    set_arg(L, a);
+    return set_shape(L, (threads + kBlock - 1) / kBlock, 1, kBlock, 0);
   }
+  if (a.m0 - 1 > 64 || a.blk_bits > 12 || a.blk_bits < 0 || a.blk_bits > a.h) return hipErrorInvalidValue;
+  if (a.store == STORE_F16) L->fn = reinterpret_cast<const void*>(&k_init16<STORE_F16>);
+  else if (a.store == STORE_BF16) L->fn = reinterpret_cast<const void*>(&k_init16<STORE_BF16>);
+  else return hipErrorInvalidValue;
+  set_arg(L, a);
+  return set_shape(L, (long long)a.n_batches << (a.h - a.blk_bits), 1, kBlock, 0);
 }
 
-typedef __attribute__((address_space(3))) void lds_void_t;
-
-// Persistent pass with double-buffered LDS tiles: the next tile is fetched
-// by direct global->LDS loads (global_load_lds_dwordx4, no VGPRs) while the
-// current tile's register phases run.  Slot pair p of a buffer holds tile
-// entries swz(p), swz(p)+1 (swz is an involution that keeps pairs), so the
-// register phases use the same placement as the other pass kernels.  Phase
-// barriers wait for LDS only, leaving the prefetch in flight.
-// One block per CU (two 2^T-entry LDS tiles): 4 or 8 waves per CU.
-template <int R, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT / 256))) void k_pass_dma(PassArgs a) {
-  constexpr int E = 1 << R;
-  constexpr int HALF = E / 2;
-  constexpr int T = R + (NT == 512 ? 9 : 8);
-  // two statically distinct buffers: the compiler can see that the phases
-  // never read the buffer the DMA is writing, so it adds no memory waits
-  __shared__ float2 ping[1 << T];
-  __shared__ float2 pong[1 << T];
-  const int tid = threadIdx.x;
-  const uint32_t tt = (uint32_t)tid;
-  const int tbits = a.h - T;
-  constexpr uint32_t tmask = (1u << T) - 1u;
-  const int wave = tid >> 6;
-  auto tile_base = [&](long long tile) -> float2* {
-    const long long batch = tile >> tbits;
-    const unsigned long long blk = (unsigned long long)tile & ((1ull << tbits) - 1ull);
-    return a.B + (batch << a.h) + block_offset(blk, a.lo_bits, a.win_lo, a.win_len);
-  };
-  auto fetch = [&](long long tile, float2* dst) {
-    const float2* src = tile_base(tile);
-#pragma unroll
-    for (int it = 0; it < HALF; ++it) {
-      const uint32_t p = (uint32_t)(it * NT + tid) * 2u;
-      const float2* g = src + tile_offset(swz(p), a.lo_bits, a.win_lo);
-      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(g),
-                                       (lds_void_t*)(reinterpret_cast<char*>(dst) + ((size_t)(it * NT + wave * 64) << 4)),
-                                       16, 0, 0);
-    }
-  };
-  // one tile: wait for its prefetch, start the next tile's, run the phases,
-  // store
-  auto process = [&](long long tile, float2* cur, float2* nxt) {
-    const long long batch = tile >> tbits;
-    // this tile's prefetch was issued before the previous tile's HALF
-    // stores, and vector-memory operations retire in issue order
-    TNC_WAIT_VMCNT(HALF);
-    TNC_WAIT_LGKM0();
-    __builtin_amdgcn_s_barrier();
-    const long long next = tile + gridDim.x;
-    if (next < a.n_tiles) fetch(next, nxt);
-    char* region = reinterpret_cast<char*>(cur);
-    PhaseCtx<R, false> ctx;
-    ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
-    ctx.rmr = nullptr;
-    ctx.bits = a.bits;
-    ctx.xpos = (size_t)batch * a.n;
-    ctx.tb = 0;
-    ctx.lane = tid & 63;
-    ctx.uniform = true;
-    for (int p = 0; p < a.n_phases; ++p) {
-      const DevPhase P = load_phase(a.phases, p);
-      phase_dispatch<R, false>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, tmask);
-      TNC_WAIT_LGKM0();
-      __builtin_amdgcn_s_barrier();
-    }
-    float2* dst = tile_base(tile);
-#pragma unroll
-    for (int it = 0; it < HALF; ++it) {
-      const uint32_t i = (uint32_t)(it * NT + tid) * 2u;
-      const float4 val = *reinterpret_cast<const float4*>(region + ((size_t)swz(i) << 3));
-      *reinterpret_cast<float4*>(dst + tile_offset(i, a.lo_bits, a.win_lo)) = val;
-    }
-  };
-  long long tile = blockIdx.x;
-  if (tile >= a.n_tiles) return;
-  fetch(tile, ping);
-  // the first tile has no stores queued behind its loads: wait for all
-  TNC_WAIT_VMCNT0();
-  for (;;) {
-    process(tile, ping, pong);
-    tile += gridDim.x;
-    if (tile >= a.n_tiles) break;
-    process(tile, pong, ping);
-    tile += gridDim.x;
-    if (tile >= a.n_tiles) break;
-  }
+hipError_t record_resolve(const ResolveArgs& a, Launch* L) {
+  *L = Launch();
+  L->cls = 0;
+  const long long total = (long long)a.n_batches * a.n_ops;
+  if (total <= 0) return hipErrorInvalidValue;
+  L->fn = reinterpret_cast<const void*>(&k_resolve);
+  L->gfn = reinterpret_cast<const void*>(&k_resolve_g);
+  set_arg(L, a);
+  return set_shape(L, (total + kBlock - 1) / kBlock, 1, kBlock, 0);
 }
 
-static int pipe_blocks_per_cu(const void* fn, int nt, size_t lds) {
-  int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, nt, lds) != hipSuccess || blocks < 1) blocks = 1;
-  return blocks;
+template <int R, int NT, bool MULTI, bool WU>
+static void pick_pass(Launch* L) {
+  L->fn = reinterpret_cast<const void*>(&k_pass<R, MULTI, WU, NT>);
+  L->gfn = reinterpret_cast<const void*>(&k_pass_g<R, MULTI, WU, NT>);
 }
 
-static int device_cus() {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-    if (cus <= 0) cus = 256;
-  }
-  return cus;
+template <int R, int NT, bool MULTI, bool WU>
+static void pick_pass16(Launch* L, int store) {
+  if (store == STORE_F16) L->fn = reinterpret_cast<const void*>(&k_pass16<R, MULTI, STORE_F16, WU, NT>);
+  else L->fn = reinterpret_cast<const void*>(&k_pass16<R, MULTI, STORE_BF16, WU, NT>);
 }
 
-template <int R, int NT>
-static hipError_t launch_pass_dma(const PassArgs& a, hipStream_t s) {
-  static int bpc = 0;
-  if (bpc == 0) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, reinterpret_cast<const void*>(&k_pass_dma<R, NT>), NT, 0) !=
-            hipSuccess ||
-        bpc < 1)
-      bpc = 1;
-  }
-  const long long grid = std::min<long long>(a.n_tiles, (long long)bpc * device_cus());
-  hipLaunchKernelGGL((k_pass_dma<R, NT>), dim3((unsigned)grid), dim3(NT), 0, s, a);
-  return hipGetLastError();
-}
-
-template <int R, int S>
-static hipError_t launch_pass16_rs(const PassArgs& a, hipStream_t s) {
-  const int TB = a.T - R;
-  if (TB < 0 || TB > 8) return hipErrorInvalidValue;
-  const bool multi = TB < 8;
-  const int tiles_per_block = multi ? (kBlock >> TB) : 1;
-  const long long blocks = ((long long)a.n_tiles + tiles_per_block - 1) / tiles_per_block;
-  const size_t lds = ((size_t)tiles_per_block << (a.T + 3)) + 2 * sizeof(uint32_t) * (size_t)kBlock;
-  if (multi && TB >= 6) hipLaunchKernelGGL((k_pass16<R, true, S, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
-  else if (multi) hipLaunchKernelGGL((k_pass16<R, true, S, false>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
-  else hipLaunchKernelGGL((k_pass16<R, false, S, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
-  return hipGetLastError();
-}
-
+// Block shape of a pass: one 2^(R+9)-entry tile per 512-thread block, one
+// 2^(R+8)-entry tile per 256-thread block, or several smaller tiles per
+// 256-thread block (their waves lie inside one tile when T - R >= 6).
 template <int R>
-static hipError_t launch_pass_r(const PassArgs& a, hipStream_t s) {
-  if (a.store == STORE_F16) return launch_pass16_rs<R, STORE_F16>(a, s);
-  if (a.store == STORE_BF16) return launch_pass16_rs<R, STORE_BF16>(a, s);
+static hipError_t record_pass_r(const PassArgs& a, Launch* L) {
   const int TB = a.T - R;
-  const bool dma_ok = a.pipeline == 1 && !a.mfma;
-  if constexpr (R >= 4) {
-    if (dma_ok && TB == 8) return launch_pass_dma<R, 256>(a, s);
-  }
-  if constexpr (R == 4) {
-    if (dma_ok && TB == 9) return launch_pass_dma<R, 512>(a, s);
-  }
-  if (TB == 9 && !a.mfma) {
-    // one 2^(R+9)-entry tile per 512-thread block
-    const size_t lds9 = (size_t)512 * (1 << R) * sizeof(float2);
-    if (a.pipeline == 2) {
-      static int bpc9[8] = {0};
-      if (bpc9[R] == 0) bpc9[R] = pipe_blocks_per_cu(reinterpret_cast<const void*>(&k_pass_pipe<R, false, 512>), 512, lds9);
-      const long long grid = std::min<long long>(a.n_tiles, (long long)bpc9[R] * device_cus());
-      hipLaunchKernelGGL((k_pass_pipe<R, false, 512>), dim3((unsigned)grid), dim3(512), lds9, s, a);
-      return hipGetLastError();
-    }
-    hipLaunchKernelGGL((k_pass<R, false, false, true, 512>), dim3((unsigned)a.n_tiles), dim3(512), lds9, s, a);
-    return hipGetLastError();
-  }
-  if (TB < 0 || TB > 8) return hipErrorInvalidValue;
+  if (TB < 0 || TB > 9) return hipErrorInvalidValue;
+  const bool s16 = a.store == STORE_F16 || a.store == STORE_BF16;
+  if (!s16 && a.store != STORE_C64) return hipErrorInvalidValue;
+  const int NT = TB == 9 ? 512 : kBlock;
   const bool multi = TB < 8;
   const int tiles_per_block = multi ? (kBlock >> TB) : 1;
   const long long blocks = ((long long)a.n_tiles + tiles_per_block - 1) / tiles_per_block;
-  const size_t lds = (size_t)kBlock * (1 << R) * sizeof(float2);
-  // matrix-core updates need the four lanes of an MFMA block in one tile
-  const bool mf = a.mfma && TB >= 2 && a.rmrows != nullptr;
-  // persistent blocks with the next tile prefetched into registers
-  // (pipeline = 2; the matrix-core form uses them for pipeline = 1 too)
-  if (!multi && (a.pipeline == 2 || (a.pipeline && mf))) {
-    const void* fn = mf ? reinterpret_cast<const void*>(&k_pass_pipe<R, true, kBlock>)
-                        : reinterpret_cast<const void*>(&k_pass_pipe<R, false, kBlock>);
-    static int per_cu[2][8] = {{0}};
-    int& bpc = per_cu[mf ? 1 : 0][R];
-    if (bpc == 0) bpc = pipe_blocks_per_cu(fn, kBlock, lds);
-    const long long resident = (long long)bpc * device_cus();
-    const long long grid = std::min<long long>(a.n_tiles, resident);
-    if (mf) hipLaunchKernelGGL((k_pass_pipe<R, true, kBlock>), dim3((unsigned)grid), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((k_pass_pipe<R, false, kBlock>), dim3((unsigned)grid), dim3(kBlock), lds, s, a);
-    return hipGetLastError();
-  }
-  if (multi) {
-    if (mf) hipLaunchKernelGGL((k_pass<R, true, true, false>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
-    else if (TB >= 6) hipLaunchKernelGGL((k_pass<R, true, false, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((k_pass<R, true, false, false>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+  size_t lds = (size_t)tiles_per_block << (a.T + 3);
+  if (s16) lds += (size_t)4 * NT;  // per-tile block maxima
+  if (TB == 9) {
+    if (s16) pick_pass16<R, 512, false, true>(L, a.store);
+    else pick_pass<R, 512, false, true>(L);
+  } else if (!multi) {
+    if (s16) pick_pass16<R, kBlock, false, true>(L, a.store);
+    else pick_pass<R, kBlock, false, true>(L);
+  } else if (TB >= 6) {
+    if (s16) pick_pass16<R, kBlock, true, true>(L, a.store);
+    else pick_pass<R, kBlock, true, true>(L);
   } else {
-    if (mf) hipLaunchKernelGGL((k_pass<R, false, true, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((k_pass<R, false, false, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    if (s16) pick_pass16<R, kBlock, true, false>(L, a.store);
+    else pick_pass<R, kBlock, true, false>(L);
   }
-  return hipGetLastError();
+  set_arg(L, a);
+  return set_shape(L, blocks, 1, NT, lds);
 }
 
-hipError_t launch_pass(const PassArgs& a, int R, hipStream_t s) {
+hipError_t record_pass(const PassArgs& a, int R, Launch* L) {
+  *L = Launch();
+  L->cls = 1;
   switch (R) {
-    case 1: return launch_pass_r<1>(a, s);
-    case 2: return launch_pass_r<2>(a, s);
-    case 3: return launch_pass_r<3>(a, s);
-    case 4: return launch_pass_r<4>(a, s);
-    case 5: return launch_pass_r<5>(a, s);
+    case 1: return record_pass_r<1>(a, L);
+    case 2: return record_pass_r<2>(a, L);
+    case 3: return record_pass_r<3>(a, L);
+    case 4: return record_pass_r<4>(a, L);
+    case 5: return record_pass_r<5>(a, L);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t issue(const Launch& L, hipStream_t s) {
+  void* args[1] = {const_cast<unsigned char*>(L.arg)};
+  return hipLaunchKernel(L.fn, L.grid, L.block, args, L.shmem, s);
+}
+
+hipError_t graph_add(const Launch& L, hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* dep, size_t n_dep) {
+  hipKernelNodeParams kp;
+  std::memset(&kp, 0, sizeof(kp));
+  void* args[1] = {const_cast<unsigned char*>(L.arg)};
+  kp.func = const_cast<void*>(L.fn);
+  kp.gridDim = L.grid;
+  kp.blockDim = L.block;
+  kp.sharedMemBytes = L.shmem;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  return hipGraphAddKernelNode(node, g, dep, n_dep, &kp);
+}
+
+bool groupable(const Launch& a, const Launch& b) {
+  return a.gfn && a.fn == b.fn && a.gfn == b.gfn && a.block.x == b.block.x && a.seg_stride == b.seg_stride;
+}
+
+size_t write_segments(const Launch* const* members, int n, unsigned char* dst) {
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    const Launch& L = *members[i];
+    std::memset(dst + off, 0, L.seg_stride);
+    const uint32_t g[2] = {L.grid.x, L.grid.y};
+    std::memcpy(dst + off, g, sizeof(g));
+    std::memcpy(dst + off + kSegHeader, L.arg, L.arg_bytes);
+    off += L.seg_stride;
+  }
+  return off;
+}
+
+hipError_t issue_grouped(const Launch* const* members, int n, const void* d_segs, hipStream_t s) {
+  if (n < 1 || n > 65535 || !d_segs) return hipErrorInvalidValue;
+  const Launch& L0 = *members[0];
+  unsigned gx = 0, gy = 0;
+  uint32_t shmem = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!groupable(L0, *members[i])) return hipErrorInvalidValue;
+    gx = std::max(gx, members[i]->grid.x);
+    gy = std::max(gy, members[i]->grid.y);
+    shmem = std::max(shmem, members[i]->shmem);
+  }
+  void* args[1] = {(void*)&d_segs};
+  return hipLaunchKernel(L0.gfn, dim3(gx, gy, (unsigned)n), L0.block, args, shmem, s);
 }
 
 // Host emulation of a fused phase, wave by wave, with the lane layout of
@@ -801,13 +686,9 @@ static void emulate_pass_r(const PassArgs& a) {
           dst[1] = src[1];
         }
       }
-    PhaseCtx<R, false> ctx;
+    PhaseCtx<R> ctx;
     ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
-    ctx.rmr = a.rmrows ? a.rmrows + (size_t)batch * a.rmstride : nullptr;
-    ctx.bits = a.bits;
-    ctx.xpos = (size_t)batch * a.n;
     ctx.tb = 0;
-    ctx.lane = 0;
     ctx.uniform = false;
     for (int p = 0; p < a.n_phases; ++p) {
       const DevPhase P = load_phase(a.phases, p);
@@ -818,23 +699,24 @@ static void emulate_pass_r(const PassArgs& a) {
         continue;
       }
       for (int tt = 0; tt < tpt; ++tt)
-        phase_dispatch<R, false>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, (uint32_t)tt, tmask);
+        phase_dispatch<R>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, (uint32_t)tt, tmask);
     }
     if (s16) {
-      float amax[2] = {0.f, 0.f};
+      const int nblk = 1 << (T - blk_bits);
+      float amax[4] = {0.f, 0.f, 0.f, 0.f};
       for (uint32_t i = 0; i < (1u << T); ++i) {
         const float2 v = lds[swz(i)];
-        float& m = amax[(i >> blk_bits) & 1u];
+        float& m = amax[(i >> blk_bits) & 3u];
         m = std::max(m, std::max(std::fabs(v.x), std::fabs(v.y)));
       }
-      const int x0 = block_exponent(amax[0]), x1 = block_exponent(amax[1]);
+      int ex[4];
+      for (int c = 0; c < 4; ++c) ex[c] = block_exponent(amax[c]);
       for (uint32_t i = 0; i < (1u << T); ++i) {
         const uint64_t g = boff + tile_offset(i, a.lo_bits, a.win_lo);
-        Bw[g] = enc(lds[swz(i)], std::ldexp(1.f, -(((i >> blk_bits) & 1u) ? x1 : x0)));
+        Bw[g] = enc(lds[swz(i)], std::ldexp(1.f, -ex[(i >> blk_bits) & 3u]));
       }
       float* sout = a.scale_out + batch * a.scale_stride + ((long long)blk << (T - blk_bits));
-      sout[0] = std::ldexp(1.f, x0);
-      if (T > blk_bits) sout[1] = std::ldexp(1.f, x1);
+      for (int c = 0; c < nblk; ++c) sout[c] = std::ldexp(1.f, ex[c]);
       continue;
     }
     for (int tt = 0; tt < tpt; ++tt)
@@ -880,17 +762,17 @@ __device__ inline double2 late_in(const LateArgs& a, const TIn* __restrict__ in,
 }
 
 template <typename TIn, int S>
-__global__ __launch_bounds__(kBlock) void k_late(LateArgs a) {
+__device__ __attribute__((always_inline)) inline void late_body(const LateArgs& a, uint32_t bx, uint32_t by) {
   __shared__ double2 As[16][65];
   __shared__ double2 Bs[16][65];
-  const int b = blockIdx.y;
+  const int b = by;
   const int tilesN = (a.N + 63) / 64;
   const int tilesM = (a.M + 63) / 64;
   // Consecutive block ids go to different XCDs (round robin over 8); the
   // tilesN column blocks of one row tile are given ids that land on the
   // same XCD, so they share its L2 for the row tile.
-  const int xcd = blockIdx.x & 7;
-  const int g = blockIdx.x >> 3;
+  const int xcd = bx & 7;
+  const int g = bx >> 3;
   const int bn = g % tilesN;
   const int bm = (g / tilesN) * 8 + xcd;
   if (bm >= tilesM) return;
@@ -951,6 +833,17 @@ __global__ __launch_bounds__(kBlock) void k_late(LateArgs a) {
   }
 }
 
+template <typename TIn, int S>
+__global__ __launch_bounds__(kBlock) void k_late(LateArgs a) { late_body<TIn, S>(a, blockIdx.x, blockIdx.y); }
+
+template <typename TIn, int S>
+__global__ __launch_bounds__(kBlock) void k_late_g(const Seg<LateArgs>* __restrict__ segs) {
+  const Seg<LateArgs>* s = group_seg(segs);
+  if (!s) return;
+  const LateArgs a = s->a;
+  late_body<TIn, S>(a, blockIdx.x, blockIdx.y);
+}
+
 // The same contraction on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
 // a 64 x 64 output tile per 256-thread block, 32 x 32 (2 x 2 MFMA tiles)
 // per wave; the complex product takes four real MFMAs per tile and k-step
@@ -959,14 +852,14 @@ __global__ __launch_bounds__(kBlock) void k_late(LateArgs a) {
 typedef double tnc_d4 __attribute__((ext_vector_type(4)));
 
 template <typename TIn, int S>
-__global__ __launch_bounds__(kBlock) void k_late_mf(LateArgs a) {
+__device__ __attribute__((always_inline)) inline void late_mf_body(const LateArgs& a, uint32_t bx, uint32_t by) {
   __shared__ double2 As[16][65];
   __shared__ double2 Bs[16][65];
-  const int b = blockIdx.y;
+  const int b = by;
   const int tilesN = (a.N + 63) / 64;
   const int tilesM = (a.M + 63) / 64;
-  const int xcd = blockIdx.x & 7;
-  const int g = blockIdx.x >> 3;
+  const int xcd = bx & 7;
+  const int g = bx >> 3;
   const int bn = g % tilesN;
   const int bm = (g / tilesN) * 8 + xcd;
   if (bm >= tilesM) return;
@@ -1046,23 +939,44 @@ __global__ __launch_bounds__(kBlock) void k_late_mf(LateArgs a) {
       }
 }
 
-hipError_t launch_late(const LateArgs& a, bool in_c64, hipStream_t s) {
+template <typename TIn, int S>
+__global__ __launch_bounds__(kBlock) void k_late_mf(LateArgs a) { late_mf_body<TIn, S>(a, blockIdx.x, blockIdx.y); }
+
+template <typename TIn, int S>
+__global__ __launch_bounds__(kBlock) void k_late_mf_g(const Seg<LateArgs>* __restrict__ segs) {
+  const Seg<LateArgs>* s = group_seg(segs);
+  if (!s) return;
+  const LateArgs a = s->a;
+  late_mf_body<TIn, S>(a, blockIdx.x, blockIdx.y);
+}
+
+hipError_t record_late(const LateArgs& a, bool in_c64, Launch* L) {
+  *L = Launch();
+  L->cls = 2;
   const long long tilesM8 = ((long long)(a.M + 63) / 64 + 7) / 8 * 8;
   const long long tiles = tilesM8 * ((a.N + 63) / 64);
-  if (tiles > 0x7fffffffLL || a.n_batches > 65535) return hipErrorInvalidValue;
-  dim3 grid((unsigned)tiles, (unsigned)a.n_batches);
   // matrix cores for contractions large enough to fill their 16 x 16 tiles
-  if (in_c64 && a.N >= 32 && a.K >= 16 && a.M >= 64) {
-    if (a.store == STORE_F16) hipLaunchKernelGGL((k_late_mf<uint32_t, STORE_F16>), grid, dim3(kBlock), 0, s, a);
-    else if (a.store == STORE_BF16) hipLaunchKernelGGL((k_late_mf<uint32_t, STORE_BF16>), grid, dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_late_mf<float2, STORE_C64>), grid, dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+  const bool mf = in_c64 && a.N >= 32 && a.K >= 16 && a.M >= 64;
+  if (!in_c64) {
+    L->fn = reinterpret_cast<const void*>(&k_late<double2, STORE_C64>);
+    L->gfn = reinterpret_cast<const void*>(&k_late_g<double2, STORE_C64>);
+  } else if (a.store == STORE_F16) {
+    L->fn = mf ? reinterpret_cast<const void*>(&k_late_mf<uint32_t, STORE_F16>)
+               : reinterpret_cast<const void*>(&k_late<uint32_t, STORE_F16>);
+  } else if (a.store == STORE_BF16) {
+    L->fn = mf ? reinterpret_cast<const void*>(&k_late_mf<uint32_t, STORE_BF16>)
+               : reinterpret_cast<const void*>(&k_late<uint32_t, STORE_BF16>);
+  } else if (a.store == STORE_C64) {
+    L->fn = mf ? reinterpret_cast<const void*>(&k_late_mf<float2, STORE_C64>)
+               : reinterpret_cast<const void*>(&k_late<float2, STORE_C64>);
+    L->gfn = mf ? reinterpret_cast<const void*>(&k_late_mf_g<float2, STORE_C64>)
+                : reinterpret_cast<const void*>(&k_late_g<float2, STORE_C64>);
+  } else {
+    return hipErrorInvalidValue;
   }
-  if (!in_c64) hipLaunchKernelGGL((k_late<double2, STORE_C64>), grid, dim3(kBlock), 0, s, a);
-  else if (a.store == STORE_F16) hipLaunchKernelGGL((k_late<uint32_t, STORE_F16>), grid, dim3(kBlock), 0, s, a);
-  else if (a.store == STORE_BF16) hipLaunchKernelGGL((k_late<uint32_t, STORE_BF16>), grid, dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL((k_late<float2, STORE_C64>), grid, dim3(kBlock), 0, s, a);
-  return hipGetLastError();
+  set_arg(L, a);
+  if (a.n_batches < 1) return hipErrorInvalidValue;
+  return set_shape(L, tiles, (unsigned)a.n_batches, kBlock, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1081,10 +995,10 @@ __device__ inline int insert_zero(int x, int bit) {
   return ((x - lo) << 1) | lo;
 }
 
-__global__ __launch_bounds__(kBlock) void k_late_ops(LateOpsArgs a) {
-  extern __shared__ double2 st[];
-  const long long row_out = blockIdx.x;
-  const int b = blockIdx.y;
+__device__ __attribute__((always_inline)) inline void late_ops_body(const LateOpsArgs& a, double2* st, uint32_t bx,
+                                                                    uint32_t by) {
+  const long long row_out = bx;
+  const int b = by;
   const int sb = a.s;
   const int total = 1 << (sb + a.j);
   const double2* in = a.in + (size_t)b * a.in_batch_stride + ((size_t)row_out << (a.j + sb));
@@ -1157,11 +1071,96 @@ __global__ __launch_bounds__(kBlock) void k_late_ops(LateOpsArgs a) {
   }
 }
 
-hipError_t launch_late_ops(const LateOpsArgs& a, hipStream_t s) {
-  if (a.s + a.j > 12 || a.rows_out > 0x7fffffffLL || a.n_batches > 65535) return hipErrorInvalidValue;
-  const size_t lds = sizeof(double2) << (a.s + a.j);
-  hipLaunchKernelGGL(k_late_ops, dim3((unsigned)a.rows_out, (unsigned)a.n_batches), dim3(kBlock), lds, s, a);
-  return hipGetLastError();
+__global__ __launch_bounds__(kBlock) void k_late_ops(LateOpsArgs a) {
+  extern __shared__ double2 st[];
+  late_ops_body(a, st, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_late_ops_g(const Seg<LateOpsArgs>* __restrict__ segs) {
+  extern __shared__ double2 st[];
+  const Seg<LateOpsArgs>* s = group_seg(segs);
+  if (!s) return;
+  const LateOpsArgs a = s->a;
+  late_ops_body(a, st, blockIdx.x, blockIdx.y);
+}
+
+hipError_t record_late_ops(const LateOpsArgs& a, Launch* L) {
+  *L = Launch();
+  L->cls = 2;
+  if (a.s + a.j > 12 || a.n_batches < 1) return hipErrorInvalidValue;
+  L->fn = reinterpret_cast<const void*>(&k_late_ops);
+  L->gfn = reinterpret_cast<const void*>(&k_late_ops_g);
+  set_arg(L, a);
+  return set_shape(L, a.rows_out, (unsigned)a.n_batches, kBlock, sizeof(double2) << (a.s + a.j));
+}
+
+// ---------------------------------------------------------------------------
+// The complex128 reference sweep: the same product initialisation as k_init
+// kept in FP64, then every update of the sweep as its own launch, each
+// thread one pair of entries.  A test path (the paper's precision study
+// compares complex64 with complex128 runs, Sec. 5.1), not tuned.
+__global__ __launch_bounds__(kBlock) void k_init64(InitArgs a) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = (long long)a.n_batches << a.h;
+  if (gid >= total) return;
+  const long long batch = gid >> a.h;
+  const unsigned long long i = (unsigned long long)gid & ((1ull << a.h) - 1ull);
+  double2* out = reinterpret_cast<double2*>(a.B) + gid;
+  const int m = a.m0;
+  if (i >> m) {
+    *out = make_double2(0.0, 0.0);
+    return;
+  }
+  const int x0 = a.bits[batch * a.n];
+  double2 val = a.v[i & 1ull];
+  for (int j = 1; j < m; ++j) {
+    const int aj = (int)((i >> j) & 1ull), ajm = (int)((i >> (j - 1)) & 1ull);
+    val = zmul(val, a.seg[4 * (j - 1) + 2 * aj + ajm]);
+  }
+  *out = zmul(val, a.f[x0][(i >> (m - 1)) & 1ull]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_op64(Op64Args a) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long pairs = (long long)a.n_batches << (a.h - 1);
+  if (gid >= pairs) return;
+  const Op64 op = *a.op;
+  const long long batch = gid >> (a.h - 1);
+  const unsigned long long p = (unsigned long long)gid & ((1ull << (a.h - 1)) - 1ull);
+  const unsigned long long ts = 1ull << op.target;
+  const unsigned long long lo = p & (ts - 1ull);
+  const unsigned long long i0 = ((p - lo) << 1) | lo, i1 = i0 | ts;
+  double2* B = a.B + (batch << a.h);
+  if (op.kind == 1) {
+    B[i1] = B[i0];
+    return;
+  }
+  const uint8_t* x = a.bits + (size_t)batch * a.n;
+  const int var = (op.xrow0 >= 0 ? 2 * (x[op.xrow0] & 1) : 0) + (op.xrow1 >= 0 ? (x[op.xrow1] & 1) : 0);
+  const int c = op.control >= 0 ? (int)((i0 >> op.control) & 1ull) : 0;
+  const double2* m = op.m[var][c];
+  const double2 b0 = B[i0], b1 = B[i1];
+  const double2 p0 = zmul(m[0], b0), q0 = zmul(m[1], b1), p1 = zmul(m[2], b0), q1 = zmul(m[3], b1);
+  B[i0] = make_double2(p0.x + q0.x, p0.y + q0.y);
+  B[i1] = make_double2(p1.x + q1.x, p1.y + q1.y);
+}
+
+hipError_t launch_init64(const InitArgs& a, hipStream_t s) {
+  if (a.m0 - 1 > 64 || a.h < 1) return hipErrorInvalidValue;
+  const long long blocks = (((long long)a.n_batches << a.h) + kBlock - 1) / kBlock;
+  if (blocks > 0x7fffffffLL || blocks < 1) return hipErrorInvalidValue;
+  InitArgs b = a;
+  return hipLaunchKernel(reinterpret_cast<const void*>(&k_init64), dim3((unsigned)blocks), dim3(kBlock),
+                         std::array<void*, 1>{&b}.data(), 0, s);
+}
+
+hipError_t launch_op64(const Op64Args& a, hipStream_t s) {
+  if (a.h < 1) return hipErrorInvalidValue;
+  const long long blocks = (((long long)a.n_batches << (a.h - 1)) + kBlock - 1) / kBlock;
+  if (blocks > 0x7fffffffLL || blocks < 1) return hipErrorInvalidValue;
+  Op64Args b = a;
+  return hipLaunchKernel(reinterpret_cast<const void*>(&k_op64), dim3((unsigned)blocks), dim3(kBlock),
+                         std::array<void*, 1>{&b}.data(), 0, s);
 }
 
 // ---------------------------------------------------------------------------

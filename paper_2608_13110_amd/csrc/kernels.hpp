@@ -183,43 +183,12 @@ constexpr int kMaxThreadBitsDev = 9;
 
 #if defined(__HIP_DEVICE_COMPILE__)
 typedef float tnc_floatx4 __attribute__((ext_vector_type(4)));
-
-// Matrix-core form of op_reg: v_mfma_f32_4x4x1_16b_f32 computes, for each
-// block of 4 lanes, D[i][j] += A[i] * B[j] with A from lane 4b+i and B from
-// lane 4b+j.  With A = row (lane % 4) of the real 4x4 M and B = one real
-// component of the lane's own pair, four accumulating steps leave M x in the
-// lane's four accumulators: every lane transforms its own pair, no padding.
-// All four lanes of a block must use the same M (same tile, same control).
-template <int R, int A, int C>
-__device__ __attribute__((always_inline)) inline Regs<R> op_reg_mfma(Regs<R> v, const float4 r0, const float4 r1) {
-#pragma unroll
-  for (int i = 0; i < (1 << R); ++i) {
-    if (i & (1 << A)) continue;
-    const int j = i | (1 << A);
-    const float4 r = ((i >> C) & 1) ? r1 : r0;
-    tnc_floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(r.x, v.x[i], acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(r.y, v.y[i], acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(r.z, v.x[j], acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(r.w, v.y[j], acc, 0, 0, 0);
-    v.x[i] = acc[0];
-    v.y[i] = acc[1];
-    v.x[j] = acc[2];
-    v.y[j] = acc[3];
-  }
-  return v;
-}
-
 #endif
 
-template <int R, bool MF>
+template <int R>
 struct PhaseCtx {
   const TNC_TBL float* __restrict__ rm;  // the tile's batch: resolved matrices, 16 floats per op
-  const float4* __restrict__ rmr;         // the same in matrix-core rows, 8 float4 per op
-  const uint8_t* bits;  // output bits, one byte per qubit per batch
-  size_t xpos;          // byte offset of this tile's batch in `bits`
   uint32_t tb;
-  int lane;
   bool uniform;
 };
 
@@ -250,18 +219,11 @@ TNC_HD inline float uniform_value(float x) {
 }
 
 // Ops 1..N-1 of a canonical phase: op b on register bit b controlled by b-1.
-template <int R, int B, int N, bool MF>
-TNC_HD inline Regs<R> stair_rest(Regs<R> v, const PhaseCtx<R, MF>& c, int op_begin) {
+template <int R, int B, int N>
+TNC_HD inline Regs<R> stair_rest(Regs<R> v, const PhaseCtx<R>& c, int op_begin) {
   if constexpr (B < N) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    if constexpr (MF) {
-      const float4* rows = c.rmr + (size_t)(op_begin + B) * 8;
-      v = op_reg_mfma<R, B, B - 1>(v, rows[c.lane & 3], rows[4 + (c.lane & 3)]);
-      return stair_rest<R, B + 1, N, MF>(v, c, op_begin);
-    }
-#endif
     v = op_reg<R, B, B - 1>(v, c.rm + (size_t)(op_begin + B) * 16);
-    return stair_rest<R, B + 1, N, MF>(v, c, op_begin);
+    return stair_rest<R, B + 1, N>(v, c, op_begin);
   }
   return v;
 }
@@ -270,8 +232,8 @@ TNC_HD inline Regs<R> stair_rest(Regs<R> v, const PhaseCtx<R, MF>& c, int op_beg
 // form of op 0: 0 a duplication, 1 an update with no control, 2 an update
 // controlled by a thread bit (cloc0).  Each form is its own code path, so no
 // register values merge across forms.
-template <int R, int N, bool MF, int K0>
-TNC_HD inline Regs<R> stair(Regs<R> v, const DevPhase& P, const PhaseCtx<R, MF>& c) {
+template <int R, int N, int K0>
+TNC_HD inline Regs<R> stair(Regs<R> v, const DevPhase& P, const PhaseCtx<R>& c) {
   if constexpr (K0 == 0) {
     v = op_dup<R, 0>(v);
   } else {
@@ -300,7 +262,7 @@ TNC_HD inline Regs<R> stair(Regs<R> v, const DevPhase& P, const PhaseCtx<R, MF>&
       }
     }
   }
-  return stair_rest<R, 1, N, MF>(v, c, P.op_begin);
+  return stair_rest<R, 1, N>(v, c, P.op_begin);
 }
 
 // One register phase: LDS -> registers (phase layout), the phase's ops,
@@ -309,14 +271,14 @@ TNC_HD inline Regs<R> stair(Regs<R> v, const DevPhase& P, const PhaseCtx<R, MF>&
 // the tile's own (rbase = 0 or a multiple of 2^(T+3)), so an entry's byte
 // offset is rbase | (swz(thread bits) << 3) ^ po[i].  po[i] (from the pass
 // tables) is swz(r_i) << 3 for the tile index r_i of register entry i.
-template <int R, int N, bool MF, int K0>
+template <int R, int N, int K0>
 TNC_HD inline void phase_exec(char* base, uint32_t rbase, const DevPhase& P, const TNC_TBL uint32_t* po,
-                              const PhaseCtx<R, MF>& c0, uint32_t tt, uint32_t tmask) {
+                              const PhaseCtx<R>& c0, uint32_t tt, uint32_t tmask) {
   constexpr int E = 1 << R;
   uint32_t rmask = 0;
 #pragma unroll
   for (int b = 0; b < R; ++b) rmask |= 1u << P.reg[b];
-  PhaseCtx<R, MF> c = c0;
+  PhaseCtx<R> c = c0;
   c.tb = pdep32(tt, tmask & ~rmask);
   const uint32_t vbase = rbase | (swz(c.tb) << 3);
   uint32_t off[E];
@@ -329,17 +291,17 @@ TNC_HD inline void phase_exec(char* base, uint32_t rbase, const DevPhase& P, con
     v.x[i] = t.x;
     v.y[i] = t.y;
   }
-  v = stair<R, N, MF, K0>(v, P, c);
+  v = stair<R, N, K0>(v, P, c);
 #pragma unroll
   for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(base + off[i]) = make_float2(v.x[i], v.y[i]);
 }
 
-template <int R, int N, bool MF>
+template <int R, int N>
 TNC_HD inline void phase_forms(char* base, uint32_t rbase, const DevPhase& P, const TNC_TBL uint32_t* po,
-                               const PhaseCtx<R, MF>& c, uint32_t tt, uint32_t tmask) {
-  if (P.first_dup) phase_exec<R, N, MF, 0>(base, rbase, P, po, c, tt, tmask);
-  else if (P.cloc0 < 0) phase_exec<R, N, MF, 1>(base, rbase, P, po, c, tt, tmask);
-  else phase_exec<R, N, MF, 2>(base, rbase, P, po, c, tt, tmask);
+                               const PhaseCtx<R>& c, uint32_t tt, uint32_t tmask) {
+  if (P.first_dup) phase_exec<R, N, 0>(base, rbase, P, po, c, tt, tmask);
+  else if (P.cloc0 < 0) phase_exec<R, N, 1>(base, rbase, P, po, c, tt, tmask);
+  else phase_exec<R, N, 2>(base, rbase, P, po, c, tt, tmask);
 }
 
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -355,10 +317,10 @@ TNC_HD inline void phase_forms(char* base, uint32_t rbase, const DevPhase& P, co
 // tpos[t], whose LDS offset is po[kPhaseEntries + t].  Updates 3..N-1 then
 // go on on the vector ALUs: update 3 on register bit 1 under lane bit 5
 // (b2), update b > 3 on register bit b - 2 under register bit b - 3.
-template <int R, int N, bool MF>
+template <int R, int N>
 __device__ __attribute__((always_inline)) inline void phase_tri(char* base, uint32_t rbase, const DevPhase& P,
                                                                 const TNC_TBL uint32_t* po, const float4* __restrict__ F,
-                                                                const PhaseCtx<R, MF>& c, uint32_t tt, int TB) {
+                                                                const PhaseCtx<R>& c, uint32_t tt, int TB) {
   constexpr int E = 1 << R;
   constexpr int G = E / 2;
   const int lane = (int)(tt & 63u);
@@ -418,35 +380,42 @@ __device__ __attribute__((always_inline)) inline void phase_tri(char* base, uint
 }
 #endif
 
+// Register phases with an instantiated form: a canonical phase of 1..R
+// updates, or (fused phases) 3..R+2 updates; the planner checks every phase
+// against this before the tables reach the device.
+TNC_HD constexpr bool phase_form_exists(int R, int n_ops, bool fused) {
+  return fused ? (R >= 3 && n_ops >= 3 && n_ops <= R + 2 && n_ops <= 7) : (n_ops >= 1 && n_ops <= R && R <= 5);
+}
+
 // TRI: the kernel runs fused phases (P.pad = 1); the host plans them only for
 // kernels whose waves each lie inside one tile.
-template <int R, bool MF, bool TRI = false>
+template <int R, bool TRI = false>
 TNC_HD inline void phase_dispatch(char* base, uint32_t rbase, const DevPhase& P, const TNC_TBL uint32_t* po,
-                                  const PhaseCtx<R, MF>& c, uint32_t tt, uint32_t tmask, const float4* fm = nullptr,
+                                  const PhaseCtx<R>& c, uint32_t tt, uint32_t tmask, const float4* fm = nullptr,
                                   int TB = 0) {
 #if defined(__HIP_DEVICE_COMPILE__)
   if constexpr (TRI && R >= 3) {
     if (P.pad) {
       // update b > 2 targets register bit b - 2: up to R + 2 updates
       switch (P.n_ops) {
-        case 3: phase_tri<R, 3, MF>(base, rbase, P, po, fm, c, tt, TB); break;
-        case 4: phase_tri<R, 4, MF>(base, rbase, P, po, fm, c, tt, TB); break;
-        case 5: phase_tri<R, 5, MF>(base, rbase, P, po, fm, c, tt, TB); break;
-        case 6: if constexpr (R >= 4) phase_tri<R, 6, MF>(base, rbase, P, po, fm, c, tt, TB); break;
-        case 7: if constexpr (R >= 5) phase_tri<R, 7, MF>(base, rbase, P, po, fm, c, tt, TB); break;
-        default: break;
+        case 3: phase_tri<R, 3>(base, rbase, P, po, fm, c, tt, TB); break;
+        case 4: phase_tri<R, 4>(base, rbase, P, po, fm, c, tt, TB); break;
+        case 5: phase_tri<R, 5>(base, rbase, P, po, fm, c, tt, TB); break;
+        case 6: if constexpr (R >= 4) phase_tri<R, 6>(base, rbase, P, po, fm, c, tt, TB); break;
+        case 7: if constexpr (R >= 5) phase_tri<R, 7>(base, rbase, P, po, fm, c, tt, TB); break;
+        default: break;  // excluded on the host (phase_form_exists)
       }
       return;
     }
   }
 #endif
   switch (P.n_ops) {
-    case 1: phase_forms<R, 1, MF>(base, rbase, P, po, c, tt, tmask); break;
-    case 2: if constexpr (R >= 2) phase_forms<R, 2, MF>(base, rbase, P, po, c, tt, tmask); break;
-    case 3: if constexpr (R >= 3) phase_forms<R, 3, MF>(base, rbase, P, po, c, tt, tmask); break;
-    case 4: if constexpr (R >= 4) phase_forms<R, 4, MF>(base, rbase, P, po, c, tt, tmask); break;
-    case 5: if constexpr (R >= 5) phase_forms<R, 5, MF>(base, rbase, P, po, c, tt, tmask); break;
-    default: break;
+    case 1: phase_forms<R, 1>(base, rbase, P, po, c, tt, tmask); break;
+    case 2: if constexpr (R >= 2) phase_forms<R, 2>(base, rbase, P, po, c, tt, tmask); break;
+    case 3: if constexpr (R >= 3) phase_forms<R, 3>(base, rbase, P, po, c, tt, tmask); break;
+    case 4: if constexpr (R >= 4) phase_forms<R, 4>(base, rbase, P, po, c, tt, tmask); break;
+    case 5: if constexpr (R >= 5) phase_forms<R, 5>(base, rbase, P, po, c, tt, tmask); break;
+    default: break;  // excluded on the host (phase_form_exists)
   }
 }
 
@@ -460,13 +429,61 @@ TNC_HD inline uint32_t phase_entry_offset(const DevPhase& P, int R, int i) {
   return swz(r) << 3;
 }
 
-// Launchers (kernels.hip).
-hipError_t launch_init(const InitArgs& a, hipStream_t s);
-hipError_t launch_init16(const InitArgs& a, hipStream_t s);
-hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s);
-hipError_t launch_pass(const PassArgs& a, int R, hipStream_t s);
-hipError_t launch_late(const LateArgs& a, bool in_c64, hipStream_t s);
-hipError_t launch_late_ops(const LateOpsArgs& a, hipStream_t s);
+// ---------------------------------------------------------------------------
+// Launch records.  A kernel launch of the amplitude path is recorded first:
+// the kernel, its grid and block, its LDS size and a copy of its single
+// by-value argument.  A record is then issued on a stream (issue), added to a
+// HIP graph as a kernel node (graph_add; no stream capture involved), or
+// merged with records of the same kernel for other requests into one grouped
+// launch (issue_grouped): the grouped entry point gfn runs segment blockIdx.z
+// of a device table of segments, each the argument and grid of one record.
+constexpr int kMaxArgBytes = 256;
+constexpr int kSegHeader = 16;
+
+template <class A>
+struct Seg {
+  uint32_t gx, gy;  // the record's own grid; blocks of a grouped launch outside it return
+  uint32_t pad[2];
+  A a;
+};
+
+struct Launch {
+  const void* fn = nullptr;   // the kernel
+  const void* gfn = nullptr;  // its grouped entry point (null: never grouped)
+  dim3 grid{1, 1, 1}, block{1, 1, 1};
+  uint32_t shmem = 0;
+  uint32_t arg_bytes = 0;
+  uint32_t seg_stride = 0;    // bytes of one segment of the grouped entry's table
+  int cls = 0;                // profiling class: 0 build-up and resolution, 1 pass, 2 late phase
+  double bytes = 0.0;         // algorithmic bytes (passes)
+  alignas(16) unsigned char arg[kMaxArgBytes] = {};
+};
+
+// Record builders (kernels.hip); hipErrorInvalidValue for a shape the
+// kernels do not take.
+hipError_t record_init(const InitArgs& a, Launch* L);
+hipError_t record_resolve(const ResolveArgs& a, Launch* L);
+hipError_t record_pass(const PassArgs& a, int R, Launch* L);
+hipError_t record_late(const LateArgs& a, bool in_c64, Launch* L);
+hipError_t record_late_ops(const LateOpsArgs& a, Launch* L);
+
+hipError_t issue(const Launch& L, hipStream_t s);
+hipError_t graph_add(const Launch& L, hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* dep, size_t n_dep);
+// Records of the same kernel with a grouped entry point and the same block.
+bool groupable(const Launch& a, const Launch& b);
+// Segment table of n groupable records, written to host memory at dst (n *
+// seg_stride bytes); returns the bytes written.
+size_t write_segments(const Launch* const* members, int n, unsigned char* dst);
+// One launch running every member; d_segs: the segment table in device
+// memory (kept valid until the launch has run).
+hipError_t issue_grouped(const Launch* const* members, int n, const void* d_segs, hipStream_t s);
+
+// The complex128 reference sweep (tests): row-0 build-up stored in FP64
+// (a.B holds double2 entries) and one unfused update per launch.
+hipError_t launch_init64(const InitArgs& a, hipStream_t s);
+hipError_t launch_op64(const Op64Args& a, hipStream_t s);
+
+// Launchers of the kernels outside the amplitude path (kernels.hip).
 hipError_t launch_fill_zero(double2* out, long long count, hipStream_t s);
 hipError_t launch_accumulate(double2* out, const double2* in, long long count, hipStream_t s);
 // Batched sampling handles up to 2^10 suffixes per batch: 4 per thread.

@@ -128,9 +128,8 @@ struct Options {
   int max_tile_bits = 13;   // tile of one pass: 2^max_tile_bits entries
   int reg_bits = 5;         // entries per thread = 2^reg_bits
   int low_bits = 4;         // contiguous low slots kept in every non-bottom tile
-  int math = 0;             // 0: vector ALU updates; 1: register-controlled updates on the matrix cores;
-                            // 2: runs of three updates fused into 8x8 products on the matrix cores
-  int pipeline = 0;         // 1: persistent, prefetching pass blocks where a block holds one tile
+  int math = 0;             // 0: vector ALU updates; 2: runs of three updates fused into 8x8 products
+                            // on the matrix cores
   int late_fold = 0;        // removals folded into the join launch (0 auto, -1 none, 1..8)
   int reg_adapt = 0;        // 1: a pass uses reg_bits - 1 when that needs no more phases; 0: never
 };

@@ -1,4 +1,4 @@
-// Ring geometry by structure-aware slicing (Sec. 7): the CZ gates of the
+// Ring geometry by structure-aware slicing (Sec. 6.3): the CZ gates of the
 // wrap pair (n-1, 0) are cut, CZ = sum_a P_a (x) Z^a with P_a = |a><a| on
 // qubit n-1 and Z^a on qubit 0.  Each of the 2^m assignments of the m cut
 // bonds is an open-chain circuit (its P_a, Z^a factors folded into the

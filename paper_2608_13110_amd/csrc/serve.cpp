@@ -8,12 +8,19 @@
 // device arena has room for their footprint (tensor workspace, bits,
 // output), so requests that arrive while others run start as soon as a
 // stream and memory free up, and the work of different requests overlaps on
-// the device.  Small requests (boundary bits <= small_bits) run as captured
-// HIP graphs; each cached graph owns its device region (workspace, bits,
-// output), so it is replayed from any stream whenever the same plan, k and
-// batch count come back and the graph is not already running.  Batches of a
-// plan share only the read-only plan (Sec. 5.3: the batches of one circuit
-// differ only in their output bits).
+// the device.
+//
+// Small requests (boundary bits <= small_bits) run together: the ready
+// complex64 requests of one width are taken as a group (up to max_group),
+// their launches are recorded, and the k-th launches of all members that use
+// the same kernel become one grouped launch (its segments are the members'
+// own arguments; kernels.hpp).  A small request whose (plan, k, batches,
+// storage) comes back runs as a cached HIP graph: built once, node by node,
+// from its launch records (no stream capture), with its own device region,
+// and replayed from any stream while idle.  No stream is ever put in capture
+// mode, so the server never constrains what other threads do on the device.
+// Batches of a plan share only the read-only plan (Sec. 5.2: the batches of
+// one circuit differ only in their output bits).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,11 +37,10 @@
 #include <unordered_map>
 #include <vector>
 
+#include "exec.hpp"
 #include "tnc.h"
 
 namespace tnc {
-
-int set_error_message(int code, const std::string& msg);  // tnc_api.cpp
 
 namespace {
 
@@ -112,7 +118,6 @@ struct CircuitKey {
 struct CachedPlan {
   CircuitKey key;
   tnc_plan_t plan = nullptr;
-  int h = 0;
   int ready = 0;  // 0 building, 1 ready, -1 failed
   int rc = 0;
 };
@@ -129,12 +134,13 @@ struct Request {
   tnc_c128* out = nullptr;
   uint64_t ws_bytes = 0, footprint = 0;
   int h = 0;
+  int n_launches = 0;  // launches of one batch group (bounds its segment table)
   int state = R_PLANNING;
   int rc = 0;
   std::string err;  // what failed, for tnc_last_error of the waiting thread
   int bypassed = 0;
   bool small = false;
-  bool graph_used = false;
+  int mode = 0;  // how it ran: 0 plain, 1 graph replay, 2 in a group of several
   int64_t t_submit = 0, t_ready = 0, t_admit = 0, t_done = 0;
 };
 
@@ -142,18 +148,18 @@ struct GraphEntry {
   hipGraphExec_t exec = nullptr;
   uint64_t off = 0;  // its own arena block: workspace, bits, output
   bool busy = false;
-  bool failed = false;  // capture did not work: run plainly from the region
 };
 
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  std::shared_ptr<Request> req;
-  uint64_t off = UINT64_MAX;      // arena block of a request run without a graph
-  GraphEntry* graph = nullptr;    // or the graph it replays
-  uint8_t* h_bits = nullptr;      // pinned staging
-  tnc_c128* h_out = nullptr;
-  size_t cap_bits = 0, cap_out = 0;
+  std::vector<std::shared_ptr<Request>> reqs;  // one request, or the members of a group
+  std::vector<size_t> out_at;                  // per member: first amplitude in h_out
+  uint64_t off = UINT64_MAX;                   // arena block (plain request or group)
+  GraphEntry* graph = nullptr;                 // or the cached graph it replays
+  unsigned char* h_in = nullptr;               // pinned staging: segment tables and bits
+  tnc_c128* h_out = nullptr;                   // pinned staging: amplitudes
+  size_t cap_in = 0, cap_out = 0;
 };
 
 struct GraphKey {
@@ -163,6 +169,8 @@ struct GraphKey {
     return std::tie(plan, k, nb, storage) < std::tie(o.plan, o.k, o.nb, o.storage);
   }
 };
+
+uint64_t up256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 }  // namespace
 
@@ -176,22 +184,20 @@ struct ServerImpl {
   std::map<int, tnc_options> tuning;  // boundary bits -> tile options
 
   std::mutex mu;
-  // held around table uploads (planners) and around graph capture
-  // (dispatcher): no allocation or blocking copy runs while a capture is open
-  std::mutex dev_mu;
   std::condition_variable cv_plan, cv_dispatch, cv_done;
   std::deque<std::shared_ptr<Request>> to_plan, ready;
   std::unordered_map<uint64_t, std::shared_ptr<Request>> reqs;
   std::unordered_multimap<uint64_t, std::shared_ptr<CachedPlan>> plans;
   std::map<GraphKey, std::unique_ptr<GraphEntry>> graphs;
+  std::map<GraphKey, int> seen;  // small requests met per key (a graph is built on the second)
   uint64_t next_id = 1;
   bool stop = false;
   std::vector<std::thread> planners;
   std::thread dispatcher;
 
   // statistics
-  uint64_t n_done = 0, n_graph_launch = 0, n_graph_capture = 0, n_capture_failed = 0, n_plain = 0, plan_hits = 0,
-           plan_misses = 0;
+  uint64_t n_done = 0, n_graph_launch = 0, n_graph_build = 0, n_graph_failed = 0, n_plain = 0, n_groups = 0,
+           n_grouped_reqs = 0, n_grouped_launches = 0, plan_hits = 0, plan_misses = 0;
   int64_t first_submit = 0, last_done = 0;
   std::vector<double> lat_ms;
   int max_inflight = 0;
@@ -205,8 +211,11 @@ struct ServerImpl {
 
   void planner_loop();
   void dispatcher_loop();
-  int launch(Slot& s, Request& r, uint64_t base, GraphEntry* g);
-  bool place(Slot& s, Request& r, uint64_t* base, GraphEntry** g);
+  int run_plain(Slot& s, Request& r);
+  int run_graph(Slot& s, Request& r, GraphEntry* g);
+  int run_group(Slot& s);
+  bool admit(Slot& s, std::deque<std::shared_ptr<Request>>::iterator it);
+  bool holding(const Request& r, int64_t now) const;
   void finish(Slot& s, bool ok);
 };
 
@@ -214,12 +223,12 @@ namespace {
 
 int ceil_half(int d) { return (d + 1) / 2; }
 
-void ensure_pinned(Slot& s, size_t bits, size_t outs) {
-  if (bits > s.cap_bits) {
-    if (s.h_bits) (void)hipHostFree(s.h_bits);
-    s.h_bits = nullptr;
-    s.cap_bits = 0;
-    if (hipHostMalloc((void**)&s.h_bits, bits) == hipSuccess) s.cap_bits = bits;
+bool ensure_pinned(Slot& s, size_t in_bytes, size_t outs) {
+  if (in_bytes > s.cap_in) {
+    if (s.h_in) (void)hipHostFree(s.h_in);
+    s.h_in = nullptr;
+    s.cap_in = 0;
+    if (hipHostMalloc((void**)&s.h_in, in_bytes) == hipSuccess) s.cap_in = in_bytes;
   }
   if (outs > s.cap_out) {
     if (s.h_out) (void)hipHostFree(s.h_out);
@@ -227,6 +236,27 @@ void ensure_pinned(Slot& s, size_t bits, size_t outs) {
     s.cap_out = 0;
     if (hipHostMalloc((void**)&s.h_out, outs * sizeof(tnc_c128)) == hipSuccess) s.cap_out = outs;
   }
+  return s.cap_in >= in_bytes && s.cap_out >= outs;
+}
+
+int fail_req(Request& r, int code, const std::string& what, hipError_t e) {
+  r.err = "serving: " + what + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string()) +
+          (code != TNC_OK && e == hipSuccess ? std::string(": ") + tnc_last_error() : std::string());
+  return code;
+}
+
+// Device layout of one request inside its block: workspace, bits, output.
+struct ReqLayout {
+  uint64_t ws = 0, bits = 0, out = 0, total = 0;
+};
+
+ReqLayout req_layout(const Request& r) {
+  ReqLayout L;
+  L.ws = 0;
+  L.bits = up256(r.ws_bytes);
+  L.out = L.bits + up256((uint64_t)r.nb * r.circuit.n);
+  L.total = L.out + up256(((uint64_t)r.nb << r.k) * sizeof(tnc_c128));
+  return L;
 }
 
 }  // namespace
@@ -263,7 +293,11 @@ void ServerImpl::planner_loop() {
     int rc = 0;
     if (build) {
       tnc_plan_t p = nullptr;
-      const tnc_options o = options_for(ceil_half(r->circuit.d));
+      tnc_options o;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        o = options_for(ceil_half(r->circuit.d));
+      }
       rc = tnc_plan(r->circuit.n, r->circuit.d, r->circuit.one.data(), (int32_t)r->circuit.gates.size(),
                     r->circuit.gates.data(), &o, &p);
       std::lock_guard<std::mutex> lk(mu);
@@ -279,10 +313,7 @@ void ServerImpl::planner_loop() {
     tnc_info info{};
     uint64_t ws = 0;
     if (!rc) rc = tnc_plan_info(cp->plan, r->k, &info);
-    if (!rc) {
-      std::lock_guard<std::mutex> dk(dev_mu);
-      rc = tnc_prepare(cp->plan, r->k);
-    }
+    if (!rc) rc = tnc_prepare(cp->plan, r->k);
     if (!rc) rc = tnc_workspace_bytes(cp->plan, r->k, r->nb, r->storage, &ws);
     const std::string perr = rc ? std::string("serving: planning: ") + tnc_last_error() : std::string();
     std::lock_guard<std::mutex> lk(mu);
@@ -291,9 +322,8 @@ void ServerImpl::planner_loop() {
     r->rc = rc;
     r->h = info.boundary_bits;
     r->ws_bytes = ws;
-    const uint64_t io = (((uint64_t)r->nb * r->circuit.n + 255) & ~uint64_t(255)) +
-                        (((uint64_t)r->nb << r->k) * sizeof(tnc_c128) + 255) / 256 * 256;
-    r->footprint = ws + io;
+    r->n_launches = 2 + info.n_passes + info.n_late_launches;
+    r->footprint = req_layout(*r).total;
     r->small = opt.small_bits > 0 && r->h <= opt.small_bits;
     r->t_ready = now_ns();
     if (rc) {
@@ -308,109 +338,278 @@ void ServerImpl::planner_loop() {
   }
 }
 
-// Runs request r on slot s from the arena block at `base`, either by
-// replaying (or first capturing) graph g, or by plain launches (g null).
-int ServerImpl::launch(Slot& s, Request& r, uint64_t base, GraphEntry* g) {
-  auto fail = [&](int code, const char* what, hipError_t e) {
-    r.err = std::string("serving: ") + what + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : "") +
-            (code != TNC_OK && e == hipSuccess ? std::string(": ") + tnc_last_error() : std::string());
-    return code;
-  };
+// A request on its own, from the arena block at s.off.
+int ServerImpl::run_plain(Slot& s, Request& r) {
+  const ReqLayout L = req_layout(r);
   const size_t nbits = (size_t)r.nb * r.circuit.n, nout = (size_t)r.nb << r.k;
-  ensure_pinned(s, nbits, nout);
-  if (s.cap_bits < nbits || s.cap_out < nout) return fail(TNC_E_NOMEM, "pinned staging allocation", hipSuccess);
-  char* ws = arena_base + base;
-  uint8_t* d_bits = reinterpret_cast<uint8_t*>(ws + r.ws_bytes);
-  tnc_c128* d_out = reinterpret_cast<tnc_c128*>(ws + r.ws_bytes + (((uint64_t)nbits + 255) & ~uint64_t(255)));
-  std::memcpy(s.h_bits, r.bits.data(), nbits);
-  hipError_t e = hipMemcpyAsync(d_bits, s.h_bits, nbits, hipMemcpyHostToDevice, s.stream);
-  if (e != hipSuccess) return fail(TNC_E_DEVICE, "bits upload", e);
-  if (g && !g->exec && !g->failed) {
-    // capture once; a capture that does not work leaves the region to plain
-    // launches (the stream leaves capture mode either way)
-    std::lock_guard<std::mutex> dk(dev_mu);
+  if (!ensure_pinned(s, nbits, nout)) return fail_req(r, TNC_E_NOMEM, "pinned staging allocation", hipSuccess);
+  char* base = arena_base + s.off;
+  uint8_t* d_bits = reinterpret_cast<uint8_t*>(base + L.bits);
+  tnc_c128* d_out = reinterpret_cast<tnc_c128*>(base + L.out);
+  std::memcpy(s.h_in, r.bits.data(), nbits);
+  hipError_t e = hipMemcpyAsync(d_bits, s.h_in, nbits, hipMemcpyHostToDevice, s.stream);
+  if (e != hipSuccess) return fail_req(r, TNC_E_DEVICE, "bits upload", e);
+  const int rc = tnc_amplitudes(r.cp->plan, r.nb, d_bits, r.k, r.storage, d_out, base + L.ws, r.ws_bytes, s.stream);
+  if (rc) return fail_req(r, rc, "launch sequence", hipSuccess);
+  e = hipMemcpyAsync(s.h_out, d_out, nout * sizeof(tnc_c128), hipMemcpyDeviceToHost, s.stream);
+  if (e != hipSuccess) return fail_req(r, TNC_E_DEVICE, "result download", e);
+  s.out_at.assign(1, 0);
+  ++n_plain;
+  return TNC_OK;
+}
+
+// A small request through its cached graph (built on first use from the
+// launch records of its own region, node after node, without capture).
+int ServerImpl::run_graph(Slot& s, Request& r, GraphEntry* g) {
+  const ReqLayout L = req_layout(r);
+  const size_t nbits = (size_t)r.nb * r.circuit.n, nout = (size_t)r.nb << r.k;
+  if (!ensure_pinned(s, nbits, nout)) return fail_req(r, TNC_E_NOMEM, "pinned staging allocation", hipSuccess);
+  char* base = arena_base + g->off;
+  uint8_t* d_bits = reinterpret_cast<uint8_t*>(base + L.bits);
+  tnc_c128* d_out = reinterpret_cast<tnc_c128*>(base + L.out);
+  if (!g->exec) {
+    std::vector<Launch> ls;
+    int rc = record_amplitudes(r.cp->plan, r.nb, d_bits, r.k, r.storage, d_out, base + L.ws, r.ws_bytes, &ls);
+    if (rc) return fail_req(r, rc, "launch records", hipSuccess);
     hipGraph_t graph = nullptr;
-    if (hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-      const int rc = tnc_amplitudes(r.cp->plan, r.nb, d_bits, r.k, r.storage, d_out, ws, r.ws_bytes, s.stream);
-      const hipError_t e2 = hipStreamEndCapture(s.stream, &graph);
-      if (rc == TNC_OK && e2 == hipSuccess && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) == hipSuccess)
-        ++n_graph_capture;
-      else
-        g->exec = nullptr;
-      if (graph) (void)hipGraphDestroy(graph);
+    hipError_t e = hipGraphCreate(&graph, 0);
+    hipGraphNode_t prev = nullptr;
+    for (size_t i = 0; e == hipSuccess && i < ls.size(); ++i) {
+      hipGraphNode_t node = nullptr;
+      e = graph_add(ls[i], graph, &node, prev ? &prev : nullptr, prev ? 1 : 0);
+      prev = node;
     }
-    (void)hipGetLastError();
-    if (!g->exec) {
-      g->failed = true;
-      ++n_capture_failed;
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      g->exec = nullptr;
+      ++n_graph_failed;
+      return fail_req(r, TNC_E_DEVICE, "graph build", e);
+    }
+    ++n_graph_build;
+  }
+  std::memcpy(s.h_in, r.bits.data(), nbits);
+  hipError_t e = hipMemcpyAsync(d_bits, s.h_in, nbits, hipMemcpyHostToDevice, s.stream);
+  if (e != hipSuccess) return fail_req(r, TNC_E_DEVICE, "bits upload", e);
+  e = hipGraphLaunch(g->exec, s.stream);
+  if (e != hipSuccess) return fail_req(r, TNC_E_DEVICE, "graph launch", e);
+  e = hipMemcpyAsync(s.h_out, d_out, nout * sizeof(tnc_c128), hipMemcpyDeviceToHost, s.stream);
+  if (e != hipSuccess) return fail_req(r, TNC_E_DEVICE, "result download", e);
+  s.out_at.assign(1, 0);
+  ++n_graph_launch;
+  return TNC_OK;
+}
+
+// The members of s.reqs (small complex64 requests of one width) together,
+// from the arena block at s.off laid out as [segment tables | bits of every
+// member | outputs of every member | workspaces].  Launch i of every member
+// that uses the same kernel as the others' launch i runs in one grouped
+// launch; the segment tables and the bits go up in one copy, the outputs
+// come back in one copy.
+int ServerImpl::run_group(Slot& s) {
+  const size_t m = s.reqs.size();
+  Request& r0 = *s.reqs[0];
+  uint64_t seg_bytes = 0, bits_bytes = 0, out_amps = 0, ws_total = 0;
+  for (auto& rp : s.reqs) {
+    seg_bytes += (uint64_t)rp->n_launches * (kSegHeader + kMaxArgBytes);
+    bits_bytes += up256((uint64_t)rp->nb * rp->circuit.n);
+    out_amps += (uint64_t)rp->nb << rp->k;
+    ws_total += up256(rp->ws_bytes);
+  }
+  seg_bytes = up256(seg_bytes);
+  if (!ensure_pinned(s, seg_bytes + bits_bytes, out_amps))
+    return fail_req(r0, TNC_E_NOMEM, "pinned staging allocation", hipSuccess);
+  char* base = arena_base + s.off;
+  const uint64_t out_base = seg_bytes + bits_bytes;
+  uint64_t ws_at = up256(out_base + out_amps * sizeof(tnc_c128));
+  uint64_t bits_at = seg_bytes, amp_at = 0;
+  std::vector<std::vector<Launch>> ls(m);
+  s.out_at.assign(m, 0);
+  size_t longest = 0;
+  for (size_t i = 0; i < m; ++i) {
+    Request& r = *s.reqs[i];
+    const size_t nbits = (size_t)r.nb * r.circuit.n;
+    std::memcpy(s.h_in + bits_at, r.bits.data(), nbits);
+    s.out_at[i] = amp_at;
+    int rc = record_amplitudes(r.cp->plan, r.nb, reinterpret_cast<uint8_t*>(base + bits_at), r.k, r.storage,
+                               reinterpret_cast<tnc_c128*>(base + out_base) + amp_at, base + ws_at, r.ws_bytes, &ls[i]);
+    if (rc) return fail_req(r0, rc, "launch records", hipSuccess);
+    bits_at += up256(nbits);
+    amp_at += (uint64_t)r.nb << r.k;
+    ws_at += up256(r.ws_bytes);
+    longest = std::max(longest, ls[i].size());
+  }
+  // step j: the j-th launch of every member, in buckets of one kernel
+  struct Item {
+    std::vector<const Launch*> members;
+    uint64_t seg_off;
+  };
+  std::vector<Item> items;
+  uint64_t seg_at = 0;
+  for (size_t j = 0; j < longest; ++j) {
+    const size_t first = items.size();
+    for (size_t i = 0; i < m; ++i) {
+      if (j >= ls[i].size()) continue;
+      const Launch* L = &ls[i][j];
+      size_t b = first;
+      while (b < items.size() && !groupable(*items[b].members[0], *L)) ++b;
+      if (b == items.size()) items.push_back(Item{{}, 0});
+      items[b].members.push_back(L);
+    }
+    for (size_t b = first; b < items.size(); ++b) {
+      Item& it = items[b];
+      if (it.members.size() < 2) continue;
+      const uint64_t need = (uint64_t)it.members.size() * it.members[0]->seg_stride;
+      if (seg_at + need > seg_bytes) return fail_req(r0, TNC_E_NOMEM, "group segment tables", hipSuccess);
+      it.seg_off = seg_at;
+      write_segments(it.members.data(), (int)it.members.size(), s.h_in + seg_at);
+      seg_at = up256(seg_at + need);
     }
   }
-  if (g && g->exec) {
-    e = hipGraphLaunch(g->exec, s.stream);
-    if (e != hipSuccess) return fail(TNC_E_DEVICE, "graph launch", e);
-    ++n_graph_launch;
+  hipError_t e = hipMemcpyAsync(base, s.h_in, seg_bytes + bits_bytes, hipMemcpyHostToDevice, s.stream);
+  if (e != hipSuccess) return fail_req(r0, TNC_E_DEVICE, "segment and bits upload", e);
+  for (const Item& it : items) {
+    if (it.members.size() == 1) {
+      std::vector<Launch> one(1, *it.members[0]);
+      const int rc = issue_recorded(one, s.stream);
+      if (rc) return fail_req(r0, rc, "launch", hipSuccess);
+      continue;
+    }
+    e = issue_grouped(it.members.data(), (int)it.members.size(), base + it.seg_off, s.stream);
+    if (e != hipSuccess) return fail_req(r0, TNC_E_DEVICE, "grouped launch", e);
+    ++n_grouped_launches;
+  }
+  e = hipMemcpyAsync(s.h_out, base + out_base, out_amps * sizeof(tnc_c128), hipMemcpyDeviceToHost, s.stream);
+  if (e != hipSuccess) return fail_req(r0, TNC_E_DEVICE, "result download", e);
+  if (m > 1) {
+    ++n_groups;
+    n_grouped_reqs += m;
   } else {
-    const int rc = tnc_amplitudes(r.cp->plan, r.nb, d_bits, r.k, r.storage, d_out, ws, r.ws_bytes, s.stream);
-    if (rc) return fail(rc, "launch sequence", hipSuccess);
     ++n_plain;
   }
-  e = hipMemcpyAsync(s.h_out, d_out, nout * sizeof(tnc_c128), hipMemcpyDeviceToHost, s.stream);
-  if (e != hipSuccess) return fail(TNC_E_DEVICE, "result download", e);
-  e = hipEventRecord(s.done, s.stream);
-  if (e != hipSuccess) return fail(TNC_E_DEVICE, "completion event", e);
+  (void)ws_total;
   return TNC_OK;
 }
 
 void ServerImpl::finish(Slot& s, bool ok) {
-  Request& r = *s.req;
-  if (ok && r.out) std::memcpy(r.out, s.h_out, ((size_t)r.nb << r.k) * sizeof(tnc_c128));
+  for (size_t i = 0; i < s.reqs.size(); ++i) {
+    Request& r = *s.reqs[i];
+    if (ok && r.rc == TNC_OK && r.out && i < s.out_at.size())
+      std::memcpy(r.out, s.h_out + s.out_at[i], ((size_t)r.nb << r.k) * sizeof(tnc_c128));
+    r.t_done = now_ns();
+    r.state = R_DONE;
+    ++n_done;
+    last_done = r.t_done;
+    lat_ms.push_back((r.t_done - r.t_submit) * 1e-6);
+  }
   if (s.graph) {
     s.graph->busy = false;
     s.graph = nullptr;
   }
   if (s.off != UINT64_MAX) arena.release(s.off);
   s.off = UINT64_MAX;
-  r.t_done = now_ns();
-  r.state = R_DONE;
-  ++n_done;
-  last_done = r.t_done;
-  lat_ms.push_back((r.t_done - r.t_submit) * 1e-6);
-  s.req.reset();
+  s.reqs.clear();
+  s.out_at.clear();
 }
 
-// Memory for request r on slot s: the region of its cached graph when it
-// has one that is idle (or can get one within the graph budget), else a
-// fresh arena block.  Returns false when neither fits now.
-bool ServerImpl::place(Slot& s, Request& r, uint64_t* base, GraphEntry** g) {
-  *g = nullptr;
-  if (r.small) {
-    const GraphKey key{r.cp->plan, r.k, r.nb, r.storage};
-    auto it = graphs.find(key);
-    if (it != graphs.end() && !it->second->busy) {
-      *g = it->second.get();
-    } else if (it == graphs.end() && graphs.size() < (size_t)opt.max_graphs &&
-               graph_bytes + r.footprint <= graph_budget) {
-      const uint64_t off = arena.alloc(r.footprint);
+// Admits the ready request at `it` (and, for a small complex64 request, the
+// other ready small complex64 requests of its width) onto slot s.  Returns
+// false, changing nothing, when its memory does not fit now.
+bool ServerImpl::admit(Slot& s, std::deque<std::shared_ptr<Request>>::iterator it) {
+  std::shared_ptr<Request> r = *it;
+  s.graph = nullptr;
+  s.off = UINT64_MAX;
+  int mode = 0;
+  if (r->small) {
+    const GraphKey key{r->cp->plan, r->k, r->nb, r->storage};
+    auto g = graphs.find(key);
+    if (g != graphs.end() && !g->second->busy) {
+      s.graph = g->second.get();
+      mode = 1;
+    } else if (g == graphs.end() && seen[key] >= 1 && graphs.size() < (size_t)opt.max_graphs &&
+               graph_bytes + up256(r->footprint) <= graph_budget) {
+      const uint64_t off = arena.alloc(r->footprint);
       if (off != UINT64_MAX) {
         auto e = std::make_unique<GraphEntry>();
         e->off = off;
-        graph_bytes += (r.footprint + 255) & ~uint64_t(255);
-        *g = e.get();
+        graph_bytes += up256(r->footprint);
+        s.graph = e.get();
         graphs.emplace(key, std::move(e));
+        mode = 1;
       }
     }
-    if (*g) {
-      (*g)->busy = true;
-      s.graph = *g;
-      *base = (*g)->off;
-      return true;
-    }
+    ++seen[key];
   }
-  const uint64_t off = arena.alloc(r.footprint);
-  if (off == UINT64_MAX) return false;
-  s.off = off;
-  *base = off;
+  std::vector<std::shared_ptr<Request>> members{r};
+  if (mode == 0 && r->small && r->storage == TNC_STORE_C64 && opt.max_group > 1) {
+    for (auto jt = ready.begin(); jt != ready.end() && (int)members.size() < opt.max_group; ++jt) {
+      if (jt == it) continue;
+      const Request& q = **jt;
+      if (q.small && q.storage == TNC_STORE_C64 && q.h == r->h) {
+        const GraphKey qk{q.cp->plan, q.k, q.nb, q.storage};
+        if (graphs.count(qk)) continue;  // it has a graph of its own
+        members.push_back(*jt);
+      }
+    }
+    // the group's block; shed members until it fits
+    while (!members.empty()) {
+      uint64_t bytes = 0, seg = 0;
+      for (auto& mp : members) {
+        bytes += mp->footprint;
+        seg += (uint64_t)mp->n_launches * (kSegHeader + kMaxArgBytes);
+      }
+      const uint64_t off = arena.alloc(bytes + up256(seg) + 256);
+      if (off != UINT64_MAX) {
+        s.off = off;
+        break;
+      }
+      members.pop_back();
+    }
+    if (s.off == UINT64_MAX) return false;
+    mode = members.size() > 1 ? 2 : 0;
+  } else if (mode == 0) {
+    s.off = arena.alloc(r->footprint);
+    if (s.off == UINT64_MAX) return false;
+  }
+  if (mode == 1) s.graph->busy = true;
+  // take the members off the ready queue (r last: `it` stays valid until then)
+  for (size_t i = 1; i < members.size(); ++i) ready.erase(std::find(ready.begin(), ready.end(), members[i]));
+  ready.erase(std::find(ready.begin(), ready.end(), r));
+  s.reqs = members;
+  const int64_t t = now_ns();
+  for (auto& mp : members) {
+    mp->state = R_RUNNING;
+    mp->t_admit = t;
+    mp->mode = mode;
+  }
+  int rc;
+  if (mode == 1) rc = run_graph(s, *r, s.graph);
+  else if (mode == 2) rc = run_group(s);
+  else if (r->small && r->storage == TNC_STORE_C64 && s.off != UINT64_MAX && members.size() == 1 &&
+           opt.max_group > 1)
+    rc = run_group(s);  // a group of one: the same block layout
+  else rc = run_plain(s, *r);
+  if (rc == TNC_OK) rc = hipEventRecord(s.done, s.stream) == hipSuccess ? TNC_OK : TNC_E_DEVICE;
+  if (rc) {
+    for (auto& mp : members) {
+      mp->rc = rc;
+      if (mp->err.empty()) mp->err = r->err.empty() ? std::string("serving: launch failed") : r->err;
+    }
+    finish(s, false);
+    cv_done.notify_all();
+  }
   return true;
+}
+
+// A small complex64 request waits (up to group_window_us after it became
+// ready) for more ready requests of its width, until max_group are there.
+bool ServerImpl::holding(const Request& r, int64_t now) const {
+  if (!r.small || r.storage != TNC_STORE_C64 || opt.max_group < 2 || opt.group_window_us <= 0) return false;
+  if (now - r.t_ready >= (int64_t)opt.group_window_us * 1000) return false;
+  int same = 0;
+  for (const auto& q : ready)
+    if (q->small && q->storage == TNC_STORE_C64 && q->h == r.h) ++same;
+  return same < opt.max_group;
 }
 
 void ServerImpl::dispatcher_loop() {
@@ -421,47 +620,39 @@ void ServerImpl::dispatcher_loop() {
     // completions
     int inflight = 0;
     for (Slot& s : slots) {
-      if (!s.req) continue;
+      if (s.reqs.empty()) continue;
       const hipError_t q = hipEventQuery(s.done);
       if (q == hipErrorNotReady) {
-        (void)hipGetLastError();  // "not ready" is a status, not an error to keep
-        ++inflight;
+        inflight += (int)s.reqs.size();
         continue;
       }
-      if (q != hipSuccess) {
-        s.req->rc = TNC_E_DEVICE;
-        s.req->err = std::string("serving: request execution: ") + hipGetErrorString(q);
-      }
+      if (q != hipSuccess)
+        for (auto& rp : s.reqs) {
+          rp->rc = TNC_E_DEVICE;
+          rp->err = std::string("serving: request execution: ") + hipGetErrorString(q);
+        }
       finish(s, q == hipSuccess);
       progressed = true;
     }
     if (progressed) cv_done.notify_all();
     // admissions: oldest first; a request that does not fit lets younger
     // ones pass at most 16 times, then the queue waits for it
+    bool held = false;
+    const int64_t now = now_ns();
     for (size_t si = 0; si < slots.size() && !ready.empty(); ++si) {
       Slot& s = slots[si];
-      if (s.req) continue;
+      if (!s.reqs.empty()) continue;
       for (auto it = ready.begin(); it != ready.end(); ++it) {
         Request& r = **it;
-        uint64_t base = 0;
-        GraphEntry* g = nullptr;
-        if (!place(s, r, &base, &g)) {
+        if (holding(r, now)) {
+          held = true;
+          continue;
+        }
+        if (!admit(s, it)) {
           if (++r.bypassed > 16) break;
           continue;
         }
-        s.req = *it;
-        ready.erase(it);
-        r.state = R_RUNNING;
-        r.t_admit = now_ns();
-        const int rc = launch(s, r, base, g);
-        r.graph_used = g != nullptr && g->exec != nullptr;
-        if (rc) {
-          r.rc = rc;
-          finish(s, false);
-          cv_done.notify_all();
-        } else {
-          ++inflight;
-        }
+        inflight += (int)s.reqs.size();
         progressed = true;
         break;
       }
@@ -473,7 +664,7 @@ void ServerImpl::dispatcher_loop() {
         if (kv.second->state == R_PLANNING) planning = true;
       if (!planning) return;
     }
-    if (!progressed) cv_dispatch.wait_for(lk, std::chrono::microseconds(inflight ? 20 : 2000));
+    if (!progressed) cv_dispatch.wait_for(lk, std::chrono::microseconds(inflight ? 20 : held ? 100 : 2000));
   }
 }
 
@@ -496,7 +687,10 @@ int tnc_server_create(const tnc_server_options* opt, tnc_server_t* out) {
   if (o.n_streams <= 0) o.n_streams = 4;
   if (o.n_planners <= 0) o.n_planners = 4;
   if (o.max_graphs <= 0) o.max_graphs = 256;
-  if (o.small_bits < 0 || o.small_bits > 24 || o.n_streams > 16 || o.n_planners > 16 || o.arena_bytes == 0)
+  if (o.max_group <= 0) o.max_group = 16;
+  if (o.group_window_us < 0 || o.group_window_us > 10000000) return TNC_E_INVALID;
+  if (o.small_bits < 0 || o.small_bits > 24 || o.n_streams > 16 || o.n_planners > 16 || o.max_group > 256 ||
+      o.arena_bytes == 0)
     return TNC_E_INVALID;
   if (hipGetDevice(&S->device) != hipSuccess) return TNC_E_DEVICE;
   // cached graphs keep their regions: at most a quarter of the arena
@@ -578,7 +772,7 @@ int tnc_server_wait(tnc_server_t sv, uint64_t id, tnc_request_stats* st) {
     st->run_ms = (r->t_admit ? r->t_done - r->t_admit : 0) * 1e-6;
     st->total_ms = (r->t_done - r->t_submit) * 1e-6;
     st->boundary_bits = r->h;
-    st->graph = r->graph_used ? 1 : 0;
+    st->mode = r->mode;
   }
   const int rc = r->rc;
   if (rc) set_error_message(rc, r->err);
@@ -593,8 +787,11 @@ int tnc_server_summary(tnc_server_t sv, tnc_server_stats* st) {
   std::memset(st, 0, sizeof(*st));
   st->completed = (int64_t)S.n_done;
   st->graph_launches = (int64_t)S.n_graph_launch;
-  st->graph_captures = (int64_t)S.n_graph_capture;
-  st->capture_failures = (int64_t)S.n_capture_failed;
+  st->graph_builds = (int64_t)S.n_graph_build;
+  st->graph_failures = (int64_t)S.n_graph_failed;
+  st->groups = (int64_t)S.n_groups;
+  st->grouped_requests = (int64_t)S.n_grouped_reqs;
+  st->grouped_launches = (int64_t)S.n_grouped_launches;
   st->plain_launches = (int64_t)S.n_plain;
   st->plan_cache_hits = (int64_t)S.plan_hits;
   st->plan_cache_misses = (int64_t)S.plan_misses;
@@ -669,7 +866,7 @@ void tnc_server_destroy(tnc_server_t sv) {
     if (s.stream) (void)hipStreamSynchronize(s.stream);
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.stream) (void)hipStreamDestroy(s.stream);
-    if (s.h_bits) (void)hipHostFree(s.h_bits);
+    if (s.h_in) (void)hipHostFree(s.h_in);
     if (s.h_out) (void)hipHostFree(s.h_out);
   }
   for (auto& kv : S.plans)

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/tnc.h"
+#include "exec.hpp"
 #include "kernels.hpp"
 #include "late.hpp"
 #include "plan.hpp"
@@ -51,7 +52,6 @@ struct PassHost {
 struct HostTables {
   std::vector<DevOp> ops;
   std::vector<float> mats;
-  std::vector<float4> mrows;
   std::vector<DevPhase> phases;
   std::vector<uint32_t> poffs;  // kPhaseOffs per phase
   std::vector<float4> fmats;    // kFusedWords per phase (fused phases only; empty without them)
@@ -147,7 +147,6 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
   const size_t nops = s.ops.size();
   t->ops.resize(nops);
   t->mats.assign(nops * 4 * 16, 0.f);
-  t->mrows.assign(nops * 4 * 8, make_float4(0.f, 0.f, 0.f, 0.f));
   // fused phases: first op -> global phase index
   std::vector<int> fused_at(nops, -1);
   {
@@ -190,16 +189,6 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
       for (int c = 0; c < 2; ++c) {
         const cd r = round_matrix(op.mat[var][c], acc_op, t->mats.data() + (o * 4 + var) * 16 + c * 8);
         if (var == 0 && c == 0) step = r;
-        // real form on (re b0, im b0, re b1, im b1): rows (re o0, im o0, re o1, im o1),
-        // from the same rounded values
-        const float* f = t->mats.data() + (o * 4 + var) * 16 + c * 8;
-        for (int r = 0; r < 2; ++r) {
-          const cd k0(f[4 * r], f[4 * r + 1]), k1(f[4 * r + 2], f[4 * r + 3]);
-          t->mrows[((o * 4 + var) * 2 + c) * 4 + 2 * r] =
-              make_float4((float)k0.real(), (float)-k0.imag(), (float)k1.real(), (float)-k1.imag());
-          t->mrows[((o * 4 + var) * 2 + c) * 4 + 2 * r + 1] =
-              make_float4((float)k0.imag(), (float)k0.real(), (float)k1.imag(), (float)k1.real());
-        }
       }
     if (fused_left > 0) --fused_left;
     else acc += step;
@@ -217,14 +206,14 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
       if (err) *err = m;
       return TNC_E_INVALID;
     };
-    // 256 threads per tile (T - R = 8), or 512 with the prefetching kernel
-    if (ps.w.tile_bits() - R > (p.opt.math != 1 ? 9 : 8))
-      return fail_t("pass tile too large for the thread block");
+    // at most 512 threads per tile (T - R <= 9)
+    if (ps.w.tile_bits() - R > 9) return fail_t("pass tile too large for the thread block");
     if (!(ps.w.lo_bits >= 1 || ps.w.win_lo == 0)) return fail_t("pass tile lacks slot 0");
     for (const Phase& pp : ps.phases) {
       const int nops = pp.op_end - pp.op_begin;
-      // a fused phase holds two targets in lane bits: up to R + 2 updates
-      if (nops < 1 || nops > (pp.mf ? R + 2 : R)) return fail_t("phase size out of range");
+      // a fused phase holds two targets in lane bits: up to R + 2 updates;
+      // every phase must have an instantiated kernel form
+      if (!phase_form_exists(R, nops, pp.mf != 0)) return fail_t("phase size without a kernel form");
       DevPhase dp;
       std::memset(&dp, 0, sizeof(dp));
       dp.op_begin = pp.op_begin;
@@ -355,8 +344,8 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
 // after every writer), the batch's resolved update matrices and the two
 // late-phase buffers.
 struct BatchLayout {
-  uint64_t tensor = 0, scales = 0, rmats = 0, rmrows = 0, late0 = 0, late1 = 0;
-  uint64_t per_batch() const { return tensor + 2 * scales + rmats + rmrows + late0 + late1; }
+  uint64_t tensor = 0, scales = 0, rmats = 0, late0 = 0, late1 = 0;
+  uint64_t per_batch() const { return tensor + 2 * scales + rmats + late0 + late1; }
 };
 
 bool is_s16(int storage) { return storage == TNC_STORE_F16_BLOCKSCALE || storage == TNC_STORE_BF16_BLOCKSCALE; }
@@ -383,7 +372,6 @@ BatchLayout batch_layout(const Plan& p, const HostTables& t, int storage) {
     L.scales = align256((uint64_t)4 << (p.h - blk));
   }
   L.rmats = align256((uint64_t)t.ops.size() * 16 * sizeof(float));
-  if (p.opt.math == 1) L.rmrows = align256((uint64_t)t.ops.size() * 8 * sizeof(float4));
   L.late0 = t.bytes_late[0];
   L.late1 = t.bytes_late[1];
   return L;
@@ -396,8 +384,8 @@ int check_storage(const HostTables& t, int storage) {
   if (is_s16(storage))
     for (const PassHost& ph : t.passes) {
       if (ph.w.lo_bits == 1) return set_err(TNC_E_INVALID, "16-bit storage needs low_bits >= 2");
-      if (ph.w.tile_bits() - ph.R > 8)
-        return set_err(TNC_E_INVALID, "16-bit storage needs max_tile_bits - reg_bits <= 8");
+      if (ph.w.tile_bits() - ph.R > 9)
+        return set_err(TNC_E_INVALID, "16-bit storage needs max_tile_bits - reg_bits <= 9");
     }
   return TNC_OK;
 }
@@ -408,18 +396,20 @@ struct DevSched {
   HostTables host;
   DevOp* d_ops = nullptr;
   float* d_mats = nullptr;
-  float4* d_mrows = nullptr;
   DevPhase* d_phases = nullptr;
   uint32_t* d_poffs = nullptr;
   float4* d_fmats = nullptr;
   double2* d_seg = nullptr;
   double2* d_J = nullptr;
   LateOpDev* d_prog = nullptr;
+  // the complex128 reference sweep's updates (built on its first use)
+  std::mutex mu64;
+  Op64* d_ops64 = nullptr;
   ~DevSched() {
     int prev = 0;
     if (device >= 0 && hipGetDevice(&prev) == hipSuccess) {
       (void)hipSetDevice(device);
-      void* ptrs[] = {d_ops, d_mats, d_mrows, d_phases, d_poffs, d_fmats, d_seg, d_J, d_prog};
+      void* ptrs[] = {d_ops, d_mats, d_phases, d_poffs, d_fmats, d_seg, d_J, d_prog, d_ops64};
       for (void* q : ptrs)
         if (q) (void)hipFree(q);
       (void)hipSetDevice(prev);
@@ -475,7 +465,6 @@ int get_dev_sched(Plan& p, int k, std::shared_ptr<DevSched>* out) {
   std::vector<double2> J;
   for (const cd& z : ds->host.late.first.J) J.push_back(make_double2(z.real(), z.imag()));
   if ((rc = upload(&ds->d_ops, ds->host.ops)) || (rc = upload(&ds->d_mats, ds->host.mats)) ||
-      (rc = upload(&ds->d_mrows, ds->host.mrows)) ||
       (rc = upload(&ds->d_phases, ds->host.phases)) || (rc = upload(&ds->d_poffs, ds->host.poffs)) ||
       (rc = upload(&ds->d_fmats, ds->host.fmats)) ||
       (rc = upload(&ds->d_seg, ds->host.seg)) ||
@@ -541,18 +530,12 @@ InitArgs init_args(const Plan& p, const HostTables& t, float2* B, const uint8_t*
 }
 
 PassArgs pass_args(const Plan& p, const PassHost& ph, const DevPhase* phases, const uint32_t* poffs,
-                   const float4* fmats, const DevOp* ops, const float* mats, const float4* mrows, float2* B,
-                   const uint8_t* bits, int nb) {
+                   const float4* fmats, float2* B, const uint8_t* bits, int nb) {
   PassArgs a;
   std::memset(&a, 0, sizeof(a));
   a.phases = phases + ph.phase_off;
   a.poffs = poffs + (size_t)ph.phase_off * kPhaseOffs;
   a.fmats = fmats ? fmats + (size_t)ph.phase_off * kFusedWords : nullptr;
-  a.ops = ops;
-  a.mats = mats;
-  a.mrows = mrows;
-  a.mfma = p.opt.math == 1 ? 1 : 0;
-  a.pipeline = p.opt.pipeline;
   a.B = B;
   a.bits = bits;
   a.n_phases = ph.n_phases;
@@ -612,15 +595,14 @@ LateOpsArgs ops_args(const Plan& p, const HostTables& t, const LateOpsLaunch& ln
   return a;
 }
 
-int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k, int storage, tnc_c128* d_out,
-               void* ws, uint64_t ws_bytes, hipStream_t stream) {
+// Every launch of one amplitude call, in order, recorded with its arguments:
+// for each group of batches that fits the workspace, the row-0 build-up, the
+// variant resolution, the passes, the join and the late launches.
+int record_launches(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k, int storage, tnc_c128* d_out,
+                    void* ws, uint64_t ws_bytes, std::vector<Launch>* out) {
   const HostTables& t = ds.host;
   int rc = check_storage(t, storage);
   if (rc) return rc;
-  // each launch is checked with hipGetLastError: drop a status left on this
-  // thread by earlier calls (a hipEventQuery that returned hipErrorNotReady
-  // leaves one) so that it is not taken for a launch failure
-  (void)hipGetLastError();
   const bool s16 = is_s16(storage);
   const BatchLayout L = batch_layout(p, t, storage);
   const uint64_t per = L.per_batch();
@@ -629,6 +611,11 @@ int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k
   const int chunk = (int)std::min<uint64_t>(fit, (uint64_t)std::min(nb_total, 65535));
   char* base = static_cast<char*>(ws);
   const long long sstride = (long long)(L.scales / 4);
+  auto shape_err = [&](const char* what) {
+    return set_err(TNC_E_INVALID, std::string("launch shape out of range: ") + what);
+  };
+  out->clear();
+  Launch rec;
   for (int b0 = 0; b0 < nb_total; b0 += chunk) {
     const int nb = std::min(chunk, nb_total - b0);
     char* q = base;
@@ -639,49 +626,40 @@ int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k
     float* rmats = reinterpret_cast<float*>(q);
     const long long rstride = (long long)(L.rmats / 4);
     q += L.rmats * nb;
-    float4* rmrows = L.rmrows ? reinterpret_cast<float4*>(q) : nullptr;
-    const long long rmstride = (long long)(L.rmrows / 16);
-    q += L.rmrows * nb;
     double2* L0 = reinterpret_cast<double2*>(q);
     double2* L1 = reinterpret_cast<double2*>(q + L.late0 * nb);
     const uint8_t* bits = d_bits + (size_t)b0 * p.n;
-    double2* out = reinterpret_cast<double2*>(d_out) + ((size_t)b0 << k);
+    double2* outp = reinterpret_cast<double2*>(d_out) + ((size_t)b0 << k);
     InitArgs ia = init_args(p, t, B, bits, nb, ds.d_seg);
-    hipError_t e;
     if (s16) {
       ia.store = storage;
       ia.scale_out = sc[0];
       ia.scale_stride = sstride;
       ia.blk_bits = std::min(12, p.h);
-      e = timed(0, 0.0, stream, [&] { return launch_init16(ia, stream); });
-    } else {
-      e = timed(0, 0.0, stream, [&] { return launch_init(ia, stream); });
     }
-    if (e != hipSuccess) return hip_err(e, "init launch");
+    if (record_init(ia, &rec) != hipSuccess) return shape_err("row-0 build-up");
+    out->push_back(rec);
     ResolveArgs ra;
     std::memset(&ra, 0, sizeof(ra));
     ra.ops = ds.d_ops;
     ra.mats = ds.d_mats;
-    ra.mrows = ds.d_mrows;
     ra.bits = bits;
     ra.rmats = rmats;
     ra.rstride = rstride;
-    ra.rmrows = rmrows;
-    ra.rmstride = rmstride;
     ra.n_ops = (int)t.ops.size();
     ra.n = p.n;
     ra.n_batches = nb;
-    e = timed(0, 0.0, stream, [&] { return launch_resolve(ra, stream); });
-    if (e != hipSuccess) return hip_err(e, "resolve launch");
+    if (ra.n_ops > 0) {
+      if (record_resolve(ra, &rec) != hipSuccess) return shape_err("variant resolution");
+      out->push_back(rec);
+    }
     const double pass_bytes = 2.0 * (s16 ? 4.0 : 8.0) * (double)(1ull << p.h) * nb;
     int cur = 0;
     ScaleMap map = init_map(p);
     for (const PassHost& ph : t.passes) {
-      PassArgs a = pass_args(p, ph, ds.d_phases, ds.d_poffs, ds.d_fmats, ds.d_ops, ds.d_mats, ds.d_mrows, B, bits, nb);
+      PassArgs a = pass_args(p, ph, ds.d_phases, ds.d_poffs, ds.d_fmats, B, bits, nb);
       a.rmats = rmats;
       a.rstride = rstride;
-      a.rmrows = rmrows;
-      a.rmstride = rmstride;
       if (s16) {
         a.store = storage;
         a.scale_in = sc[cur];
@@ -689,15 +667,16 @@ int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k
         a.scale_stride = sstride;
         a.in_map = map;
       }
-      e = timed(1, pass_bytes, stream, [&] { return launch_pass(a, ph.R, stream); });
-      if (e != hipSuccess) return hip_err(e, "pass launch");
+      if (record_pass(a, ph.R, &rec) != hipSuccess) return shape_err("pass");
+      rec.bytes = pass_bytes;
+      out->push_back(rec);
       if (s16) {
         cur ^= 1;
         map = pass_map(ph);
       }
     }
     const LateFirst& F = t.late.first;
-    double2* fout = F.final ? out : L0;
+    double2* fout = F.final ? outp : L0;
     const long long fstride = F.final ? (1ll << k) : (long long)(t.bytes_late[0] / 16);
     LateArgs fa = first_args(p, t, B, fout, fstride, ds.d_J, bits, nb);
     if (s16) {
@@ -706,21 +685,119 @@ int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k
       fa.scale_stride = sstride;
       fa.in_map = map;
     }
-    e = timed(2, 0.0, stream, [&] { return launch_late(fa, true, stream); });
-    if (e != hipSuccess) return hip_err(e, "late launch");
+    if (record_late(fa, true, &rec) != hipSuccess) return shape_err("join");
+    out->push_back(rec);
     const double2* curl = L0;
     long long cur_stride = fstride;
     for (size_t i = 0; i < t.late.ops.size(); ++i) {
       const LateOpsLaunch& ln = t.late.ops[i];
-      double2* dst = ln.final ? out : ((i + 1) & 1 ? L1 : L0);
+      double2* dst = ln.final ? outp : ((i + 1) & 1 ? L1 : L0);
       const long long dstride = ln.final ? (1ll << k) : (long long)(t.bytes_late[(i + 1) & 1] / 16);
       LateOpsArgs a = ops_args(p, t, ln, curl, dst, dstride, ds.d_prog, bits, nb, k);
       a.in_batch_stride = cur_stride;
-      e = timed(2, 0.0, stream, [&] { return launch_late_ops(a, stream); });
-      if (e != hipSuccess) return hip_err(e, "late-ops launch");
+      if (record_late_ops(a, &rec) != hipSuccess) return shape_err("late program");
+      out->push_back(rec);
       curl = dst;
       cur_stride = dstride;
     }
+  }
+  return TNC_OK;
+}
+
+// Issues recorded launches on `stream`; every launch's own status is
+// checked (nothing pending on the calling thread is read or cleared).
+int issue_all(const std::vector<Launch>& ls, hipStream_t stream) {
+  for (const Launch& L : ls) {
+    const hipError_t e = timed(L.cls, L.bytes, stream, [&] { return issue(L, stream); });
+    if (e != hipSuccess) return hip_err(e, "kernel launch");
+  }
+  return TNC_OK;
+}
+
+int run_device(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k, int storage, tnc_c128* d_out,
+               void* ws, uint64_t ws_bytes, hipStream_t stream) {
+  std::vector<Launch> ls;
+  const int rc = record_launches(p, ds, nb_total, d_bits, k, storage, d_out, ws, ws_bytes, &ls);
+  if (rc) return rc;
+  return issue_all(ls, stream);
+}
+
+// The complex128 reference path (tests): per batch the 2^h complex128
+// tensor and the two late-phase buffers.
+uint64_t c128_per_batch(const Plan& p, const HostTables& t) {
+  return align256((uint64_t)16 << p.h) + t.bytes_late[0] + t.bytes_late[1];
+}
+
+int run_c128(Plan& p, DevSched& ds, int nb_total, const uint8_t* d_bits, int k, tnc_c128* d_out, void* ws,
+             uint64_t ws_bytes, hipStream_t stream) {
+  const HostTables& t = ds.host;
+  std::shared_ptr<Schedule> s;
+  std::string err;
+  int rc = get_schedule(p, k, &s, &err);
+  if (rc) return set_err(rc, err);
+  {
+    std::lock_guard<std::mutex> lk(ds.mu64);
+    if (!ds.d_ops64 && !s->ops.empty()) {
+      std::vector<Op64> ops(s->ops.size());
+      for (size_t o = 0; o < s->ops.size(); ++o) {
+        const SweepOp& so = s->ops[o];
+        Op64& d = ops[o];
+        std::memset(&d, 0, sizeof(d));
+        d.kind = so.kind == OP_DUP ? 1 : 0;
+        d.target = so.target;
+        d.control = so.control;
+        d.xrow0 = so.xrow[0];
+        d.xrow1 = so.xrow[1];
+        for (int v = 0; v < 4; ++v)
+          for (int c = 0; c < 2; ++c)
+            for (int e = 0; e < 4; ++e) d.m[v][c][e] = make_double2(so.mat[v][c].a[e].real(), so.mat[v][c].a[e].imag());
+      }
+      if ((rc = upload(&ds.d_ops64, ops))) return rc;
+    }
+  }
+  const uint64_t per = c128_per_batch(p, t);
+  const uint64_t fit = ws_bytes / per;
+  if (fit < 1) return set_err(TNC_E_NOMEM, "workspace smaller than one batch");
+  const int chunk = (int)std::min<uint64_t>(fit, (uint64_t)std::min(nb_total, 65535));
+  const uint64_t tensor = align256((uint64_t)16 << p.h);
+  for (int b0 = 0; b0 < nb_total; b0 += chunk) {
+    const int nb = std::min(chunk, nb_total - b0);
+    char* q = static_cast<char*>(ws);
+    double2* B = reinterpret_cast<double2*>(q);
+    q += tensor * nb;
+    double2* L0 = reinterpret_cast<double2*>(q);
+    double2* L1 = reinterpret_cast<double2*>(q + t.bytes_late[0] * nb);
+    const uint8_t* bits = d_bits + (size_t)b0 * p.n;
+    double2* outp = reinterpret_cast<double2*>(d_out) + ((size_t)b0 << k);
+    InitArgs ia = init_args(p, t, reinterpret_cast<float2*>(B), bits, nb, ds.d_seg);
+    hipError_t e = launch_init64(ia, stream);
+    if (e != hipSuccess) return hip_err(e, "complex128 build-up launch");
+    for (size_t o = 0; o < s->ops.size(); ++o) {
+      Op64Args a{B, bits, ds.d_ops64 + o, p.h, p.n, nb};
+      if ((e = launch_op64(a, stream)) != hipSuccess) return hip_err(e, "complex128 update launch");
+    }
+    // the late phase reads the complex128 tensor (the FP64 join kernel)
+    const LateFirst& F = t.late.first;
+    double2* fout = F.final ? outp : L0;
+    const long long fstride = F.final ? (1ll << k) : (long long)(t.bytes_late[0] / 16);
+    LateArgs fa = first_args(p, t, B, fout, fstride, ds.d_J, bits, nb);
+    std::vector<Launch> ls(1);
+    if (record_late(fa, false, &ls[0]) != hipSuccess) return set_err(TNC_E_INVALID, "launch shape out of range: join");
+    const double2* curl = L0;
+    long long cur_stride = fstride;
+    for (size_t i = 0; i < t.late.ops.size(); ++i) {
+      const LateOpsLaunch& ln = t.late.ops[i];
+      double2* dst = ln.final ? outp : ((i + 1) & 1 ? L1 : L0);
+      const long long dstride = ln.final ? (1ll << k) : (long long)(t.bytes_late[(i + 1) & 1] / 16);
+      LateOpsArgs a = ops_args(p, t, ln, curl, dst, dstride, ds.d_prog, bits, nb, k);
+      a.in_batch_stride = cur_stride;
+      Launch L;
+      if (record_late_ops(a, &L) != hipSuccess) return set_err(TNC_E_INVALID, "launch shape out of range: late");
+      ls.push_back(L);
+      curl = dst;
+      cur_stride = dstride;
+    }
+    if ((rc = issue_all(ls, stream))) return rc;
   }
   return TNC_OK;
 }
@@ -787,7 +864,8 @@ int emulate(Plan& p, int k, int nb, const uint8_t* bits, int storage, cd* out) {
   int cur = 0;
   ScaleMap map = init_map(p);
   for (const PassHost& ph : t.passes) {
-    PassArgs a = pass_args(p, ph, t.phases.data(), t.poffs.data(), t.fmats.empty() ? nullptr : t.fmats.data(), t.ops.data(), t.mats.data(), t.mrows.data(), B.data(), bits, nb);
+    PassArgs a = pass_args(p, ph, t.phases.data(), t.poffs.data(), t.fmats.empty() ? nullptr : t.fmats.data(), B.data(),
+                           bits, nb);
     a.rmats = rmats.data();
     a.rstride = rstride;
     if (s16) {
@@ -893,6 +971,22 @@ int emulate(Plan& p, int k, int nb, const uint8_t* bits, int storage, cd* out) {
 Plan* get(tnc_plan_t h) { return h ? h->plan.get() : nullptr; }
 
 }  // namespace
+
+int record_amplitudes(tnc_plan_t plan, int32_t n_batches, const uint8_t* d_bits, int32_t k, int32_t storage,
+                      tnc_c128* d_out, void* d_workspace, uint64_t workspace_bytes, std::vector<Launch>* out) {
+  Plan* p = get(plan);
+  out->clear();
+  if (!p || n_batches < 0 || (n_batches > 0 && (!d_bits || !d_out || !d_workspace)))
+    return set_err(TNC_E_INVALID, "bad argument");
+  if (storage != TNC_STORE_C64 && !is_s16(storage)) return set_err(TNC_E_INVALID, "unknown storage mode");
+  if (n_batches == 0) return TNC_OK;
+  std::shared_ptr<DevSched> ds;
+  int rc = get_dev_sched(*p, k, &ds);
+  if (rc) return rc;
+  return record_launches(*p, *ds, n_batches, d_bits, k, storage, d_out, d_workspace, workspace_bytes, out);
+}
+
+int issue_recorded(const std::vector<Launch>& ls, hipStream_t stream) { return issue_all(ls, stream); }
 }  // namespace tnc
 
 using namespace tnc;
@@ -909,17 +1003,13 @@ int tnc_plan(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, c
     if (opt->reg_bits) o.reg_bits = opt->reg_bits;
     if (opt->low_bits) o.low_bits = opt->low_bits;
     o.math = opt->math;
-    o.pipeline = opt->pipeline;
     o.late_fold = opt->late_fold;
     o.reg_adapt = opt->reg_adapt;
   }
   if (o.max_tile_bits < 6 || o.max_tile_bits > 14 || o.reg_bits < 1 || o.reg_bits > 5 || o.low_bits < 1 ||
-      o.low_bits > o.max_tile_bits - 2 || o.math < 0 || o.math > 2 || o.pipeline < 0 || o.pipeline > 2 ||
-      o.late_fold < -1 || o.late_fold > 8 || o.reg_adapt < 0 || o.reg_adapt > 1 ||
-      o.max_tile_bits - o.reg_bits > (o.math != 1 ? 9 : 8))
+      o.low_bits > o.max_tile_bits - 2 || (o.math != 0 && o.math != 2) || o.late_fold < -1 || o.late_fold > 8 ||
+      o.reg_adapt < 0 || o.reg_adapt > 1 || o.max_tile_bits - o.reg_bits > 9)
     return set_err(TNC_E_INVALID, "tile options out of range");
-  if (o.math == 2 && o.pipeline == 1)
-    return set_err(TNC_E_INVALID, "fused matrix-core phases (math = 2) need pipeline 0 or 2");
   if (n < 2 || d < 2 || (int64_t)n * (d + 1) > (1 << 24)) return set_err(TNC_E_DOMAIN, "need n >= 2, d >= 2");
   std::vector<cd> one((size_t)(d + 1) * n * 4);
   for (size_t i = 0; i < one.size(); ++i) one[i] = cd(one_qubit[i].re, one_qubit[i].im);
@@ -1002,6 +1092,32 @@ int tnc_amplitudes(tnc_plan_t plan, int32_t n_batches, const uint8_t* d_bits, in
                     static_cast<hipStream_t>(stream));
 }
 
+int tnc_debug_workspace_c128(tnc_plan_t plan, int32_t k, int32_t n_batches, uint64_t* bytes) {
+  Plan* p = get(plan);
+  if (!p || !bytes || n_batches < 0) return set_err(TNC_E_INVALID, "bad argument");
+  std::shared_ptr<Schedule> s;
+  std::string err;
+  int rc = get_schedule(*p, k, &s, &err);
+  if (rc) return set_err(rc, err);
+  HostTables t;
+  rc = build_tables(*p, *s, &t, &err);
+  if (rc) return set_err(rc, err);
+  *bytes = (uint64_t)n_batches * c128_per_batch(*p, t);
+  return TNC_OK;
+}
+
+int tnc_debug_amplitudes_c128(tnc_plan_t plan, int32_t n_batches, const uint8_t* d_bits, int32_t k, tnc_c128* d_out,
+                              void* d_workspace, uint64_t workspace_bytes, void* stream) {
+  Plan* p = get(plan);
+  if (!p || n_batches < 0 || (n_batches > 0 && (!d_bits || !d_out || !d_workspace)))
+    return set_err(TNC_E_INVALID, "bad argument");
+  if (n_batches == 0) return TNC_OK;
+  std::shared_ptr<DevSched> ds;
+  int rc = get_dev_sched(*p, k, &ds);
+  if (rc) return rc;
+  return run_c128(*p, *ds, n_batches, d_bits, k, d_out, d_workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
 int tnc_amplitudes_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, int32_t storage,
                         tnc_c128* out) {
   Plan* p = get(plan);
@@ -1013,26 +1129,37 @@ int tnc_amplitudes_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits,
   uint8_t* d_bits = nullptr;
   tnc_c128* d_out = nullptr;
   void* d_ws = nullptr;
+  hipStream_t st = nullptr;
   hipError_t e;
+  // a stream of this call's own: waiting for it never waits for (or fails
+  // on) other work on the device
   auto cleanup = [&]() {
+    if (st) (void)hipStreamSynchronize(st);
     if (d_bits) (void)hipFree(d_bits);
     if (d_out) (void)hipFree(d_out);
     if (d_ws) (void)hipFree(d_ws);
+    if (st) (void)hipStreamDestroy(st);
   };
   const size_t nbits = (size_t)n_batches * p->n, nout = (size_t)n_batches << k;
+  if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) {
+    st = nullptr;
+    return hip_err(e, "hipStreamCreate");
+  }
   if ((e = hipMalloc((void**)&d_bits, nbits)) != hipSuccess || (e = hipMalloc((void**)&d_out, nout * 16)) != hipSuccess ||
       (e = hipMalloc(&d_ws, ws)) != hipSuccess) {
     cleanup();
     return set_err(TNC_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   }
-  if ((e = hipMemcpy(d_bits, bits, nbits, hipMemcpyHostToDevice)) != hipSuccess) {
+  if ((e = hipMemcpyAsync(d_bits, bits, nbits, hipMemcpyHostToDevice, st)) != hipSuccess) {
     cleanup();
-    return hip_err(e, "hipMemcpy");
+    return hip_err(e, "hipMemcpyAsync");
   }
-  rc = tnc_amplitudes(plan, n_batches, d_bits, k, storage, d_out, d_ws, ws, nullptr);
+  rc = tnc_amplitudes(plan, n_batches, d_bits, k, storage, d_out, d_ws, ws, st);
   if (rc == TNC_OK) {
-    if ((e = hipDeviceSynchronize()) != hipSuccess) rc = hip_err(e, "kernel execution");
-    else if ((e = hipMemcpy(out, d_out, nout * 16, hipMemcpyDeviceToHost)) != hipSuccess) rc = hip_err(e, "hipMemcpy");
+    if ((e = hipMemcpyAsync(out, d_out, nout * 16, hipMemcpyDeviceToHost, st)) != hipSuccess)
+      rc = hip_err(e, "hipMemcpyAsync");
+    else if ((e = hipStreamSynchronize(st)) != hipSuccess)
+      rc = hip_err(e, "kernel execution");
   }
   cleanup();
   return rc;

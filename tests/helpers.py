@@ -16,7 +16,7 @@ def header_symbols():
     for f in os.listdir(inc):
         if f.endswith(".h"):
             txt = open(os.path.join(inc, f)).read()
-            syms |= set(re.findall(r"^\s*(?:int|void|const char\*)\s+(tnc_\w+)\s*\(", txt, re.M))
+            syms |= set(re.findall(r"^\s*(?:int|void|uint64_t|const char\*)\s+(tnc_\w+)\s*\(", txt, re.M))
     return sorted(syms)
 
 

@@ -81,24 +81,24 @@ SMALL = [
     (14, 29, 0, 0.3, 2, 6, None),
     (10, 8, 1, 0.3, 4, 3, None),   # 2k = d: no late layer beyond the early region
     (6, 12, 0, 0.5, 5, 2, None),   # k = n - 1: one fixed row
-    (16, 30, 1, 0.3, 4, 8, dict(math=1)),
-    (12, 24, 0, 0.3, 6, 4, dict(max_tile_bits=8, low_bits=4, reg_bits=4, math=1)),
-    # persistent prefetching pass blocks: 256 threads x 32, 512 x 16, 256 x 16
-    (16, 30, 1, 0.3, 4, 8, dict(pipeline=1)),
-    (16, 30, 0, 0.3, 3, 8, dict(pipeline=1, reg_bits=4)),
-    (16, 31, 1, 0.3, 2, 8, dict(pipeline=1, reg_bits=4, max_tile_bits=12)),
+    # one 2^13-entry tile per 512-thread block (16 entries per thread)
+    (16, 30, 1, 0.3, 4, 8, dict(max_tile_bits=13, low_bits=5, reg_bits=4)),
     # one 2^14-entry tile per 512-thread block, 64-byte low runs
     (17, 32, 1, 0.3, 4, 4, dict(max_tile_bits=14, low_bits=3)),
-    # persistent blocks prefetching into registers
-    (16, 30, 1, 0.3, 4, 8, dict(pipeline=2, reg_bits=4, max_tile_bits=12)),
-    (15, 29, 0, 0.3, 3, 8, dict(pipeline=2, reg_bits=3, max_tile_bits=11)),
+    # passes narrowed to reg_bits - 1 where that costs no phase
+    (16, 30, 0, 0.3, 3, 8, dict(max_tile_bits=12, reg_adapt=1)),
+    (15, 29, 1, 0.3, 3, 8, dict(max_tile_bits=11, reg_bits=4, reg_adapt=1)),
+    # late removals folded into the join (5 and 7: the defaults from 2^30 and
+    # at 2^35 entries)
+    (14, 28, 1, 0.3, 2, 6, dict(late_fold=5)),
+    (16, 31, 0, 0.3, 2, 8, dict(late_fold=7, math=2, max_tile_bits=12, reg_bits=4)),
     # runs of three updates fused into 8x8 products on the matrix cores:
     # 128-thread tiles (two per block), 64-thread tiles (four per block),
-    # 256-thread tiles, and the prefetching blocks
+    # 256-thread and 512-thread tiles
     (14, 28, 1, 0.3, 4, 6, dict(math=2, max_tile_bits=11, low_bits=4, reg_bits=4)),
     (12, 24, 0, 0.3, 3, 5, dict(math=2, max_tile_bits=9, low_bits=3, reg_bits=3)),
     (13, 26, 1, 0.0, 6, 4, dict(math=2, max_tile_bits=12, low_bits=4, reg_bits=4)),
-    (16, 30, 0, 0.3, 4, 8, dict(math=2, pipeline=2, max_tile_bits=12, reg_bits=4)),
+    (16, 30, 0, 0.3, 4, 8, dict(math=2, max_tile_bits=13, low_bits=5, reg_bits=4)),
 ]
 
 
@@ -112,13 +112,12 @@ def test_small_circuits(n, d, fp, dense, k, nb, opts):
     assert_close(got, ref, n)
 
 
-@pytest.mark.parametrize("opts", [None, dict(pipeline=1), dict(pipeline=1, reg_bits=4),
-                                  dict(pipeline=2, reg_bits=4, max_tile_bits=12),
+@pytest.mark.parametrize("opts", [None, dict(max_tile_bits=13, low_bits=5, reg_bits=4, math=2),
+                                  dict(max_tile_bits=12, reg_adapt=1),
                                   dict(max_tile_bits=14, low_bits=3), dict(math=2)])
 def test_medium_config_restriction(opts):
     # medium workload (d = 40, w = 20), restricted to 24 qubits, 64 batches,
-    # k = 6: 8192 tiles per pass, so persistent blocks loop over many tiles
-    # and cross batch boundaries
+    # k = 6: thousands of tiles per pass, crossing batch boundaries
     from paper_2608_13110_amd import Plan
     c = W.restrict(W.config_circuit(1), 24)
     bits = W.config_bitstrings(1)[:, :24]
@@ -141,13 +140,40 @@ def test_medium_config_full_alg1_matches_alg2():
     assert per.max() < 2 * H.TOL_C64
 
 
-def test_precision_config_restriction():
+# every option set the benchmark's autotuner and the serving tuner choose
+# from (the tuner's pick at w = 28 is reg_bits = 4 with fused phases)
+TUNED = [None, dict(max_tile_bits=12, math=2), dict(reg_bits=4, math=2),
+         dict(max_tile_bits=13, low_bits=5, reg_bits=4, math=2), dict(max_tile_bits=12, reg_adapt=1),
+         dict(max_tile_bits=12, reg_bits=4), dict(max_tile_bits=11, reg_bits=4)]
+
+
+@pytest.mark.parametrize("opts", TUNED)
+def test_precision_config_restriction(opts):
     # precision workload shape (d = 56, w = 28) restricted to 22 qubits, k = 8
     from paper_2608_13110_amd import Plan
     c = W.restrict(W.config_circuit(2), 22)
     bits = W.config_bitstrings(2)[:3, :22]
     ref = oracle.amplitudes(c, bits, 8)
-    got = gpu_amps(Plan.from_circuit(c), bits, 8)
+    got = gpu_amps(Plan.from_circuit(c, opts), bits, 8)
+    assert_close(got, ref, c.n)
+
+
+def test_width35_restriction_t_doped():
+    # the width-35 shape (n = d = 70, 468 T) restricted to 22 qubits: the
+    # 2^35-entry tensor (256 GiB) with seven late removals folded into the
+    # join, in the benchmark's tile options, against the oracle (Sec. 4.3,
+    # Alg. 2)
+    from paper_2608_13110_amd import Plan
+    c = W.restrict(W.config_circuit(5), 22)
+    bits = W.random_bitstrings(22, 1, W.rng_for(408, 1))
+    ref = oracle.amplitudes(c, bits, 8)
+    p = Plan.from_circuit(c, dict(max_tile_bits=13, low_bits=5, reg_bits=4, math=2))
+    torch.cuda.empty_cache()
+    print(f"  [gpu] width-35 restriction: {p.workspace_bytes(8, 1) / 1e9:.1f} GB of workspace", flush=True)
+    ws = torch.empty(p.workspace_bytes(8, 1), dtype=torch.uint8, device="cuda")
+    got = gpu_amps(p, bits, 8, workspace=ws)
+    del ws
+    torch.cuda.empty_cache()
     assert_close(got, ref, c.n)
 
 
@@ -264,7 +290,11 @@ STORAGE_BOUNDS = {1: (1.5e-2, 6e-3), 2: (1.2e-1, 5e-2)}
 @pytest.mark.parametrize("cid,m,k,nb,opts", [(1, 24, 6, 16, None), (2, 22, 8, 2, None), (4, 22, 8, 1, None),
                                              # fused matrix-core phases on the decoded tile
                                              (2, 22, 8, 2, dict(math=2)),
-                                             (4, 22, 8, 1, dict(max_tile_bits=12, math=2))])
+                                             (4, 22, 8, 1, dict(max_tile_bits=12, math=2)),
+                                             # 512-thread tiles: two scale blocks per tile (2^13
+                                             # entries) and four (2^14 entries)
+                                             (4, 22, 8, 1, dict(max_tile_bits=13, low_bits=5, reg_bits=4, math=2)),
+                                             (2, 22, 8, 2, dict(max_tile_bits=14, low_bits=3, reg_bits=5))])
 def test_block_scaled_storage_vs_oracle(storage, cid, m, k, nb, opts):
     from paper_2608_13110_amd import Plan
     c = W.restrict(W.config_circuit(cid), m)

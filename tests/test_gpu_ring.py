@@ -1,4 +1,4 @@
-"""GPU tests of the ring geometry (Sec. 7) by slicing its wrap-pair CZ
+"""GPU tests of the ring geometry (Sec. 6.3) by slicing its wrap-pair CZ
 bonds: the sum over 2^m open-chain slices, through the C ABI, against the
 FP64 oracle's state vector of the ring itself."""
 import numpy as np

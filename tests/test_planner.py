@@ -108,10 +108,13 @@ def test_host_execution_matches_oracle(n, d, fp, dense):
 
 TILES = [dict(max_tile_bits=6, low_bits=2, reg_bits=3), dict(max_tile_bits=6, low_bits=1, reg_bits=5),
          dict(max_tile_bits=7, low_bits=3, reg_bits=2), dict(max_tile_bits=8, low_bits=4, reg_bits=4), None,
-         # late removals folded into the join launch (the default for large tensors)
+         # late removals folded into the join launch (the default for large tensors:
+         # 3 from 2^26 entries, 5 from 2^30, 7 at 2^35)
          dict(late_fold=3), dict(late_fold=1, max_tile_bits=8, low_bits=3, reg_bits=4),
+         dict(late_fold=5), dict(late_fold=7, max_tile_bits=8, low_bits=4, reg_bits=4, math=2),
          # passes narrowed to reg_bits - 1 where that costs no phase
          dict(reg_adapt=1, max_tile_bits=8, low_bits=4, reg_bits=5),
+         dict(reg_adapt=1, max_tile_bits=9, low_bits=3, reg_bits=4, math=2),
          # runs of three updates fused into 8x8 products on the matrix cores
          dict(math=2, max_tile_bits=9, low_bits=3, reg_bits=3), dict(math=2, max_tile_bits=10, low_bits=4, reg_bits=4),
          dict(math=2, max_tile_bits=11, low_bits=4, reg_bits=5, late_fold=3)]
@@ -189,9 +192,13 @@ def test_block_scaled_storage_is_rejected_with_one_low_slot():
 
 
 def test_fused_phases_restrictions():
-    # fused 8x8 phases do not run in the LDS-prefetching kernel
+    # the update forms are 0 (vector ALUs) and 2 (fused matrix-core phases);
+    # any other value, and unknown option names, are rejected
     c = H.mixed_circuit(14, 28, 98)
-    with pytest.raises(TncError):
+    for bad in (1, 3, -1):
+        with pytest.raises(TncError):
+            Plan.from_circuit(c, dict(math=bad, max_tile_bits=10, reg_bits=4))
+    with pytest.raises(ValueError):
         Plan.from_circuit(c, dict(math=2, max_tile_bits=10, reg_bits=4, pipeline=1))
     p = Plan.from_circuit(c, dict(math=2, max_tile_bits=10, low_bits=4, reg_bits=4))
     # with 16-bit storage the fused phases run on the decoded tile, to the
@@ -234,7 +241,7 @@ def test_sampler_entry_points_validate_on_the_host():
 
 
 def test_ring_slicing_matches_oracle_in_emulation():
-    # the ring (Sec. 7) as the sum of its 2^m open-chain slices, emulated on
+    # the ring (Sec. 6.3) as the sum of its 2^m open-chain slices, emulated on
     # the host, against the oracle's ring state vector; and the slice count
     import oracle as O
     from paper_2608_13110_amd import RingPlan
