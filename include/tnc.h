@@ -159,6 +159,27 @@ int tnc_workspace_bytes(tnc_plan_t plan, int32_t k, int32_t n_batches, int32_t s
 int tnc_amplitudes(tnc_plan_t plan, int32_t n_batches, const uint8_t* d_bits, int32_t k, int32_t storage,
                    tnc_c128* d_out, void* d_workspace, uint64_t workspace_bytes, void* stream);
 
+/*
+ * tnc_amplitudes for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same launches, with the workspace taken from a scratch array that the
+ * library holds on each GPU (tnc_noalloc_scratch_bytes() bytes, 256 MiB:
+ * one batch up to about 2^22 boundary entries with k >= 1) until the process
+ * ends.  No hipMalloc, hipFree or other allocating call is made.
+ *   d_bits, d_out, stream: as for tnc_amplitudes (caller-owned device memory).
+ *   The device tables for k must already be on the current device
+ *   (tnc_prepare, or an earlier tnc_amplitudes call): TNC_E_INVALID otherwise.
+ *   A batch whose workspace exceeds the scratch: TNC_E_NOMEM.  Batches that
+ *   fit together run in groups, as with a small workspace.
+ * Every call on one GPU shares that GPU's scratch, so calls that overlap on
+ * one GPU (different streams or threads) race; calls in one stream do not.
+ * Nothing in the scratch is read before this call writes it.
+ */
+int tnc_amplitudes_noalloc(tnc_plan_t plan, int32_t n_batches, const uint8_t* d_bits, int32_t k, int32_t storage,
+                           tnc_c128* d_out, void* stream);
+/* Size of the per-GPU scratch of tnc_amplitudes_noalloc, in bytes. */
+uint64_t tnc_noalloc_scratch_bytes(void);
+
 /* Same with host buffers: allocates device memory, runs, synchronizes. */
 int tnc_amplitudes_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, int32_t storage,
                         tnc_c128* out);

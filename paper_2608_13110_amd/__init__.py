@@ -40,7 +40,7 @@ EXPORTED = [
     "tnc_autotune", "tnc_server_create", "tnc_server_destroy", "tnc_server_set_tuning", "tnc_server_submit",
     "tnc_server_wait", "tnc_server_summary", "tnc_debug_arena_check", "tnc_sample_batched", "tnc_frugal_accept",
     "tnc_plan_ring", "tnc_ring_info", "tnc_ring_amplitudes", "tnc_debug_ring_emulate", "tnc_ring_release",
-    "tnc_debug_workspace_c128", "tnc_debug_amplitudes_c128",
+    "tnc_amplitudes_noalloc", "tnc_noalloc_scratch_bytes", "tnc_debug_workspace_c128", "tnc_debug_amplitudes_c128",
 ]
 
 
@@ -133,6 +133,9 @@ def lib() -> ctypes.CDLL:
     L.tnc_workspace_bytes.argtypes = [vp, i32, i32, i32, ctypes.POINTER(u64)]
     L.tnc_amplitudes.argtypes = [vp, i32, vp, i32, i32, vp, vp, u64, vp]
     L.tnc_amplitudes_host.argtypes = [vp, i32, vp, i32, i32, vp]
+    L.tnc_amplitudes_noalloc.argtypes = [vp, i32, vp, i32, i32, vp, vp]
+    L.tnc_noalloc_scratch_bytes.argtypes = []
+    L.tnc_noalloc_scratch_bytes.restype = u64
     L.tnc_debug_workspace_c128.argtypes = [vp, i32, i32, ctypes.POINTER(u64)]
     L.tnc_debug_amplitudes_c128.argtypes = [vp, i32, vp, i32, vp, vp, u64, vp]
     L.tnc_logxeb.argtypes = [vp, i32, i32, vp, i32, vp, vp]
@@ -163,7 +166,8 @@ def lib() -> ctypes.CDLL:
     L.tnc_server_summary.argtypes = [vp, ctypes.POINTER(ServerStats)]
     L.tnc_debug_arena_check.argtypes = [u64, i32]
     for name in EXPORTED:
-        if name not in ("tnc_release", "tnc_strerror", "tnc_last_error", "tnc_server_destroy", "tnc_ring_release"):
+        if name not in ("tnc_release", "tnc_strerror", "tnc_last_error", "tnc_server_destroy", "tnc_ring_release",
+                        "tnc_noalloc_scratch_bytes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -275,6 +279,23 @@ class Plan:
         s = stream if stream is not None else torch.cuda.current_stream(bits.device)
         _check(lib().tnc_amplitudes(self._h, nb, bits.data_ptr(), int(k), int(storage), out.data_ptr(),
                                     workspace.data_ptr(), workspace.numel(), ctypes.c_void_p(s.cuda_stream)))
+        return out
+
+    def amplitudes_noalloc(self, bits, k: int, out=None, stream=None, storage: int = STORE_C64):
+        """``tnc_amplitudes_noalloc``: as ``amplitudes``, with the workspace
+        taken from the library's per-GPU scratch (no device allocation by the
+        library; ``prepare(k)`` must have run on this device)."""
+        import torch
+        if bits.device.type != "cuda" or bits.dtype != torch.uint8 or not bits.is_contiguous():
+            raise ValueError("bits must be a contiguous uint8 CUDA tensor")
+        nb = int(bits.shape[0])
+        if bits.shape[1] != self.n:
+            raise ValueError("bits must have n columns")
+        if out is None:
+            out = torch.empty((nb, 1 << k), dtype=torch.complex128, device=bits.device)
+        s = stream if stream is not None else torch.cuda.current_stream(bits.device)
+        _check(lib().tnc_amplitudes_noalloc(self._h, nb, bits.data_ptr(), int(k), int(storage), out.data_ptr(),
+                                            ctypes.c_void_p(s.cuda_stream)))
         return out
 
     def amplitudes_host(self, bits: np.ndarray, k: int, storage: int = STORE_C64) -> np.ndarray:

@@ -475,6 +475,51 @@ int get_dev_sched(Plan& p, int k, std::shared_ptr<DevSched>* out) {
   return 0;
 }
 
+// The device tables for (k, current device) if they were already built,
+// else null; never builds, uploads or allocates.
+std::shared_ptr<DevSched> find_dev_sched(Plan& p, int k) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  {
+    std::lock_guard<std::mutex> lk(p.mu);
+    if (!p.device) return nullptr;
+  }
+  PlanDevice& pd = plan_device(p);
+  std::lock_guard<std::mutex> lk(pd.mu);
+  auto it = pd.m.find({k, dev});
+  return it == pd.m.end() ? nullptr : it->second;
+}
+
+// Scratch memory of tnc_amplitudes_noalloc: one copy of this array on each
+// GPU the library runs on, held until the process ends.  In host code the
+// name stands for a host-side handle, never for the device address: every
+// host use goes through the per-device address from hipGetSymbolAddress.
+constexpr uint64_t kNoAllocScratchBytes = 256ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device -> address of `scratch` there
+
+// The scratch address on the current device (looked up once per device,
+// with that device current).
+int scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_err(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return TNC_OK;
+  }
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return hip_err(e, "hipGetSymbolAddress of the scratch array");
+  g_scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return TNC_OK;
+}
+
 // Process-wide event timing of kernel launches (tnc_profile_*).
 struct Profiler {
   std::mutex mu;
@@ -1091,6 +1136,37 @@ int tnc_amplitudes(tnc_plan_t plan, int32_t n_batches, const uint8_t* d_bits, in
   return run_device(*p, *ds, n_batches, d_bits, k, storage, d_out, d_workspace, workspace_bytes,
                     static_cast<hipStream_t>(stream));
 }
+
+int tnc_amplitudes_noalloc(tnc_plan_t plan, int32_t n_batches, const uint8_t* d_bits, int32_t k, int32_t storage,
+                           tnc_c128* d_out, void* stream) {
+  Plan* p = get(plan);
+  if (!p || n_batches < 0 || (n_batches > 0 && (!d_bits || !d_out))) return set_err(TNC_E_INVALID, "bad argument");
+  if (storage != TNC_STORE_C64 && !is_s16(storage)) return set_err(TNC_E_INVALID, "unknown storage mode");
+  if (n_batches == 0) return TNC_OK;
+  std::shared_ptr<DevSched> ds = find_dev_sched(*p, k);
+  if (!ds)
+    return set_err(TNC_E_INVALID, "device tables for these open legs are not prepared on this device "
+                                  "(call tnc_prepare first; this entry point allocates nothing)");
+  int rc = check_storage(ds->host, storage);
+  if (rc) return rc;
+  const uint64_t per = batch_layout(*p, ds->host, storage).per_batch();
+  if (per > kNoAllocScratchBytes)
+    return set_err(TNC_E_NOMEM, "one batch needs " + std::to_string(per) + " bytes of workspace, above the " +
+                                    std::to_string(kNoAllocScratchBytes) + "-byte scratch of tnc_amplitudes_noalloc");
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  std::vector<Launch> ls;
+  rc = record_launches(*p, *ds, n_batches, d_bits, k, storage, d_out, ws, kNoAllocScratchBytes, &ls);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (const Launch& L : ls) {
+    const hipError_t e = issue(L, st);
+    if (e != hipSuccess) return hip_err(e, "kernel launch");
+  }
+  return TNC_OK;
+}
+
+uint64_t tnc_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
 
 int tnc_debug_workspace_c128(tnc_plan_t plan, int32_t k, int32_t n_batches, uint64_t* bytes) {
   Plan* p = get(plan);
