@@ -17,6 +17,11 @@ Contents
                  last k qubits, index b read MSB-first over qubits n-k..n-1.
 ``logxeb``       the log-XEB estimator of Sec. 5.2 (Eq. normalized-log-xeb),
                  with its empirical standard error and 95 % interval.
+``product_amplitudes`` <x|U|0^n> for circuits whose entanglers are all
+                 SWAP gates dressed with one-qubit gates (G = (P (x) Q) SWAP),
+                 at any n: U|0^n> stays a product state, tracked qubit by
+                 qubit (operator Schmidt rank 4 entanglers with a closed form,
+                 for checks of the bond-dimension-four path at full width).
 ``tv_conditional`` total-variation distance of the conditional
                  distributions p(b|a), the accuracy metric of Sec. 5.1.
 ``batched_sample`` the batched sampler of Sec. 4.2: one suffix b per batch
@@ -112,6 +117,43 @@ def amplitudes(circ, bitstrings: np.ndarray, k: int, psi: Optional[np.ndarray] =
     base = prefix_index(bitstrings, k)
     cols = np.arange(1 << k, dtype=np.int64)
     return psi[base[:, None] + cols[None, :]]
+
+
+SWAP = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]], dtype=np.complex128)
+
+
+def product_amplitudes(circ, bitstrings: np.ndarray) -> np.ndarray:
+    """<x|U|0^n> (one per bitstring row) when every entangler is G = (P (x) Q)
+    SWAP (basis 2*x_q + x_{q+1}).  The state is then a product of one-qubit
+    states s_0 (x) ... (x) s_{n-1} at every layer (Sec. 2.1's U applied layer
+    by layer): a one-qubit gate L maps s_q to L s_q, and G maps (s_q, s_{q+1})
+    to (P s_{q+1}, Q s_q).  P (x) Q = G SWAP is recovered as the rank-one
+    factor of its realignment R[2a+a'][2b+b'] = (G SWAP)[2a+b][2a'+b'] (the
+    largest singular pair); a gate whose realignment is not rank one is
+    refused.  The amplitude is prod_q s_q[x_q].
+    """
+    n, d = circ.n, circ.d
+    one = np.asarray(circ.one_qubit, dtype=np.complex128)
+    factors = {}
+    for (layer, q, kind, m) in circ.gates:
+        if m is None:
+            raise ValueError("product_amplitudes needs dressed-SWAP entanglers, not CZ")
+        k = np.asarray(m, dtype=np.complex128) @ SWAP
+        r = k.reshape(2, 2, 2, 2).transpose(0, 2, 1, 3).reshape(4, 4)
+        u, sv, vh = np.linalg.svd(r)
+        if sv[1] > 1e-9 * sv[0]:
+            raise ValueError("entangler is not a dressed SWAP")
+        factors[(layer, q)] = ((u[:, 0] * sv[0]).reshape(2, 2), vh[0].reshape(2, 2))
+    s = np.zeros((n, 2), dtype=np.complex128)
+    s[:, 0] = 1.0
+    s = np.einsum("qij,qj->qi", one[0], s)
+    for layer in range(1, d + 1):
+        for (l, q), (P, Q) in factors.items():
+            if l == layer:
+                s[q], s[q + 1] = P @ s[q + 1], Q @ s[q]
+        s = np.einsum("qij,qj->qi", one[layer], s)
+    bits = np.asarray(bitstrings, dtype=np.int64)
+    return np.prod(s[np.arange(n)[None, :], bits], axis=1)
 
 
 def logxeb(probs: np.ndarray, n: int):

@@ -316,3 +316,20 @@ def test_frugal_accept_rate_on_a_grid():
         acc, z = oracle.frugal_accept(np.full(N, a), n, M, u)
         assert np.allclose(z, 2.0 ** n * abs(a) ** 2, rtol=1e-15, atol=0)
         assert abs(acc.mean() - min(1.0, z[0] / M)) <= 1.0 / N
+
+
+# oracle.product_amplitudes (dressed-SWAP networks, any n): brute force on
+# small chains, and refusal of gates whose G SWAP is not a product
+@pytest.mark.parametrize("n,d,fp", [(2, 2, 1), (5, 6, 0), (8, 8, 1), (11, 10, 0), (14, 12, 1)])
+def test_product_oracle_matches_state_vector(n, d, fp):
+    # pin of oracle.product_amplitudes: brute force on small chains
+    c = W.swap_network_circuit(n, d, W.rng_for(411, n, d), fp)
+    bits = W.random_bitstrings(n, 16, W.rng_for(412, n))
+    ref = oracle.amplitudes(c, bits, 0)[:, 0]
+    assert np.max(np.abs(oracle.product_amplitudes(c, bits) - ref)) < 1e-13
+
+
+def test_product_oracle_refuses_entangling_gates():
+    c = W.generic_brickwork_circuit(4, 4, W.rng_for(413))
+    with pytest.raises(ValueError):
+        oracle.product_amplitudes(c, W.random_bitstrings(4, 2, W.rng_for(414)))

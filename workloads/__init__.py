@@ -234,6 +234,49 @@ def random_unitary_2x2(rng: np.random.Generator) -> np.ndarray:
     return qm * (np.diag(r) / np.abs(np.diag(r)))
 
 
+def random_unitary_4x4(rng: np.random.Generator) -> np.ndarray:
+    """A Haar-random two-qubit unitary (QR of a complex Gaussian with the
+    phases of R's diagonal divided out); operator Schmidt rank 4 with
+    probability one."""
+    z = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+    qm, r = np.linalg.qr(z)
+    return qm * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def generic_brickwork_circuit(n: int, d: int, rng: np.random.Generator, first_parity: int = 1,
+                              label: str = "") -> Circuit:
+    """Open-chain brickwork in which every entangler is an independent
+    Haar-random two-qubit unitary (bond dimension four) and every one-qubit
+    site an independent Haar-random 2x2: the hardened circuit family of
+    Sec. 6.2 (generic gates in place of CZ)."""
+    if n < 2 or d < 1:
+        raise ValueError("need n >= 2 and d >= 1")
+    one = np.stack([[random_unitary_2x2(rng) for _ in range(n)] for _ in range(d + 1)])
+    gates = []
+    for layer in range(1, d + 1):
+        for q in brickwork_pairs(n, layer, first_parity):
+            gates.append((layer, q, GATE_DENSE4, random_unitary_4x4(rng)))
+    return Circuit(n=n, d=d, one_qubit=one, gates=gates, first_parity=first_parity, label=label)
+
+
+SWAP_GATE = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]], dtype=np.complex128)
+
+
+def swap_network_circuit(n: int, d: int, rng: np.random.Generator, first_parity: int = 1,
+                         label: str = "") -> Circuit:
+    """Open-chain brickwork whose entanglers are SWAP gates dressed with
+    Haar-random one-qubit gates, (A (x) B) SWAP (C (x) D): operator Schmidt
+    rank four, yet U|0^n> stays a product state, so every amplitude has a
+    closed form at any n.  One-qubit sites are Haar-random."""
+    one = np.stack([[random_unitary_2x2(rng) for _ in range(n)] for _ in range(d + 1)])
+    gates = []
+    for layer in range(1, d + 1):
+        for q in brickwork_pairs(n, layer, first_parity):
+            a, b, c, e = (random_unitary_2x2(rng) for _ in range(4))
+            gates.append((layer, q, GATE_DENSE4, np.kron(a, b) @ SWAP_GATE @ np.kron(c, e)))
+    return Circuit(n=n, d=d, one_qubit=one, gates=gates, first_parity=first_parity, label=label)
+
+
 def random_rank2_gate(rng: np.random.Generator, kind: str = "zz") -> np.ndarray:
     """A two-qubit unitary of operator Schmidt rank 2 (basis 2*x_q + x_{q+1}).
 
