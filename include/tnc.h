@@ -96,7 +96,13 @@ typedef struct {
   int32_t reg_adapt;     /* 1: a pass takes reg_bits - 1 when that needs no more register
                             phases and its tile fits 256 threads (more resident waves);
                             0: every pass uses reg_bits (default) */
-  int32_t reserved[2];
+  int32_t bond;          /* bond dimension of the lowering (Sec. 6.2, Effect of bond dimension):
+                            0 (default) the smallest that holds every entangler: 2 when all have
+                            operator Schmidt rank <= 2, else 4; 2: rank > 2 is TNC_E_RANK; 4: two
+                            legs per crossing for every entangler.  Bond 4 needs even d, gives a
+                            boundary tensor of d - 1 slots (the width min(n, d-1) for n >= d-1)
+                            updated by dense 4x4s, and k = 0 only (TNC_E_DOMAIN otherwise) */
+  int32_t reserved;
 } tnc_options;
 
 typedef struct {
@@ -111,7 +117,9 @@ typedef struct {
   int32_t early_layers;       /* c = 2k entangling layers in the early region */
   int32_t late_layers;        /* d - c layers absorbed after the join */
   double log2_cost;           /* log2 C(P), C = sum |I||J||K| (Sec. 2.2) */
-  uint64_t workspace_per_batch; /* device bytes per concurrent batch */
+  uint64_t workspace_per_batch; /* device bytes per concurrent batch (0: width above 40, planned only) */
+  int32_t bond;               /* bond dimension of the lowering (2 or 4) */
+  int32_t reserved;
 } tnc_info;
 
 /*
@@ -123,7 +131,8 @@ typedef struct {
  *              Pattern pairs without a gate are identity.  Copied.
  *   opt:       may be NULL.
  * Host only: no device memory is touched.  Returns TNC_OK and *out, or
- * TNC_E_INVALID / TNC_E_DOMAIN (n < 2, d < 2, width > 40) / TNC_E_RANK.
+ * TNC_E_INVALID / TNC_E_DOMAIN (n < 2, d < 2, width > 40, bond 4 at odd d) /
+ * TNC_E_RANK (an entangler of rank > 2 with opt->bond = 2).
  */
 int tnc_plan(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, const tnc_gate2* gates,
              const tnc_options* opt, tnc_plan_t* out);
@@ -272,6 +281,16 @@ typedef struct {
 
 int tnc_profile_begin(void);
 int tnc_profile_end(tnc_profile* out);
+/* The launches timed by the last tnc_profile_end, in issue order: class
+ * (0 build-up / variant resolution, 1 pass, 2 late phase) and duration in
+ * ms; *n = their number, at most cap are written. */
+int tnc_profile_launches(int32_t* cls, double* ms, int64_t cap, int64_t* n);
+
+/* The HBM passes of the fixed sweep for k open legs, in launch order: seven
+ * int32 per pass, {low slots, window start, window length, register bits,
+ * updates, register phases, fused phases}; *n_passes = their number, at most
+ * cap are written.  Host only. */
+int tnc_plan_passes(tnc_plan_t plan, int32_t k, int32_t* out, int32_t cap, int32_t* n_passes);
 
 /*
  * Tile autotuner.  Times each candidate tile option set on the current
@@ -395,11 +414,19 @@ int tnc_debug_emulate_device(tnc_plan_t plan, int32_t n_batches, const uint8_t* 
  * (Sec. 5.1).  Arguments as for tnc_amplitudes (complex64 storage modes do
  * not apply); the workspace holds the complex128 tensor and the late
  * buffers per batch (tnc_debug_workspace_c128), and the update tables are
- * uploaded on first use (synchronous).
+ * uploaded on first use (synchronous).  Bond-dimension-2 plans only (a
+ * bond-4 plan: TNC_E_DOMAIN).
  */
 int tnc_debug_workspace_c128(tnc_plan_t plan, int32_t k, int32_t n_batches, uint64_t* bytes);
 int tnc_debug_amplitudes_c128(tnc_plan_t plan, int32_t n_batches, const uint8_t* d_bits, int32_t k, tnc_c128* d_out,
                               void* d_workspace, uint64_t workspace_bytes, void* stream);
+
+/* Planner self-check of the LDS placement: over every register phase of the
+ * pass tables for k, stats[0] = phases, stats[1] = phases in which two of the
+ * 16 lanes of a bank cycle (lanes 16 c .. 16 c + 15) meet the same slot
+ * modulo 16, stats[2] = the same for 32-lane cycles modulo 32 (8-byte slots).
+ * Host only. */
+int tnc_debug_lds_conflicts(tnc_plan_t plan, int32_t k, int64_t* stats);
 
 /* Host self-check of the serving loop's device-arena allocator: n_ops
  * seeded random allocations and releases, checked for overlap, bounds and

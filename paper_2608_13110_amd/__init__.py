@@ -41,6 +41,7 @@ EXPORTED = [
     "tnc_server_wait", "tnc_server_summary", "tnc_debug_arena_check", "tnc_sample_batched", "tnc_frugal_accept",
     "tnc_plan_ring", "tnc_ring_info", "tnc_ring_amplitudes", "tnc_debug_ring_emulate", "tnc_ring_release",
     "tnc_amplitudes_noalloc", "tnc_noalloc_scratch_bytes", "tnc_debug_workspace_c128", "tnc_debug_amplitudes_c128",
+    "tnc_debug_lds_conflicts", "tnc_profile_launches", "tnc_plan_passes",
 ]
 
 
@@ -63,7 +64,7 @@ class Options(ctypes.Structure):
     _fields_ = [("max_tile_bits", ctypes.c_int32), ("reg_bits", ctypes.c_int32),
                 ("low_bits", ctypes.c_int32), ("math", ctypes.c_int32),
                 ("late_fold", ctypes.c_int32), ("reg_adapt", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("bond", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -72,7 +73,8 @@ class Info(ctypes.Structure):
                 ("n_passes", ctypes.c_int32), ("n_phases", ctypes.c_int32),
                 ("n_late_launches", ctypes.c_int32), ("fixed_rows", ctypes.c_int32),
                 ("early_layers", ctypes.c_int32), ("late_layers", ctypes.c_int32),
-                ("log2_cost", ctypes.c_double), ("workspace_per_batch", ctypes.c_uint64)]
+                ("log2_cost", ctypes.c_double), ("workspace_per_batch", ctypes.c_uint64),
+                ("bond", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
@@ -136,6 +138,9 @@ def lib() -> ctypes.CDLL:
     L.tnc_amplitudes_noalloc.argtypes = [vp, i32, vp, i32, i32, vp, vp]
     L.tnc_noalloc_scratch_bytes.argtypes = []
     L.tnc_noalloc_scratch_bytes.restype = u64
+    L.tnc_debug_lds_conflicts.argtypes = [vp, i32, vp]
+    L.tnc_profile_launches.argtypes = [vp, vp, ctypes.c_int64, vp]
+    L.tnc_plan_passes.argtypes = [vp, i32, vp, i32, vp]
     L.tnc_debug_workspace_c128.argtypes = [vp, i32, i32, ctypes.POINTER(u64)]
     L.tnc_debug_amplitudes_c128.argtypes = [vp, i32, vp, i32, vp, vp, u64, vp]
     L.tnc_logxeb.argtypes = [vp, i32, i32, vp, i32, vp, vp]
@@ -197,7 +202,7 @@ def _gate_array(gates: Sequence):
     return garr
 
 
-_OPTION_KEYS = ("max_tile_bits", "reg_bits", "low_bits", "math", "late_fold", "reg_adapt")
+_OPTION_KEYS = ("max_tile_bits", "reg_bits", "low_bits", "math", "late_fold", "reg_adapt", "bond")
 
 
 def _options(options: dict) -> Options:
@@ -329,6 +334,22 @@ class Plan:
         _check(lib().tnc_debug_execute_host(self._h, bits.shape[0], bits.ctypes.data, int(k), out.ctypes.data))
         return out
 
+    def passes(self, k: int) -> list:
+        """The sweep's HBM passes in launch order (``tnc_plan_passes``)."""
+        n = ctypes.c_int32()
+        _check(lib().tnc_plan_passes(self._h, int(k), None, 0, ctypes.byref(n)))
+        buf = np.zeros(7 * max(1, n.value), dtype=np.int32)
+        _check(lib().tnc_plan_passes(self._h, int(k), buf.ctypes.data, n.value, ctypes.byref(n)))
+        keys = ("low_bits", "win_lo", "win_len", "reg_bits", "updates", "phases", "fused_phases")
+        return [dict(zip(keys, map(int, buf[7 * i:7 * i + 7]))) for i in range(n.value)]
+
+    def debug_lds_conflicts(self, k: int) -> dict:
+        """Register phases of the pass tables whose bank-cycle lane groups
+        meet a slot twice (``tnc_debug_lds_conflicts``)."""
+        st = np.zeros(3, dtype=np.int64)
+        _check(lib().tnc_debug_lds_conflicts(self._h, int(k), st.ctypes.data))
+        return {"phases": int(st[0]), "conflicted_16": int(st[1]), "conflicted_32": int(st[2])}
+
     def debug_emulate_device(self, bits: np.ndarray, k: int, storage: int = STORE_C64) -> np.ndarray:
         bits = np.ascontiguousarray(bits, dtype=np.uint8)
         out = np.empty((bits.shape[0], 1 << k), dtype=np.complex128)
@@ -408,6 +429,17 @@ def profile_end() -> dict:
     pr = Profile()
     _check(lib().tnc_profile_end(ctypes.byref(pr)))
     return pr.as_dict()
+
+
+def profile_launches():
+    """(class, ms) of every launch timed by the last ``profile_end``, in issue
+    order (class 0 build-up / resolution, 1 pass, 2 late phase)."""
+    n = ctypes.c_int64()
+    _check(lib().tnc_profile_launches(None, None, 0, ctypes.byref(n)))
+    cls = np.zeros(max(1, n.value), dtype=np.int32)
+    ms = np.zeros(max(1, n.value), dtype=np.float64)
+    _check(lib().tnc_profile_launches(cls.ctypes.data, ms.ctypes.data, n.value, ctypes.byref(n)))
+    return list(zip(cls[:n.value].tolist(), ms[:n.value].tolist()))
 
 
 def logxeb(amps, k: int, n_qubits: int, select=None, stream=None):

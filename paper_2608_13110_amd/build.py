@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtnc.so")
 
 HIP_SOURCES = ["kernels.hip", "tnc_api.cpp", "serve.cpp", "autotune.cpp", "ring.cpp"]
-CXX_SOURCES = ["plan.cpp", "late.cpp"]
+CXX_SOURCES = ["plan.cpp", "plan4.cpp", "late.cpp"]
 ARCH = os.environ.get("TNC_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]

@@ -30,8 +30,9 @@ struct ScaleMap {
 
 // One boundary-tensor update inside a pass (16 bytes).  Within a register
 // phase, op b acts on the pairs along register bit b; ops b >= 1 are
-// controlled by register bit b-1, op 0 by the tile bit `cloc` of the thread
-// part (cloc < 0: no control), or op 0 is the phase's DUP.
+// controlled by register bit b-1, op 0 by a thread bit (DevPhase.cloc0) or
+// by nothing, or op 0 is the phase's DUP.  cloc: op 0's control as a local
+// tile bit (-1: none; a planner record, not read by the kernels).
 // Matrices: mats[(mat*4 + var)*16 ..+16): [ctl][k00 k01 k10 k11 as (re, im)],
 // var = 2*x[xrow0] + x[xrow1] (an absent row reads as 0).
 struct DevOp {
@@ -45,24 +46,29 @@ struct DevOp {
 static_assert(sizeof(DevOp) == 16, "DevOp layout");
 
 // A register phase: n_ops consecutive ops from op_begin, run with local tile
-// bits reg[0..R-1] held in registers (register bit b <-> local bit reg[b]).
-// first_dup: op 0 copies the register half with bit 0 clear onto the half
-// with bit 0 set (the top-slot expand of odd depth).  cloc0: op 0's control
-// as a local tile bit of the thread part (-1: uncontrolled).
+// bits reg[0..R-1] held in registers (register bit b <-> local bit reg[b]);
+// the thread bits sit on the other tile bits in the order the planner chose
+// (their LDS offsets are in the phase's offset table).  first_dup: op 0
+// copies the register half with bit 0 clear onto the half with bit 0 set (the
+// top-slot expand of odd depth).  cloc0: the thread bit whose value controls
+// op 0 (-1: uncontrolled).
 struct DevPhase {
   int32_t op_begin;
   int8_t n_ops;
   int8_t first_dup;
   int8_t reg[8];
   int8_t cloc0;
-  int8_t pad;   // 1: a fused phase (three updates as one 8x8 on the matrix cores)
+  int8_t pad;   // 1: a fused phase (three updates as one 8x8 on the matrix cores);
+                // 2: a dense phase (n_ops / 2 dense 4x4 updates, update g on
+                // register bits (2g, 2g+1), its matrix rows in ops op_begin + 2g
+                // and op_begin + 2g + 1)
 };
 static_assert(sizeof(DevPhase) == 16, "DevPhase layout");
 
 // Launch parameters of one pass (a kernel argument).
 //   mats:  per op [var 4][ctl 2][k00 k01 k10 k11 as (re, im)]  (16 floats / var)
 // A phase's LDS offset table: one word per register entry (up to 2^5), then
-// (fused phases) one per thread bit: the offset of that tile bit alone.
+// one per thread bit: the offset of the tile bit it sits on.
 constexpr int kPhaseEntries = 32;
 constexpr int kPhaseOffs = 48;
 // Matrix-core operands of a fused phase: [control 2][lane 64] float4.
@@ -120,7 +126,7 @@ struct LateArgs {
 
 // One op of a late program (device copy of LateOp, plan.hpp).
 struct LateOpDev {
-  int32_t kind;  // 1 U1, 2 G4, 3 REMOVE
+  int32_t kind;  // 1 U1, 2 G4, 3 REMOVE (xrow >= 0: m[8..16) when x[xrow] = 1), 6 REMOVE2
   int32_t a;
   int32_t xrow;
   int32_t pad;

@@ -222,6 +222,25 @@ __device__ __attribute__((always_inline)) inline unsigned xcd_block(uint32_t bx,
   return (gx & 7u) == 0u ? (bx & 7u) * (gx >> 3) + (bx >> 3) : bx;
 }
 
+// LDS slots of the iteration parts it << shift (it < 32) of the entries a
+// thread stages: swz is linear, so the slot of it << shift is the XOR of the
+// slots of its set bits, taken from five values computed once per thread.
+struct IterSlots {
+  uint32_t b[5];
+  __device__ __attribute__((always_inline)) explicit IterSlots(int shift) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) b[q] = swz(1u << (shift + q));
+  }
+  // `it` is a compile-time constant in the unrolled staging loops
+  __device__ __attribute__((always_inline)) uint32_t of(int it) const {
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+      if ((it >> q) & 1) s ^= b[q];
+    return s;
+  }
+};
+
 template <int R, bool MULTI, bool WU, int NT>
 __device__ __attribute__((always_inline)) inline void pass_body(const PassArgs& a, float2* lds, uint32_t bx,
                                                                 uint32_t gx) {
@@ -242,17 +261,28 @@ __device__ __attribute__((always_inline)) inline void pass_body(const PassArgs& 
   char* region = reinterpret_cast<char*>(lds) + ((size_t)tile_in_block << (T + 3));
   const int tpt = 1 << TB;
 
+  // LDS slot of entry i = (it * tpt + tt) * 2: the thread part and the
+  // (wave-uniform) iteration part occupy disjoint bits, so their slots XOR;
+  // the iteration part's slot is the XOR of the slots of its set bits
+  const uint32_t st = swz(tt * 2u);
+  const IterSlots isl(TB + 1);
   if (active) {
+    // every load in flight before the first LDS write
+    float4 ld[E / 2];
 #pragma unroll
     for (int it = 0; it < E / 2; ++it) {
       const uint32_t i = (uint32_t)(it * tpt + (int)tt) * 2u;
-      const float4 val = *reinterpret_cast<const float4*>(Bt + tile_offset(i, a.lo_bits, a.win_lo));
-      *reinterpret_cast<float4*>(region + ((size_t)swz(i) << 3)) = val;
+      ld[it] = *reinterpret_cast<const float4*>(Bt + tile_offset(i, a.lo_bits, a.win_lo));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int it = 0; it < E / 2; ++it) {
+      const uint32_t si = isl.of(it) ^ st;
+      *reinterpret_cast<float4*>(region + pair_slot(si)) = pair_order(ld[it], pair_swapped(si));
     }
   }
   __syncthreads();
 
-  const uint32_t tmask = (1u << T) - 1u;
   PhaseCtx<R> ctx;
   ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
   ctx.tb = 0;
@@ -261,7 +291,7 @@ __device__ __attribute__((always_inline)) inline void pass_body(const PassArgs& 
   for (int p = 0; p < a.n_phases; ++p) {
     const DevPhase P = load_phase(a.phases, p);
     phase_dispatch<R, WU>(reinterpret_cast<char*>(lds), rbase, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs,
-                          ctx, tt, tmask, a.fmats + (size_t)p * kFusedWords, TB);
+                          ctx, tt, TB, a.fmats + (size_t)p * kFusedWords);
     __syncthreads();
   }
 
@@ -269,8 +299,9 @@ __device__ __attribute__((always_inline)) inline void pass_body(const PassArgs& 
 #pragma unroll
     for (int it = 0; it < E / 2; ++it) {
       const uint32_t i = (uint32_t)(it * tpt + (int)tt) * 2u;
-      const float4 val = *reinterpret_cast<const float4*>(region + ((size_t)swz(i) << 3));
-      *reinterpret_cast<float4*>(Bt + tile_offset(i, a.lo_bits, a.win_lo)) = val;
+      const uint32_t si = isl.of(it) ^ st;
+      const float4 val = *reinterpret_cast<const float4*>(region + pair_slot(si));
+      *reinterpret_cast<float4*>(Bt + tile_offset(i, a.lo_bits, a.win_lo)) = pair_order(val, pair_swapped(si));
     }
   }
 }
@@ -333,29 +364,43 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_p
   // slots; the iteration part is the same for every thread (scalar work).
   const uint64_t slot_t = scale_slot(boff, a.in_map) |
                           scale_slot(tile_offset(tt * (uint32_t)U, a.lo_bits, a.win_lo), a.in_map);
+  const uint32_t st = swz(tt * (uint32_t)U);  // LDS slot of the thread part (see k_pass)
+  const IterSlots isl(TB + (U == 4 ? 2 : 1));
   if (active) {
+    // every load (and its scale) in flight before the first LDS write
+    uint4 ld[E / U];
+    float scl[E / U];
 #pragma unroll
     for (int it = 0; it < E / U; ++it) {
       const uint32_t i = (uint32_t)(it * tpt + (int)tt) * (uint32_t)U;
       const uint64_t g = boff + tile_offset(i, a.lo_bits, a.win_lo);
       const uint64_t slot_i = scale_slot(tile_offset((uint32_t)(it * tpt) * (uint32_t)U, a.lo_bits, a.win_lo), a.in_map);
-      const float sc = sin[slot_t | slot_i];
+      scl[it] = sin[slot_t | slot_i];
       if constexpr (U == 4) {
-        const uint4 w = *reinterpret_cast<const uint4*>(Bw + g);
-        const float2 e0 = unpack16<S>(w.x, sc), e1 = unpack16<S>(w.y, sc);
-        const float2 e2 = unpack16<S>(w.z, sc), e3 = unpack16<S>(w.w, sc);
-        *reinterpret_cast<float4*>(region + ((size_t)swz(i) << 3)) = make_float4(e0.x, e0.y, e1.x, e1.y);
-        *reinterpret_cast<float4*>(region + ((size_t)swz(i + 2u) << 3)) = make_float4(e2.x, e2.y, e3.x, e3.y);
+        ld[it] = *reinterpret_cast<const uint4*>(Bw + g);
       } else {
         const uint2 w = *reinterpret_cast<const uint2*>(Bw + g);
-        const float2 e0 = unpack16<S>(w.x, sc), e1 = unpack16<S>(w.y, sc);
-        *reinterpret_cast<float4*>(region + ((size_t)swz(i) << 3)) = make_float4(e0.x, e0.y, e1.x, e1.y);
+        ld[it] = make_uint4(w.x, w.y, 0u, 0u);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int it = 0; it < E / U; ++it) {
+      const float sc = scl[it];
+      const uint32_t si = isl.of(it) ^ st;  // swz(i); swz(i + 2) = si ^ 2
+      const uint4 w = ld[it];
+      const float2 e0 = unpack16<S>(w.x, sc), e1 = unpack16<S>(w.y, sc);
+      *reinterpret_cast<float4*>(region + pair_slot(si)) =
+          pair_order(make_float4(e0.x, e0.y, e1.x, e1.y), pair_swapped(si));
+      if constexpr (U == 4) {
+        const float2 e2 = unpack16<S>(w.z, sc), e3 = unpack16<S>(w.w, sc);
+        *reinterpret_cast<float4*>(region + pair_slot(si ^ 2u)) =
+            pair_order(make_float4(e2.x, e2.y, e3.x, e3.y), pair_swapped(si));
       }
     }
   }
   __syncthreads();
 
-  const uint32_t tmask = (1u << T) - 1u;
   PhaseCtx<R> ctx;
   ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
   ctx.tb = 0;
@@ -363,8 +408,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_p
   for (int p = 0; p < a.n_phases; ++p) {
     const DevPhase P = load_phase(a.phases, p);
     phase_dispatch<R, WU>(reinterpret_cast<char*>(lds), (uint32_t)tile_in_block << (T + 3), P,
-                          (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, tmask,
-                          a.fmats + (size_t)p * kFusedWords, TB);
+                          (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, TB,
+                          a.fmats + (size_t)p * kFusedWords);
     __syncthreads();
   }
 
@@ -373,10 +418,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_p
   // their iteration part: one running maximum per block)
   if (active) {
     float m[4] = {0.f, 0.f, 0.f, 0.f};
+    const uint32_t st2 = swz(tt * 2u);
+    const IterSlots isl2(TB + 1);
 #pragma unroll
     for (int it = 0; it < E / 2; ++it) {
       const uint32_t i = (uint32_t)(it * tpt + (int)tt) * 2u;
-      const float4 v = *reinterpret_cast<const float4*>(region + ((size_t)swz(i) << 3));
+      const float4 v = *reinterpret_cast<const float4*>(region + pair_slot(isl2.of(it) ^ st2));  // order irrelevant
       const float am = fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w)));
       const uint32_t q = (i >> blk_bits) & 3u;
 #pragma unroll
@@ -399,9 +446,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_p
       const uint64_t g = boff + tile_offset(i, a.lo_bits, a.win_lo);
       const uint32_t q = (i >> blk_bits) & 3u;
       const float iv = q == 0 ? inv[0] : q == 1 ? inv[1] : q == 2 ? inv[2] : inv[3];
-      const float4 v0 = *reinterpret_cast<const float4*>(region + ((size_t)swz(i) << 3));
+      const uint32_t si = isl.of(it) ^ st;
+      const float4 v0 = pair_order(*reinterpret_cast<const float4*>(region + pair_slot(si)), pair_swapped(si));
       if constexpr (U == 4) {
-        const float4 v1 = *reinterpret_cast<const float4*>(region + ((size_t)swz(i + 2u) << 3));
+        const float4 v1 = pair_order(*reinterpret_cast<const float4*>(region + pair_slot(si ^ 2u)), pair_swapped(si));
         *reinterpret_cast<uint4*>(Bw + g) = make_uint4(pack16<S>(v0.x, v0.y, iv), pack16<S>(v0.z, v0.w, iv),
                                                        pack16<S>(v1.x, v1.y, iv), pack16<S>(v1.z, v1.w, iv));
       } else {
@@ -656,7 +704,6 @@ static void emulate_pass_r(const PassArgs& a) {
   const int tbits = a.h - T;
   std::vector<float2> lds((size_t)1 << T);
   char* region = reinterpret_cast<char*>(lds.data());
-  const uint32_t tmask = (1u << T) - 1u;
   const bool s16 = a.store == STORE_F16 || a.store == STORE_BF16;
   auto dec = [&](uint32_t w, float sc) {
     return a.store == STORE_F16 ? unpack16<STORE_F16>(w, sc) : unpack16<STORE_BF16>(w, sc);
@@ -674,16 +721,15 @@ static void emulate_pass_r(const PassArgs& a) {
     for (int tt = 0; tt < tpt; ++tt)
       for (int it = 0; it < E / 2; ++it) {
         const uint32_t i = (uint32_t)(it * tpt + tt) * 2u;
-        float2* dst = reinterpret_cast<float2*>(region + ((size_t)swz(i) << 3));
         if (s16) {
           const uint64_t g = boff + tile_offset(i, a.lo_bits, a.win_lo);
           const float sc = a.scale_in[batch * a.scale_stride + (long long)scale_slot(g, a.in_map)];
-          dst[0] = dec(Bw[g], sc);
-          dst[1] = dec(Bw[g + 1], sc);
+          lds[swz(i)] = dec(Bw[g], sc);
+          lds[swz(i + 1u)] = dec(Bw[g + 1], sc);
         } else {
           const float2* src = Bt + tile_offset(i, a.lo_bits, a.win_lo);
-          dst[0] = src[0];
-          dst[1] = src[1];
+          lds[swz(i)] = src[0];
+          lds[swz(i + 1u)] = src[1];
         }
       }
     PhaseCtx<R> ctx;
@@ -692,14 +738,14 @@ static void emulate_pass_r(const PassArgs& a) {
     ctx.uniform = false;
     for (int p = 0; p < a.n_phases; ++p) {
       const DevPhase P = load_phase(a.phases, p);
-      if (P.pad) {
+      if (P.pad == 1) {
         if constexpr (R >= 3)
           emulate_tri<R>(region, P, a.poffs + p * kPhaseOffs, a.fmats + (size_t)p * kFusedWords,
                          a.rmats + (size_t)batch * a.rstride, TB);
         continue;
       }
       for (int tt = 0; tt < tpt; ++tt)
-        phase_dispatch<R>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, (uint32_t)tt, tmask);
+        phase_dispatch<R>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, (uint32_t)tt, TB);
     }
     if (s16) {
       const int nblk = 1 << (T - blk_bits);
@@ -722,10 +768,9 @@ static void emulate_pass_r(const PassArgs& a) {
     for (int tt = 0; tt < tpt; ++tt)
       for (int it = 0; it < E / 2; ++it) {
         const uint32_t i = (uint32_t)(it * tpt + tt) * 2u;
-        const float2* src = reinterpret_cast<const float2*>(region + ((size_t)swz(i) << 3));
         float2* dst = Bt + tile_offset(i, a.lo_bits, a.win_lo);
-        dst[0] = src[0];
-        dst[1] = src[1];
+        dst[0] = lds[swz(i)];
+        dst[1] = lds[swz(i + 1u)];
       }
   }
 }
@@ -1038,6 +1083,8 @@ __device__ __attribute__((always_inline)) inline void late_ops_body(const LateOp
         for (int u = 0; u < 4; ++u) st[idx[u]] = y[u];
       }
     } else if (op.kind == 3) {
+      // an output-bit variant (xrow >= 0) takes the second set of matrices
+      const double2* m = op.m + ((op.xrow >= 0 && (a.bits[(size_t)b * a.n + op.xrow] & 1)) ? 8 : 0);
       const int items = (1 << (live - 1)) << (sb - 1);
       for (int w = threadIdx.x; w < items; w += blockDim.x) {
         const int ra = (w >> (sb - 1)) << (l + 1);
@@ -1045,12 +1092,33 @@ __device__ __attribute__((always_inline)) inline void late_ops_body(const LateOp
         const int t0 = (w & ((1 << (sb - 1)) - 1)) << 1;
         const int ia = (ra << sb) | t0, ib = (rb << sb) | t0;
         const double2 x0 = st[ia], x1 = st[ia | 1], y0 = st[ib], y1 = st[ib | 1];
-        const double2 o0a = zfma2(op.m[0], x0, op.m[1], x1), o0b = zfma2(op.m[4], y0, op.m[5], y1);
-        const double2 o1a = zfma2(op.m[2], x0, op.m[3], x1), o1b = zfma2(op.m[6], y0, op.m[7], y1);
+        const double2 o0a = zfma2(m[0], x0, m[1], x1), o0b = zfma2(m[4], y0, m[5], y1);
+        const double2 o1a = zfma2(m[2], x0, m[3], x1), o1b = zfma2(m[6], y0, m[7], y1);
         st[ia] = make_double2(o0a.x + o0b.x, o0a.y + o0b.y);
         st[ia | 1] = make_double2(o1a.x + o1b.x, o1a.y + o1b.y);
       }
       ++l;
+    } else if (op.kind == 6) {
+      // two slots (l, l+1) at once: row u = bit l + 2 bit (l+1) takes C_u
+      const int items = (1 << (live - 2)) << (sb - 1);
+      for (int w = threadIdx.x; w < items; w += blockDim.x) {
+        const int r0 = (w >> (sb - 1)) << (l + 2);
+        const int t0 = (w & ((1 << (sb - 1)) - 1)) << 1;
+        double2 o0 = make_double2(0.0, 0.0), o1 = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int iu = ((r0 | (u << l)) << sb) | t0;
+          const double2 x0 = st[iu], x1 = st[iu | 1];
+          const double2 p0 = zfma2(op.m[4 * u], x0, op.m[4 * u + 1], x1);
+          const double2 p1 = zfma2(op.m[4 * u + 2], x0, op.m[4 * u + 3], x1);
+          o0 = make_double2(o0.x + p0.x, o0.y + p0.y);
+          o1 = make_double2(o1.x + p1.x, o1.y + p1.y);
+        }
+        const int i0 = (r0 << sb) | t0;
+        st[i0] = o0;
+        st[i0 | 1] = o1;
+      }
+      l += 2;
     }
     __syncthreads();
   }

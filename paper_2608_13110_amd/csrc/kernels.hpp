@@ -8,16 +8,21 @@
 #include <cstdint>
 
 #include "device_tables.hpp"
+#include "lds_layout.hpp"
 
 namespace tnc {
 
 constexpr int kBlock = 256;
 
-// LDS placement of tile entry i: bits 1..5 are XORed with bits 6..10 and
-// 11..15 so that strided register layouts spread over the banks.  The map is
-// linear over GF(2): swz(a ^ b) = swz(a) ^ swz(b); bit 0 is kept, so the
-// pair (2i, 2i+1) stays adjacent and ordered.
-TNC_HD inline uint32_t swz(uint32_t i) { return i ^ ((((i >> 6) ^ (i >> 11)) & 31u) << 1); }
+// A float4 holding the entry pair (i, i + 1) in index order, as stored in
+// (or to be stored to) its LDS slot, whose order is swapped when s is set.
+// A bitwise select (no branch, no wait on a load beyond this value's own).
+TNC_HD inline float4 pair_order(float4 v, bool s) {
+  const uint32_t m = 0u - (uint32_t)s;
+  const uint32_t x = __float_as_uint(v.x), y = __float_as_uint(v.y), z = __float_as_uint(v.z), w = __float_as_uint(v.w);
+  return make_float4(__uint_as_float(x ^ ((x ^ z) & m)), __uint_as_float(y ^ ((y ^ w) & m)),
+                     __uint_as_float(z ^ ((z ^ x) & m)), __uint_as_float(w ^ ((w ^ y) & m)));
+}
 
 // Offset of local tile entry i inside its batch, without the block part.
 TNC_HD inline uint64_t tile_offset(uint32_t i, int lo_bits, int win_lo) {
@@ -31,19 +36,6 @@ TNC_HD inline uint64_t block_offset(uint64_t blk, int lo_bits, int win_lo, int w
   const uint64_t low = blk & ((1ull << gap) - 1ull);
   const uint64_t high = blk >> gap;
   return (low << lo_bits) | (high << (win_lo + win_len));
-}
-
-// Scatter the bits of `x` into the set bits of `mask` (ascending).
-TNC_HD inline uint32_t pdep32(uint32_t x, uint32_t mask) {
-  uint32_t r = 0;
-  int b = 0;
-  while (mask) {
-    const uint32_t low = mask & (~mask + 1u);
-    if ((x >> b) & 1u) r |= low;
-    mask &= mask - 1u;
-    ++b;
-  }
-  return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -157,6 +149,37 @@ TNC_HD inline Regs<R> op_reg(Regs<R> v, const TNC_TBL float* __restrict__ m) {
   return v;
 }
 
+// A dense 4x4 on register bits (A, A+1): the entries with u = bit A +
+// 2 bit (A+1) become M (e_0 .. e_3); m: M row-major, 32 floats (re, im).
+template <int R, int A, class P>
+TNC_HD inline Regs<R> op_dense(Regs<R> v, P m) {
+  float k[32];
+#pragma unroll
+  for (int e = 0; e < 32; ++e) k[e] = m[e];
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    if (i & (3 << A)) continue;
+    float ix[4], iy[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ix[u] = v.x[i | (u << A)];
+      iy[u] = v.y[i | (u << A)];
+    }
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      float ox = 0.f, oy = 0.f;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ox = ox + k[8 * o + 2 * u] * ix[u] - k[8 * o + 2 * u + 1] * iy[u];
+        oy = oy + k[8 * o + 2 * u] * iy[u] + k[8 * o + 2 * u + 1] * ix[u];
+      }
+      v.x[i | (o << A)] = ox;
+      v.y[i | (o << A)] = oy;
+    }
+  }
+  return v;
+}
+
 template <int R, int A, class P>
 TNC_HD inline Regs<R> op_sel(Regs<R> v, P k) {
 #pragma unroll
@@ -188,7 +211,7 @@ typedef float tnc_floatx4 __attribute__((ext_vector_type(4)));
 template <int R>
 struct PhaseCtx {
   const TNC_TBL float* __restrict__ rm;  // the tile's batch: resolved matrices, 16 floats per op
-  uint32_t tb;
+  uint32_t tb;                           // the thread's index within its tile
   bool uniform;
 };
 
@@ -241,7 +264,7 @@ TNC_HD inline Regs<R> stair(Regs<R> v, const DevPhase& P, const PhaseCtx<R>& c) 
     if constexpr (K0 == 1) {
       v = op_sel<R, 0>(v, m);
     } else {
-      const bool hi = (c.tb >> P.cloc0) & 1u;
+      const bool hi = (c.tb >> P.cloc0) & 1u;  // op 0's control: thread bit cloc0
       if (c.uniform) {
         // thread-controlled: pick the values per thread from the
         // wave-uniform pair of matrices (a per-thread address would need
@@ -265,22 +288,30 @@ TNC_HD inline Regs<R> stair(Regs<R> v, const DevPhase& P, const PhaseCtx<R>& c) 
   return stair_rest<R, 1, N>(v, c, P.op_begin);
 }
 
+// LDS byte offset of a thread's base entry in a phase: thread bit t adds the
+// tile bit the planner placed it on, whose offset is po[kPhaseEntries + t]
+// (wave-uniform table reads: scalar loads).
+TNC_HD inline uint32_t phase_thread_base(uint32_t rbase, const TNC_TBL uint32_t* po, uint32_t tt, int TB) {
+  uint32_t vb = rbase;
+#pragma unroll
+  for (int t = 0; t < kMaxThreadBitsDev; ++t)
+    if (t < TB) vb ^= (0u - ((tt >> t) & 1u)) & po[kPhaseEntries + t];
+  return vb;
+}
+
 // One register phase: LDS -> registers (phase layout), the phase's ops,
 // registers -> LDS.  Each thread writes back exactly the entries it read.
 // The tile sits at byte offset `rbase` of `base`, with rbase's bits above
-// the tile's own (rbase = 0 or a multiple of 2^(T+3)), so an entry's byte
-// offset is rbase | (swz(thread bits) << 3) ^ po[i].  po[i] (from the pass
-// tables) is swz(r_i) << 3 for the tile index r_i of register entry i.
+// the tile's own (rbase = 0 or a multiple of 2^(T+3)).  po[i] (from the pass
+// tables) is swz(r_i) << 3 for the tile index r_i of register entry i; the
+// swizzle is linear, so an entry's offset is the thread's base ^ po[i].
 template <int R, int N, int K0>
 TNC_HD inline void phase_exec(char* base, uint32_t rbase, const DevPhase& P, const TNC_TBL uint32_t* po,
-                              const PhaseCtx<R>& c0, uint32_t tt, uint32_t tmask) {
+                              const PhaseCtx<R>& c0, uint32_t tt, int TB) {
   constexpr int E = 1 << R;
-  uint32_t rmask = 0;
-#pragma unroll
-  for (int b = 0; b < R; ++b) rmask |= 1u << P.reg[b];
   PhaseCtx<R> c = c0;
-  c.tb = pdep32(tt, tmask & ~rmask);
-  const uint32_t vbase = rbase | (swz(c.tb) << 3);
+  c.tb = tt;
+  const uint32_t vbase = phase_thread_base(rbase, po, tt, TB);
   uint32_t off[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) off[i] = vbase ^ po[i];
@@ -296,12 +327,36 @@ TNC_HD inline void phase_exec(char* base, uint32_t rbase, const DevPhase& P, con
   for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(base + off[i]) = make_float2(v.x[i], v.y[i]);
 }
 
+// A dense phase: G dense 4x4 updates, update g on register bits (2g, 2g+1)
+// with the 32 floats of ops op_begin + 2g, op_begin + 2g + 1 (rows 0-1,
+// rows 2-3).  Same register entries and LDS placement as phase_exec.
+template <int R, int G>
+TNC_HD inline void phase_dense(char* base, uint32_t rbase, const DevPhase& P, const TNC_TBL uint32_t* po,
+                               const PhaseCtx<R>& c, uint32_t tt, int TB) {
+  constexpr int E = 1 << R;
+  const uint32_t vbase = phase_thread_base(rbase, po, tt, TB);
+  uint32_t off[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) off[i] = vbase ^ po[i];
+  Regs<R> v;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const float2 t = *reinterpret_cast<const float2*>(base + off[i]);
+    v.x[i] = t.x;
+    v.y[i] = t.y;
+  }
+  v = op_dense<R, 0>(v, c.rm + (size_t)P.op_begin * 16);
+  if constexpr (G >= 2) v = op_dense<R, 2>(v, c.rm + (size_t)(P.op_begin + 2) * 16);
+#pragma unroll
+  for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(base + off[i]) = make_float2(v.x[i], v.y[i]);
+}
+
 template <int R, int N>
 TNC_HD inline void phase_forms(char* base, uint32_t rbase, const DevPhase& P, const TNC_TBL uint32_t* po,
-                               const PhaseCtx<R>& c, uint32_t tt, uint32_t tmask) {
-  if (P.first_dup) phase_exec<R, N, 0>(base, rbase, P, po, c, tt, tmask);
-  else if (P.cloc0 < 0) phase_exec<R, N, 1>(base, rbase, P, po, c, tt, tmask);
-  else phase_exec<R, N, 2>(base, rbase, P, po, c, tt, tmask);
+                               const PhaseCtx<R>& c, uint32_t tt, int TB) {
+  if (P.first_dup) phase_exec<R, N, 0>(base, rbase, P, po, c, tt, TB);
+  else if (P.cloc0 < 0) phase_exec<R, N, 1>(base, rbase, P, po, c, tt, TB);
+  else phase_exec<R, N, 2>(base, rbase, P, po, c, tt, TB);
 }
 
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -326,13 +381,7 @@ __device__ __attribute__((always_inline)) inline void phase_tri(char* base, uint
   const int lane = (int)(tt & 63u);
   const float4 a0 = F[lane];
   const float4 a1 = F[64 + lane];
-  uint32_t vb = rbase;
-#pragma unroll
-  for (int t = 0; t < kMaxThreadBitsDev; ++t)
-    if (t < TB) {
-      const uint32_t w = po[kPhaseEntries + t];  // wave-uniform: a scalar load
-      vb ^= (0u - ((tt >> t) & 1u)) & w;
-    }
+  const uint32_t vb = phase_thread_base(rbase, po, tt, TB);
   uint32_t off[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) off[i] = vb ^ po[i];
@@ -381,21 +430,32 @@ __device__ __attribute__((always_inline)) inline void phase_tri(char* base, uint
 #endif
 
 // Register phases with an instantiated form: a canonical phase of 1..R
-// updates, or (fused phases) 3..R+2 updates; the planner checks every phase
-// against this before the tables reach the device.
-TNC_HD constexpr bool phase_form_exists(int R, int n_ops, bool fused) {
-  return fused ? (R >= 3 && n_ops >= 3 && n_ops <= R + 2 && n_ops <= 7) : (n_ops >= 1 && n_ops <= R && R <= 5);
+// updates (form 0), a fused phase of 3..R+2 updates (form 1), or a dense
+// phase of one 4x4 (two ops; R >= 2) or two (four ops; R >= 4) (form 2);
+// the planner checks every phase against this before the tables reach the
+// device.
+TNC_HD constexpr bool phase_form_exists(int R, int n_ops, int form) {
+  return form == 1   ? (R >= 3 && n_ops >= 3 && n_ops <= R + 2 && n_ops <= 7)
+         : form == 2 ? ((n_ops == 2 && R >= 2) || (n_ops == 4 && R >= 4)) && R <= 5
+                     : (n_ops >= 1 && n_ops <= R && R <= 5);
 }
 
 // TRI: the kernel runs fused phases (P.pad = 1); the host plans them only for
 // kernels whose waves each lie inside one tile.
 template <int R, bool TRI = false>
 TNC_HD inline void phase_dispatch(char* base, uint32_t rbase, const DevPhase& P, const TNC_TBL uint32_t* po,
-                                  const PhaseCtx<R>& c, uint32_t tt, uint32_t tmask, const float4* fm = nullptr,
-                                  int TB = 0) {
+                                  const PhaseCtx<R>& c, uint32_t tt, int TB, const float4* fm = nullptr) {
+  if (P.pad == 2) {
+    if constexpr (R >= 2) {
+      if (P.n_ops == 2) phase_dense<R, 1>(base, rbase, P, po, c, tt, TB);
+      if constexpr (R >= 4)
+        if (P.n_ops == 4) phase_dense<R, 2>(base, rbase, P, po, c, tt, TB);
+    }
+    return;
+  }
 #if defined(__HIP_DEVICE_COMPILE__)
   if constexpr (TRI && R >= 3) {
-    if (P.pad) {
+    if (P.pad == 1) {
       // update b > 2 targets register bit b - 2: up to R + 2 updates
       switch (P.n_ops) {
         case 3: phase_tri<R, 3>(base, rbase, P, po, fm, c, tt, TB); break;
@@ -410,11 +470,11 @@ TNC_HD inline void phase_dispatch(char* base, uint32_t rbase, const DevPhase& P,
   }
 #endif
   switch (P.n_ops) {
-    case 1: phase_forms<R, 1>(base, rbase, P, po, c, tt, tmask); break;
-    case 2: if constexpr (R >= 2) phase_forms<R, 2>(base, rbase, P, po, c, tt, tmask); break;
-    case 3: if constexpr (R >= 3) phase_forms<R, 3>(base, rbase, P, po, c, tt, tmask); break;
-    case 4: if constexpr (R >= 4) phase_forms<R, 4>(base, rbase, P, po, c, tt, tmask); break;
-    case 5: if constexpr (R >= 5) phase_forms<R, 5>(base, rbase, P, po, c, tt, tmask); break;
+    case 1: phase_forms<R, 1>(base, rbase, P, po, c, tt, TB); break;
+    case 2: if constexpr (R >= 2) phase_forms<R, 2>(base, rbase, P, po, c, tt, TB); break;
+    case 3: if constexpr (R >= 3) phase_forms<R, 3>(base, rbase, P, po, c, tt, TB); break;
+    case 4: if constexpr (R >= 4) phase_forms<R, 4>(base, rbase, P, po, c, tt, TB); break;
+    case 5: if constexpr (R >= 5) phase_forms<R, 5>(base, rbase, P, po, c, tt, TB); break;
     default: break;  // excluded on the host (phase_form_exists)
   }
 }

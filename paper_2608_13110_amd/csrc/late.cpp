@@ -63,18 +63,25 @@ int build_late(const Plan& p, const Schedule& s, LatePlan* out, std::string* err
   out->final_xrow = fin.xrow;
   if (fin.kind == L_DOT) out->dot = fin.m;
   const int nbody = int(L.size()) - 1;
-  std::vector<int> rpos;
+  // removals and the slots they consume: slots_to[i] = slots removed by
+  // removals 0..i-1
+  std::vector<int> rpos, slots_to(1, 0);
   for (int i = 0; i < nbody; ++i)
-    if (L[i].kind == L_REMOVE) rpos.push_back(i);
+    if (L[i].kind == L_REMOVE || L[i].kind == L_REMOVE2) {
+      rpos.push_back(i);
+      slots_to.push_back(slots_to.back() + (L[i].kind == L_REMOVE2 ? 2 : 1));
+    }
   const int nrem = int(rpos.size());
-  // k = 0: fold up to 12 removals (the state is one qubit).  k >= 1: folding
-  // j removals costs O(2^(3k+j)) on the host and shrinks the first launch's
-  // FP64 output to 2^(m-j) rows; worth it for large tensors only.  With no
-  // removal folded, the join matrix is Z_early itself and every late op runs
-  // on the device.
-  int j1;
+  // k = 0: fold removals of up to 12 slots (the state is one qubit), but not
+  // a removal with an output-bit variant (the first launch has one variant
+  // row, the final one's).  k >= 1: folding j removals costs O(2^(3k+j)) on
+  // the host and shrinks the first launch's FP64 output to 2^(m-j) rows;
+  // worth it for large tensors only.  With no removal folded, the join
+  // matrix is Z_early itself and every late op runs on the device.
+  int j1;  // removals folded
   if (k == 0) {
-    j1 = std::min(nrem, 12);
+    j1 = 0;
+    while (j1 < nrem && slots_to[j1 + 1] <= 12 && L[rpos[j1]].xrow < 0) ++j1;
   } else {
     // 2^35-entry tensors (256 GiB of complex64) leave room for a join output
     // of 2^(h-j) x 16 B only with j = 7 (4 GiB; the fold takes ~4 s).  From
@@ -87,8 +94,9 @@ int build_late(const Plan& p, const Schedule& s, LatePlan* out, std::string* err
   const bool first_final = j1 == nrem;
   const int first_end = first_final ? nbody : (j1 == 0 ? 0 : rpos[j1 - 1] + 1);
 
-  // P_u for each assignment u of the folded removals
-  const int nu = 1 << j1;
+  // P_u for each assignment u of the folded slots
+  const int js = slots_to[j1];
+  const int nu = 1 << js;
   std::vector<std::vector<cd>> P(nu);
   for (int u = 0; u < nu; ++u) {
     std::vector<cd> cols((size_t)dim * dim, cd(0));
@@ -102,16 +110,20 @@ int build_late(const Plan& p, const Schedule& s, LatePlan* out, std::string* err
         const int b = (u >> l) & 1;
         cols_u1(cols, sb, 0, o.m.data() + 4 * b);
         ++l;
+      } else if (o.kind == L_REMOVE2) {
+        const int b = (u >> l) & 3;
+        cols_u1(cols, sb, 0, o.m.data() + 4 * b);
+        l += 2;
       }
     }
     P[u].swap(cols);
   }
   LateFirst& F = out->first;
-  F.j = j1;
+  F.j = js;
   F.final = first_final;
   const int ub = s.join_u_bits;
-  F.K = 1 << (ub + j1);
-  F.M = 1LL << (s.m_fix - ub - j1);
+  F.K = 1 << (ub + js);
+  F.M = 1LL << (s.m_fix - ub - js);
   // unpermuted J: Ju[kk][t]
   std::vector<cd> Ju((size_t)F.K * dim, cd(0));
   for (int u = 0; u < nu; ++u) {
@@ -166,14 +178,17 @@ int build_late(const Plan& p, const Schedule& s, LatePlan* out, std::string* err
   }
   // remaining launches
   if (!first_final) {
-    const int jmax = std::max(1, 12 - sb);
+    // each launch takes whole removals of at most jmax slots
+    const int jmax = std::max(2, 12 - sb);
     int done = j1;
     int pos = first_end;
     long long rows = F.M;
     while (done < nrem) {
-      const int j = std::min(nrem - done, jmax);
-      const bool last = done + j == nrem;
-      const int end = last ? nbody : rpos[done + j - 1] + 1;
+      int e = done + 1;
+      while (e < nrem && slots_to[e + 1] - slots_to[done] <= jmax) ++e;
+      const int j = slots_to[e] - slots_to[done];
+      const bool last = e == nrem;
+      const int end = last ? nbody : rpos[e - 1] + 1;
       LateOpsLaunch ln;
       ln.op_begin = pos;
       ln.op_end = end;
@@ -182,7 +197,7 @@ int build_late(const Plan& p, const Schedule& s, LatePlan* out, std::string* err
       ln.final = last;
       out->ops.push_back(ln);
       rows >>= j;
-      done += j;
+      done = e;
       pos = end;
     }
   }

@@ -2,6 +2,8 @@
 // tensor schedule (see plan.hpp for the formulation).
 #include "plan.hpp"
 
+#include "lds_layout.hpp"
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -420,6 +422,8 @@ int build_plan(int n, int d, const cd* one_qubit, int n_gate2, const Gate2In* ga
                const Options& opt, std::unique_ptr<Plan>* out, std::string* err) {
   if (n < 2 || d < 2) return fail(err, kErrDomain, "need n >= 2 qubits and d >= 2 layers");
   if (n > 4096 || d > 4096) return fail(err, kErrDomain, "n or d too large");
+  if (opt.bond != 0 && opt.bond != 2 && opt.bond != 4) return fail(err, kErrInvalid, "bond must be 0, 2 or 4");
+  bool rank4 = opt.bond == 4;
   auto p = std::make_unique<Plan>();
   p->n = n;
   p->d = d;
@@ -453,8 +457,16 @@ int build_plan(int n, int d, const cd* one_qubit, int n_gate2, const Gate2In* ga
       m16[15] = -1;
     } else if (g.kind == 1) {
       for (int e = 0; e < 16; ++e) m16[e] = g.m[e];
-      int rc = split_entangler(g.m, &p->split[pi], err);
-      if (rc) return rc;
+      if (opt.bond != 4) {
+        std::string why;
+        int rc = split_entangler(g.m, &p->split[pi], &why);
+        if (rc == kErrRank && opt.bond == 0) {
+          rank4 = true;  // lowered with bond dimension four below
+        } else if (rc) {
+          if (err) *err = why;
+          return rc;
+        }
+      }
     } else {
       return fail(err, kErrInvalid, "unknown gate kind");
     }
@@ -477,6 +489,13 @@ int build_plan(int n, int d, const cd* one_qubit, int n_gate2, const Gate2In* ga
     for (int l = 1; l <= d; ++l)
       if (in_pattern(*p, l, c)) p->X[c].push_back(l);
     p->h = std::max(p->h, int(p->X[c].size()));
+  }
+  if (rank4) {
+    // operator Schmidt rank 4: two legs per crossing (plan4.cpp)
+    int rc = build_rows4(*p, err);
+    if (rc) return rc;
+    *out = std::move(p);
+    return 0;
   }
   if (p->h > 40) return fail(err, kErrDomain, "width above 40 is not supported");
   // row 0 build-up
@@ -506,8 +525,9 @@ int build_plan(int n, int d, const cd* one_qubit, int n_gate2, const Gate2In* ga
 // ---------------------------------------------------------------------------
 namespace {
 
-// Live slot count after rows 0..r.
-int live_after_row(const Plan& p, int r) { return int(p.X[r].size()); }
+// Live slot count after rows 0..r (bond dimension four: every cut has
+// d - 1 slots).
+int live_after_row(const Plan& p, int r) { return p.chi == 4 ? p.h : int(p.X[r].size()); }
 
 std::vector<Window> window_grid(const Plan& p, int hmax) {
   const int T = p.opt.max_tile_bits;
@@ -554,9 +574,78 @@ std::vector<Window> window_grid(const Plan& p, int hmax) {
   return ws;
 }
 
+// GF(2) span of lane slot directions (bit masks), one basis vector per
+// leading bit.
+struct Gf2Basis {
+  uint32_t b[32] = {};
+  uint32_t reduce(uint32_t x) const {
+    for (int bit = 31; bit >= 0 && x; --bit)
+      if ((x >> bit) & 1u) {
+        if (!b[bit]) return x;
+        x ^= b[bit];
+      }
+    return x;
+  }
+  bool independent(uint32_t x) const { return reduce(x) != 0u; }
+  void add(uint32_t x) {
+    x = reduce(x);
+    for (int bit = 31; bit >= 0; --bit)
+      if ((x >> bit) & 1u) {
+        b[bit] = x;
+        return;
+      }
+  }
+};
+
+// Thread-bit order of a register phase: the tile bits (ascending in `free`)
+// that thread bits 0, 1, ... sit on.  The lanes of one bank cycle of an
+// 8-byte LDS access are lanes 0..15 (or 0..31); they meet distinct slots when
+// the slot directions (lane_slot_dir) of lane bits 0..3 are independent
+// modulo 16 and those of lane bits 0..4 modulo 32.  So lane bits 0..3 take
+// the first tile bits that keep both spans growing, lane bit 4 (unless pinned
+// to tile bit pin4) the first one that adds a fifth direction, lane bit 5 is
+// pin5 when given, and the remaining bits follow in increasing order.
+std::vector<int> lane_order(std::vector<int> free_bits, int pin4, int pin5) {
+  std::vector<int> order;
+  Gf2Basis b16, b32;
+  if (pin4 >= 0) b32.add(lane_slot_dir(pin4));
+  auto take = [&](size_t i) {
+    const int p = free_bits[i];
+    free_bits.erase(free_bits.begin() + (long)i);
+    b16.add(lane_slot_dir(p) & 15u);
+    b32.add(lane_slot_dir(p));
+    order.push_back(p);
+  };
+  for (int lane = 0; lane < 4 && !free_bits.empty(); ++lane) {
+    size_t pick = free_bits.size();
+    for (size_t i = 0; i < free_bits.size() && pick == free_bits.size(); ++i) {
+      const uint32_t dv = lane_slot_dir(free_bits[i]);
+      if (b16.independent(dv & 15u) && b32.independent(dv)) pick = i;
+    }
+    for (size_t i = 0; i < free_bits.size() && pick == free_bits.size(); ++i)
+      if (b32.independent(lane_slot_dir(free_bits[i]))) pick = i;
+    take(pick == free_bits.size() ? 0 : pick);
+  }
+  if (pin4 >= 0) {
+    order.push_back(pin4);
+  } else if (!free_bits.empty()) {
+    size_t pick = 0;
+    for (size_t i = 0; i < free_bits.size(); ++i)
+      if (b32.independent(lane_slot_dir(free_bits[i]))) {
+        pick = i;
+        break;
+      }
+    take(pick);
+  }
+  if (pin5 >= 0) order.push_back(pin5);
+  for (int p : free_bits) order.push_back(p);
+  return order;
+}
+
 bool op_fits(const SweepOp& op, const Window& w) {
   if (!w.contains(op.target)) return false;
   if (op.control >= 0 && !w.contains(op.control)) return false;
+  if (op.pair >= 0 && !w.contains(op.pair)) return false;
   return true;
 }
 
@@ -575,6 +664,73 @@ void pad_regs(std::vector<int>& regs, int ctl0, int T, int R) {
     }
   for (int c = 0; int(regs.size()) < R && c < T; ++c)
     if (usable(c)) regs.push_back(c);
+}
+
+// Bank-cycle conflicts of a lane order: 2 if lanes 0..3 do not reach 16
+// distinct slots, plus 1 if lanes 0..4 do not reach 32.
+int lane_conflicts(const std::vector<int>& order) {
+  Gf2Basis b16, b32;
+  int r16 = 0, r32 = 0;
+  for (size_t t = 0; t < order.size() && t < 5; ++t) {
+    const uint32_t dv = lane_slot_dir(order[t]);
+    if (t < 4 && b16.independent(dv & 15u)) {
+      b16.add(dv & 15u);
+      ++r16;
+    }
+    if (b32.independent(dv)) {
+      b32.add(dv);
+      ++r32;
+    }
+  }
+  const int want16 = std::min<int>(4, (int)order.size()), want32 = std::min<int>(5, (int)order.size());
+  return (r16 < want16 ? 2 : 0) + (r32 < want32 ? 1 : 0);
+}
+
+// The padding registers of a phase whose targets are `regs`: the bits next
+// to the targets (pad_regs), unless another choice leaves free bits on which
+// the lanes of a bank cycle meet distinct LDS slots (lane_order); candidates
+// are tried nearest first.
+void pad_regs_lds(std::vector<int>& regs, int ctl0, int T, int R) {
+  std::vector<int> near = regs;
+  pad_regs(near, ctl0, T, T);  // every usable bit, nearest first
+  const std::vector<int> cand(near.begin() + (long)regs.size(), near.end());
+  const int need = R - (int)regs.size();
+  auto free_of = [&](const std::vector<int>& rg) {
+    std::vector<int> f;
+    for (int c = 0; c < T; ++c)
+      if (std::find(rg.begin(), rg.end(), c) == rg.end()) f.push_back(c);
+    return f;
+  };
+  std::vector<int> best = regs;
+  pad_regs(best, ctl0, T, R);
+  if (need <= 0 || T - R < 4) {
+    regs = best;
+    return;
+  }
+  int best_score = lane_conflicts(lane_order(free_of(best), -1, -1));
+  if (best_score == 0 || need > (int)cand.size()) {
+    regs = best;
+    return;
+  }
+  // combinations of `need` candidates, lexicographic over the nearest-first list
+  std::vector<int> idx(need);
+  for (int q = 0; q < need; ++q) idx[q] = q;
+  for (int tries = 0; tries < 4096; ++tries) {
+    std::vector<int> rg = regs;
+    for (int q : idx) rg.push_back(cand[q]);
+    const int sc = lane_conflicts(lane_order(free_of(rg), -1, -1));
+    if (sc < best_score) {
+      best_score = sc;
+      best = rg;
+      if (sc == 0) break;
+    }
+    int q = need - 1;
+    while (q >= 0 && idx[q] == (int)cand.size() - need + q) --q;
+    if (q < 0) break;
+    ++idx[q];
+    for (int r = q + 1; r < need; ++r) idx[r] = idx[r - 1] + 1;
+  }
+  regs = best;
 }
 
 // The first three updates from op i can run as one fused product: plain
@@ -604,6 +760,33 @@ void plan_phases(Pass& ps, const std::vector<SweepOp>& ops, int R, bool fuse) {
   while (i < ps.op_end) {
     Phase ph;
     ph.op_begin = i;
+    if (ops[i].kind == OP_D4) {
+      // dense phase: up to two 4x4 updates on disjoint slot pairs, update g
+      // on register bits (2g, 2g+1)
+      std::vector<int> regs;
+      int j = i;
+      while (j + 1 < ps.op_end && ops[j].kind == OP_D4 && int(regs.size()) + 2 <= std::min(4, Reff)) {
+        const int lo = ps.w.local(ops[j].target), hi = ps.w.local(ops[j].pair);
+        if (std::find(regs.begin(), regs.end(), lo) != regs.end() ||
+            std::find(regs.begin(), regs.end(), hi) != regs.end())
+          break;
+        regs.push_back(lo);
+        regs.push_back(hi);
+        j += 2;
+      }
+      ph.op_end = j;
+      ph.mf = 2;
+      pad_regs_lds(regs, -1, T, Reff);
+      for (int q = 0; q < kMaxReg; ++q) ph.reg[q] = q < int(regs.size()) ? regs[q] : -1;
+      std::vector<int> free_bits;
+      for (int c = 0; c < T; ++c)
+        if (std::find(regs.begin(), regs.end(), c) == regs.end()) free_bits.push_back(c);
+      const std::vector<int> lanes = lane_order(free_bits, -1, -1);
+      for (int t = 0; t < kMaxThreadBits; ++t) ph.tpos[t] = t < int(lanes.size()) ? lanes[t] : -1;
+      ps.phases.push_back(ph);
+      i = j;
+      continue;
+    }
     std::vector<int> regs = {ps.w.local(ops[i].target)};
     const int ctl0 = ops[i].kind == OP_CU && ops[i].control >= 0 ? ps.w.local(ops[i].control) : -1;
     const int limit = fuse && fusable_start(ops, i, ps.op_end) ? Reff + 2 - (ctl0 >= 0 ? 1 : 0) : Reff;
@@ -617,8 +800,13 @@ void plan_phases(Pass& ps, const std::vector<SweepOp>& ops, int R, bool fuse) {
       regs.push_back(t);
     }
     ph.op_end = j;
-    pad_regs(regs, ctl0, T, Reff);
+    pad_regs_lds(regs, ctl0, T, Reff);
     for (int q = 0; q < kMaxReg; ++q) ph.reg[q] = q < int(regs.size()) ? regs[q] : -1;
+    std::vector<int> free_bits;
+    for (int c = 0; c < T; ++c)
+      if (std::find(regs.begin(), regs.end(), c) == regs.end()) free_bits.push_back(c);
+    const std::vector<int> lanes = lane_order(free_bits, -1, -1);
+    for (int t = 0; t < kMaxThreadBits; ++t) ph.tpos[t] = t < int(lanes.size()) ? lanes[t] : -1;
     ps.phases.push_back(ph);
     i = j;
   }
@@ -638,6 +826,7 @@ void split_triples(Pass& ps, const std::vector<SweepOp>& ops) {
   const int TB = T - R;
   if (R < 3 || TB < 6 || TB > kMaxThreadBits) return;
   for (Phase& ph : ps.phases) {
+    if (ph.mf == 2) continue;  // dense phases stay on the vector ALUs
     const int o = ph.op_begin;
     const int nops = ph.op_end - o;
     bool ok = nops >= 3;
@@ -657,20 +846,22 @@ void split_triples(Pass& ps, const std::vector<SweepOp>& ops) {
     std::vector<int> rest;
     for (int c = 0; c < T; ++c)
       if (!used(c)) rest.push_back(c);
-    // lanes 0..3: the four lowest free bits (adjacent LDS entries), then
-    // the filler register bits, then the wave bits
+    // lanes 0..3: free bits whose LDS slot directions keep the lanes of a
+    // bank cycle apart (with b1 on lane 4), then the filler register bits,
+    // then the wave bits
     Phase mp;
     mp.op_begin = o;
     mp.op_end = ph.op_end;
     mp.mf = 1;
+    const std::vector<int> lanes = lane_order(rest, b1, b2);
+    for (int t = 0; t < 6; ++t) mp.tpos[t] = lanes[t];
+    std::vector<int> left(lanes.begin() + 6, lanes.end());
     size_t q = 0;
-    for (int t = 0; t < 4; ++t) mp.tpos[t] = rest[q++];
-    mp.tpos[4] = b1;
-    mp.tpos[5] = b2;
-    while (int(regs.size()) < R - (ctl0 >= 0 ? 1 : 0)) regs.push_back(rest[q++]);
+    while (int(regs.size()) < R - (ctl0 >= 0 ? 1 : 0)) regs.push_back(left[q++]);
     if (ctl0 >= 0) regs.push_back(ctl0);
     for (int r = 0; r < kMaxReg; ++r) mp.reg[r] = r < int(regs.size()) ? regs[r] : -1;
-    for (int t = 6; t < TB; ++t) mp.tpos[t] = rest[q++];
+    for (int t = 6; t < TB; ++t) mp.tpos[t] = left[q++];
+    for (int t = TB; t < kMaxThreadBits; ++t) mp.tpos[t] = -1;
     ph = mp;
   }
 }
@@ -749,6 +940,70 @@ double log2_sum(const std::vector<double>& log2s) {
   return mx + std::log2(s);
 }
 
+// Fold an end 2x2 `e` of a bond-dimension-four row (no control) into the
+// dense 4x4 (halves a, b) listed just before it, on the slot e targets.
+bool merge_into_dense(SweepOp& a, SweepOp& b, const SweepOp& e) {
+  if (e.kind != OP_CU || e.control >= 0 || (e.target != a.target && e.target != a.pair)) return false;
+  const bool ev = e.xrow[0] >= 0 || e.xrow[1] >= 0, dv = a.xrow[0] >= 0 || a.xrow[1] >= 0;
+  if (ev && dv) return false;
+  const int sh = e.target == a.target ? 0 : 1;
+  for (int var = 0; var < 4; ++var) {
+    cd M[4][4], R[4][4];
+    for (int o = 0; o < 4; ++o)
+      for (int u = 0; u < 4; ++u) M[o][u] = (o < 2 ? a : b).mat[var][o & 1].a[u];
+    const M2& S = e.mat[var][0];
+    for (int o = 0; o < 4; ++o)
+      for (int u = 0; u < 4; ++u) {
+        const int ob = (o >> sh) & 1;
+        cd acc = 0;
+        for (int t = 0; t < 2; ++t) acc += S(ob, t) * M[(o & ~(1 << sh)) | (t << sh)][u];
+        R[o][u] = acc;
+      }
+    for (int o = 0; o < 4; ++o)
+      for (int u = 0; u < 4; ++u) (o < 2 ? a : b).mat[var][o & 1].a[u] = R[o][u];
+  }
+  if (ev) {
+    a.xrow[0] = b.xrow[0] = e.xrow[0];
+    a.xrow[1] = b.xrow[1] = e.xrow[1];
+  }
+  return true;
+}
+
+// The schedule of a bond-dimension-four plan (k = 0): rows 1..n-2 as dense
+// 4x4 updates, the end 2x2 of each row merged into the 4x4 before it, and
+// the last row as the late program.
+int schedule4(Plan& p, Schedule& s, std::string* err) {
+  if (s.k != 0) return fail(err, kErrDomain, "open legs k >= 1 need entanglers of operator Schmidt rank <= 2");
+  const int n = p.n, W = p.h;
+  s.last_fixed_row = n - 2;
+  s.m_fix = W;
+  for (int r = 1; r <= n - 2; ++r)
+    for (const SweepOp& op : p.row_ops[r]) {
+      const size_t m = s.ops.size();
+      if (m >= 2 && s.ops[m - 2].kind == OP_D4 && merge_into_dense(s.ops[m - 2], s.ops[m - 1], op)) continue;
+      s.ops.push_back(op);
+    }
+  // a dense update holds two register bits
+  s.reg_bits = std::max(2, std::min(p.opt.reg_bits, W));
+  s.passes = plan_passes(p, s.ops, s.reg_bits);
+  int rc = build_late4(p, s, err);
+  if (rc) return rc;
+  // Cost in the |I||J||K| convention of Sec. 2.2: a crossing above absorbed
+  // with its worldline piece costs 2^(W+3) (two steps of 2^(W+2)), the end
+  // piece of a row 2^(W+1); build-up and the last row as for bond two.
+  std::vector<double> cost;
+  for (int j = 1; j <= p.m0; ++j) cost.push_back(j + 2.0);
+  const int hc = (W + 1) / 2;
+  for (int r = 1; r <= n - 2; ++r) {
+    for (int j = 0; j < hc - 1; ++j) cost.push_back(W + 3.0);
+    cost.push_back(W + 1.0);
+  }
+  for (int j = W; j >= 1; --j) cost.push_back(j + 1.0);
+  s.log2_cost = log2_sum(cost);
+  s.width = W;
+  return 0;
+}
+
 }  // namespace
 
 int get_schedule(Plan& p, int k, std::shared_ptr<Schedule>* out, std::string* err) {
@@ -764,6 +1019,13 @@ int get_schedule(Plan& p, int k, std::shared_ptr<Schedule>* out, std::string* er
   auto s = std::make_shared<Schedule>();
   s->k = k;
   const int n = p.n;
+  if (p.chi == 4) {
+    int rc = schedule4(p, *s, err);
+    if (rc) return rc;
+    p.sched[k] = s;
+    *out = s;
+    return 0;
+  }
   s->last_fixed_row = (k == 0) ? n - 2 : n - k - 1;
   s->m_fix = live_after_row(p, s->last_fixed_row);
   // sweep ops: rows 1..last_fixed_row, merged at turns
@@ -927,6 +1189,27 @@ int get_schedule(Plan& p, int k, std::shared_ptr<Schedule>* out, std::string* er
 // FP64 host execution of the plan tables (self-check of the lowering).
 namespace {
 
+// Dense 4x4 (halves a, b) on the slot pair (a.target, a.pair).
+void host_apply_dense(const SweepOp& a, const SweepOp& b, std::vector<cd>& B, int h, const uint8_t* x) {
+  const size_t dim = size_t(1) << h;
+  int var = 0;
+  if (a.xrow[0] >= 0) var += 2 * x[a.xrow[0]];
+  if (a.xrow[1] >= 0) var += x[a.xrow[1]];
+  const size_t lo = size_t(1) << a.target, hi = size_t(1) << a.pair;
+  for (size_t i = 0; i < dim; ++i) {
+    if (i & (lo | hi)) continue;
+    const size_t idx[4] = {i, i | lo, i | hi, i | lo | hi};
+    cd in[4];
+    for (int u = 0; u < 4; ++u) in[u] = B[idx[u]];
+    for (int o = 0; o < 4; ++o) {
+      const M2& row = (o < 2 ? a : b).mat[var][o & 1];
+      cd acc = 0;
+      for (int u = 0; u < 4; ++u) acc += row.a[u] * in[u];
+      B[idx[o]] = acc;
+    }
+  }
+}
+
 void host_apply_op(const SweepOp& op, std::vector<cd>& B, int h, const uint8_t* x) {
   const size_t dim = size_t(1) << h;
   int var = 0;
@@ -967,7 +1250,11 @@ int execute_host(Plan& p, int k, int n_batches, const uint8_t* bits, cd* out, st
       v *= p.init_f[x[0]][int(i >> (m0 - 1) & 1)];
       B[i] = v;
     }
-    for (const auto& op : s->ops) host_apply_op(op, B, h, x);
+    for (size_t i = 0; i < s->ops.size(); ++i) {
+      const SweepOp& op = s->ops[i];
+      if (op.kind == OP_D4) host_apply_dense(op, s->ops[i + 1], B, h, x);
+      else if (op.kind != OP_D4H) host_apply_op(op, B, h, x);
+    }
     // late: state tensor st[rest][t] with t in the low s bits
     const int sb = s->s_bits;
     const int ub = s->join_u_bits;
@@ -1002,19 +1289,22 @@ int execute_host(Plan& p, int k, int n_batches, const uint8_t* bits, cd* out, st
           band_apply_g4(v, sb, lo.a, lo.m);
           std::copy(v.begin(), v.end(), st.begin() + rr * sd);
         }
-      } else if (lo.kind == L_REMOVE) {
-        M2 C[2];
-        for (int b = 0; b < 2; ++b)
-          for (int e = 0; e < 4; ++e) C[b].a[e] = lo.m[4 * b + e];
-        std::vector<cd> ns((sd << (rest_bits - 1)), cd(0));
-        for (size_t rr = 0; rr < (nrest >> 1); ++rr)
-          for (int u = 0; u < 2; ++u) {
-            std::vector<cd> v(st.begin() + ((rr << 1) | u) * sd, st.begin() + (((rr << 1) | u) + 1) * sd);
+      } else if (lo.kind == L_REMOVE || lo.kind == L_REMOVE2) {
+        const int nb = lo.kind == L_REMOVE ? 1 : 2;
+        const int off = (lo.kind == L_REMOVE && lo.xrow >= 0 && x[lo.xrow]) ? 8 : 0;
+        M2 C[4];
+        for (int b = 0; b < (1 << nb); ++b)
+          for (int e = 0; e < 4; ++e) C[b].a[e] = lo.m[off + 4 * b + e];
+        std::vector<cd> ns((sd << (rest_bits - nb)), cd(0));
+        for (size_t rr = 0; rr < (nrest >> nb); ++rr)
+          for (int u = 0; u < (1 << nb); ++u) {
+            const size_t row = (rr << nb) | (size_t)u;
+            std::vector<cd> v(st.begin() + row * sd, st.begin() + (row + 1) * sd);
             band_apply_u1(v, sb, 0, C[u]);
             for (size_t t = 0; t < sd; ++t) ns[rr * sd + t] += v[t];
           }
         st.swap(ns);
-        rest_bits--;
+        rest_bits -= nb;
       } else if (lo.kind == L_DOT) {
         int xv = x[lo.xrow];
         o[0] = lo.m[2 * xv] * st[0] + lo.m[2 * xv + 1] * st[1];

@@ -3,7 +3,10 @@
 // The planner fixes the unsliced sweep of the deterministic temporal-state
 // contraction (Sec. 3.1, Alg. 1) and of its batched extension with k open
 // output legs (Sec. 4.3, Alg. 2) for an open-chain brickwork circuit whose
-// entanglers have operator Schmidt rank <= 2 (Sec. 2.1-2.2).
+// entanglers have operator Schmidt rank <= 2 (Sec. 2.1-2.2), and, for
+// entanglers of rank 4 (generic two-qubit gates, Sec. 6.2 "Effect of bond
+// dimension"), the sweep of bond dimension four described in plan4.cpp
+// (even depth, k = 0).
 //
 // Lowering used here (derived from the tensor network of Sec. 2.2):
 //  * every entangler on (q, q+1) is written as
@@ -54,29 +57,37 @@ struct Split {
   M2 C[2];
 };
 
-enum SweepKind { OP_CU = 0, OP_DUP = 1 };
+enum SweepKind { OP_CU = 0, OP_DUP = 1, OP_D4 = 2, OP_D4H = 3 };
 
 // One update of the boundary tensor.  OP_CU: for every index whose control
 // bit is c (c = 0 if control < 0), the pair (b0, b1) along `target` becomes
 // mat[var][c] * (b0, b1).  OP_DUP: the half with target bit 1 is overwritten
 // by the half with target bit 0 (the top-slot expand of odd depth).
+// OP_D4 + OP_D4H (always adjacent, in this order): one dense 4x4 M on the
+// slot pair (target, pair): the four entries with u = bit(target) +
+// 2 bit(pair) become M (b_0 .. b_3); OP_D4 holds rows 0 and 1 of M, OP_D4H
+// rows 2 and 3, as mat[var][r].a[c] = M[row r of the half][c] (c = 0..3).
 // var = 2*x[xrow0] + x[xrow1] (an unused xrow reads as 0).
 struct SweepOp {
   int kind = OP_CU;
   int target = -1;
   int control = -1;
+  int pair = -1;  // OP_D4 / OP_D4H: the upper slot of the pair
   int xrow[2] = {-1, -1};
   M2 mat[4][2];
   int row = -1;
 };
 
-enum LateKind { L_U1 = 1, L_G4 = 2, L_REMOVE = 3, L_DOT = 4, L_OUT = 5 };
+enum LateKind { L_U1 = 1, L_G4 = 2, L_REMOVE = 3, L_DOT = 4, L_OUT = 5, L_REMOVE2 = 6 };
 
 // Late program on a state of s bits (s = k for k >= 1, s = 1 for k = 0):
 //  L_U1 a:       2x2 on state bit a (m: 4 entries)
 //  L_G4 a:       4x4 on state bits (a, a+1), basis 2*bit_a + bit_{a+1} (m: 16)
 //  L_REMOVE:     sum out the lowest remaining slot u with C_u on state bit 0
-//                (m: C_0 then C_1, 8 entries)
+//                (m: C_0 then C_1, 8 entries; with xrow >= 0 a second set of
+//                8 for output bit x[xrow] = 1)
+//  L_REMOVE2:    sum out the two lowest remaining slots (u0 the lower, u1)
+//                with C_u, u = u0 + 2 u1, on state bit 0 (m: C_0..C_3, 16)
 //  L_DOT xrow:   k = 0 only: amplitude = sum_w f_x[w] state[w]  (m: f_0, f_1)
 //  L_OUT:        k >= 1: out[b] = state[bit-reverse_k(b)]
 struct LateOp {
@@ -97,6 +108,13 @@ struct Window {
 
 constexpr int kMaxReg = 8;
 
+// Boundary tensors the device path runs: up to 2^40 entries.  Bond-four
+// plans are built (width, cost, schedule; no device tables) up to width 69,
+// the n = d = 70 point of Sec. 6.2 (the late buffers' byte counts stay below
+// 2^64 there).
+constexpr int kMaxDeviceWidth = 40;
+constexpr int kMaxPlanWidth = 69;
+
 // Register bits of a pass with 2^T-entry tiles: at most R, and at least one
 // bit left for the thread part so that op 0's control is never a register.
 inline int pass_reg_bits(int R, int T) { return T <= 1 ? 1 : (R < T - 1 ? R : T - 1); }
@@ -108,8 +126,9 @@ constexpr int kMaxThreadBits = 9;
 // op 0's control, on the matrix cores, with targets reg[0] (a register bit)
 // and tpos[4], tpos[5] (lane bits 4 and 5); op 0's control, if any, is
 // reg[R-1]; the staircase goes on on the vector ALUs: update 3 targets
-// reg[1] under tpos[5], update b > 3 reg[b-2] under reg[b-3].  tpos[t] is
-// the tile bit of thread bit t.
+// reg[1] under tpos[5], update b > 3 reg[b-2] under reg[b-3].  mf = 2: a
+// dense phase of one or two 4x4 updates (OP_D4 + OP_D4H each), update g on
+// register bits (2g, 2g+1).  tpos[t] is the tile bit of thread bit t.
 struct Phase {
   int op_begin = 0, op_end = 0;
   int reg[kMaxReg] = {0};  // local tile bits held in registers, in register-bit order
@@ -132,6 +151,8 @@ struct Options {
                             // on the matrix cores
   int late_fold = 0;        // removals folded into the join launch (0 auto, -1 none, 1..8)
   int reg_adapt = 0;        // 1: a pass uses reg_bits - 1 when that needs no more phases; 0: never
+  int bond = 0;             // entangler bond dimension of the lowering: 0 the smallest that holds
+                            // every gate, 2, or 4
 };
 
 // Everything that depends on k (the number of open output legs).
@@ -153,6 +174,7 @@ struct Schedule {
 
 struct Plan {
   int n = 0, d = 0, h = 0;
+  int chi = 2;                           // bond dimension of the lowering (2 or 4)
   int parity1 = 1;                       // upper-qubit parity of layer 1's pairs
   std::vector<M2> one;                   // (d+1)*n one-qubit gates
   std::vector<std::vector<int>> X;       // X[c] = crossing layers of cut c, ascending
@@ -190,6 +212,13 @@ int get_schedule(Plan& p, int k, std::shared_ptr<Schedule>* out, std::string* er
 // FP64 host execution of the plan's own tables (planner self-check; the GPU
 // path never calls this).  out: n_batches * 2^k amplitudes.
 int execute_host(Plan& p, int k, int n_batches, const uint8_t* bits, cd* out, std::string* err);
+
+// The bond-dimension-four lowering (plan4.cpp): fills row 0's build-up,
+// the row updates and p.h of a plan whose gates, one-qubit layers and
+// crossing lists are set.
+int build_rows4(Plan& p, std::string* err);
+// Its late program (k = 0: the last row's absorption).
+int build_late4(const Plan& p, Schedule& s, std::string* err);
 
 // Decompose a 4x4 (basis 2*x_upper + x_lower) into copy-on-upper form.
 // Returns 0, or TNC_E_RANK-equivalent (-3) when the operator Schmidt rank

@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -153,7 +155,7 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
     int gp = 0;
     for (const Pass& ps : s.passes)
       for (const Phase& pp : ps.phases) {
-        if (pp.mf) {
+        if (pp.mf == 1) {
           if (pp.op_end - pp.op_begin < 3) {
             if (err) *err = "fused phase of fewer than three updates";
             return TNC_E_INVALID;
@@ -180,6 +182,25 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
         if (c == 0) acc += r;
       }
       fused_left = 3;
+    }
+    if (op.kind == OP_D4) {
+      // a dense 4x4: its 16 entries rounded together (one bias factor), the
+      // rows split over the two halves' tables
+      const SweepOp& hb = s.ops[o + 1];
+      cd step = 0;
+      for (int var = 0; var < 4; ++var) {
+        cd K[16];
+        float K32[32];
+        for (int rr = 0; rr < 4; ++rr)
+          for (int c = 0; c < 4; ++c) K[4 * rr + c] = (rr < 2 ? op : hb).mat[var][rr & 1].a[c];
+        const cd r = round_entries(K, 16, acc, K32);
+        if (var == 0) step = r;
+        std::copy(K32, K32 + 16, t->mats.data() + (o * 4 + var) * 16);
+        std::copy(K32 + 16, K32 + 32, t->mats.data() + ((o + 1) * 4 + var) * 16);
+      }
+      acc += step;
+      ++o;
+      continue;
     }
     // updates inside a fused product keep their own tables (unused by the
     // matrix cores) out of the running bias
@@ -213,7 +234,7 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
       const int nops = pp.op_end - pp.op_begin;
       // a fused phase holds two targets in lane bits: up to R + 2 updates;
       // every phase must have an instantiated kernel form
-      if (!phase_form_exists(R, nops, pp.mf != 0)) return fail_t("phase size without a kernel form");
+      if (!phase_form_exists(R, nops, pp.mf)) return fail_t("phase size without a kernel form");
       DevPhase dp;
       std::memset(&dp, 0, sizeof(dp));
       dp.op_begin = pp.op_begin;
@@ -228,7 +249,7 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
       }
       t->phases.push_back(dp);
       const int T = ps.w.tile_bits();
-      if (pp.mf) {
+      if (pp.mf == 1) {
         // fused phase: targets reg[0], tpos[4], tpos[5]; op 0's control (if
         // any) reg[R-1]; every tile bit exactly once among registers and
         // thread bits
@@ -281,10 +302,49 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
         }
         continue;
       }
-      for (int i = 0; i < kPhaseOffs; ++i) t->poffs.push_back(i < (1 << R) ? phase_entry_offset(dp, R, i) : 0u);
+      if (pp.mf == 2) {
+        // dense phase: update g = ops (2g, 2g+1) on register bits (2g, 2g+1)
+        for (int g = 0; g < nops / 2; ++g) {
+          const SweepOp& a = s.ops[pp.op_begin + 2 * g];
+          const SweepOp& b = s.ops[pp.op_begin + 2 * g + 1];
+          if (a.kind != OP_D4 || b.kind != OP_D4H || b.target != a.target || b.pair != a.pair ||
+              !ps.w.contains(a.target) || !ps.w.contains(a.pair) || ps.w.local(a.target) != pp.reg[2 * g] ||
+              ps.w.local(a.pair) != pp.reg[2 * g + 1] || b.xrow[0] != a.xrow[0] || b.xrow[1] != a.xrow[1])
+            return fail_t("dense phase not canonical");
+        }
+        t->phases.back().pad = 2;
+      }
+      // thread bits: every tile bit outside the registers exactly once
+      {
+        const int TB = T - R;
+        if (TB > kMaxThreadBits) return fail_t("too many thread bits");
+        uint32_t seen = 0;
+        for (int b = 0; b < R; ++b) seen |= 1u << pp.reg[b];
+        for (int q = 0; q < TB; ++q) {
+          if (pp.tpos[q] < 0 || pp.tpos[q] >= T || (seen >> pp.tpos[q] & 1u)) return fail_t("bad thread map");
+          seen |= 1u << pp.tpos[q];
+        }
+        for (int i = 0; i < kPhaseOffs; ++i) {
+          uint32_t w = 0;
+          if (i < (1 << R)) w = phase_entry_offset(dp, R, i);
+          else if (i >= kPhaseEntries && i - kPhaseEntries < TB) w = swz(1u << pp.tpos[i - kPhaseEntries]) << 3;
+          t->poffs.push_back(w);
+        }
+      }
       for (int b = 0; b < nops; ++b) {
         const int o = pp.op_begin + b;
         const SweepOp& op = s.ops[o];
+        if (pp.mf == 2) {
+          DevOp d;
+          std::memset(&d, 0, sizeof(d));
+          d.cloc = -1;
+          d.xrow0 = (int16_t)op.xrow[0];
+          d.xrow1 = (int16_t)op.xrow[1];
+          d.mat = o;
+          t->ops[o] = d;
+          continue;
+        }
+        if (op.kind != OP_CU && op.kind != OP_DUP) return fail_t("dense update outside a dense phase");
         if (!ps.w.contains(op.target) || ps.w.local(op.target) != pp.reg[b]) return fail_t("op target not canonical");
         DevOp d;
         std::memset(&d, 0, sizeof(d));
@@ -295,8 +355,12 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
             const int lc = ps.w.local(op.control);
             for (int q = 0; q < R; ++q)
               if (pp.reg[q] == lc) return fail_t("first op control held in registers");
+            int tb = -1;
+            for (int q = 0; q < T - R; ++q)
+              if (pp.tpos[q] == lc) tb = q;
+            if (tb < 0) return fail_t("first op control on no thread bit");
             d.cloc = (int8_t)lc;
-            t->phases.back().cloc0 = (int8_t)lc;
+            t->phases.back().cloc0 = (int8_t)tb;
           }
         } else {
           if (op.kind != OP_CU || op.control < 0 || !ps.w.contains(op.control) ||
@@ -444,6 +508,7 @@ int upload(T** dst, const std::vector<T>& src) {
 }
 
 int get_dev_sched(Plan& p, int k, std::shared_ptr<DevSched>* out) {
+  if (p.h > kMaxDeviceWidth) return set_err(TNC_E_DOMAIN, "boundary tensors above 2^40 entries are planned only");
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_err(e, "hipGetDevice");
@@ -532,6 +597,8 @@ struct Profiler {
   std::vector<Rec> recs;
 };
 Profiler g_prof;
+// per-launch durations of the last finished profiling session (class, ms)
+std::vector<std::pair<int, double>> g_prof_last;
 
 // Records an event pair around `launch` when profiling is on.
 template <typename F>
@@ -981,16 +1048,24 @@ int emulate(Plan& p, int k, int nb, const uint8_t* bits, int storage, cd* out) {
                 }
                 for (int u = 0; u < 4; ++u) v[idx[u]] = y[u];
               }
-            } else if (op.kind == L_REMOVE && (r & 1) == 0) {
-              cd* w = st.data() + ((size_t)(row | (1 << l)) << sb);
+            } else if ((op.kind == L_REMOVE && (r & 1) == 0) || (op.kind == L_REMOVE2 && (r & 3) == 0)) {
+              const int nu = op.kind == L_REMOVE ? 2 : 4;
+              const int off = (op.kind == L_REMOVE && op.xrow >= 0 && (bits[(size_t)b * p.n + op.xrow] & 1)) ? 8 : 0;
               for (int i = 0; i < (1 << sb); i += 2) {
-                const cd x0 = v[i], x1 = v[i + 1], y0 = w[i], y1 = w[i + 1];
-                v[i] = op.m[0] * x0 + op.m[1] * x1 + op.m[4] * y0 + op.m[5] * y1;
-                v[i + 1] = op.m[2] * x0 + op.m[3] * x1 + op.m[6] * y0 + op.m[7] * y1;
+                cd y0 = 0, y1 = 0;
+                for (int u = 0; u < nu; ++u) {
+                  const cd* w = st.data() + ((size_t)(row | (u << l)) << sb);
+                  const cd* m = op.m.data() + off + 4 * u;
+                  y0 += m[0] * w[i] + m[1] * w[i + 1];
+                  y1 += m[2] * w[i] + m[3] * w[i + 1];
+                }
+                v[i] = y0;
+                v[i + 1] = y1;
               }
             }
           }
           if (op.kind == L_REMOVE) ++l;
+          else if (op.kind == L_REMOVE2) l += 2;
         }
         for (int q = 0; q < (1 << sb); ++q) nxt[((size_t)ro << sb) + q] = st[q];
       }
@@ -1050,10 +1125,12 @@ int tnc_plan(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, c
     o.math = opt->math;
     o.late_fold = opt->late_fold;
     o.reg_adapt = opt->reg_adapt;
+    o.bond = opt->bond;
   }
   if (o.max_tile_bits < 6 || o.max_tile_bits > 14 || o.reg_bits < 1 || o.reg_bits > 5 || o.low_bits < 1 ||
       o.low_bits > o.max_tile_bits - 2 || (o.math != 0 && o.math != 2) || o.late_fold < -1 || o.late_fold > 8 ||
-      o.reg_adapt < 0 || o.reg_adapt > 1 || o.max_tile_bits - o.reg_bits > 9)
+      o.reg_adapt < 0 || o.reg_adapt > 1 || o.max_tile_bits - o.reg_bits > 9 ||
+      (o.bond != 0 && o.bond != 2 && o.bond != 4))
     return set_err(TNC_E_INVALID, "tile options out of range");
   if (n < 2 || d < 2 || (int64_t)n * (d + 1) > (1 << 24)) return set_err(TNC_E_DOMAIN, "need n >= 2, d >= 2");
   std::vector<cd> one((size_t)(d + 1) * n * 4);
@@ -1089,7 +1166,7 @@ int tnc_plan_info(tnc_plan_t plan, int32_t k, tnc_info* info) {
   info->width = s->width;
   info->boundary_bits = p->h;
   info->live_slots_fixed = s->m_fix;
-  info->n_ops = (int32_t)s->ops.size();
+  info->n_ops = (int32_t)std::count_if(s->ops.begin(), s->ops.end(), [](const SweepOp& o) { return o.kind != OP_D4H; });
   info->n_passes = (int32_t)s->passes.size();
   info->n_phases = (int32_t)t.phases.size();
   info->n_late_launches = 1 + (int32_t)t.late.ops.size();
@@ -1097,7 +1174,8 @@ int tnc_plan_info(tnc_plan_t plan, int32_t k, tnc_info* info) {
   info->early_layers = k >= 1 ? 2 * k : 0;
   info->late_layers = k >= 1 ? p->d - 2 * k : 0;
   info->log2_cost = s->log2_cost;
-  info->workspace_per_batch = batch_layout(*p, t, TNC_STORE_C64).per_batch();
+  info->workspace_per_batch = p->h <= kMaxDeviceWidth ? batch_layout(*p, t, TNC_STORE_C64).per_batch() : 0;
+  info->bond = p->chi;
   return TNC_OK;
 }
 
@@ -1119,6 +1197,7 @@ int tnc_workspace_bytes(tnc_plan_t plan, int32_t k, int32_t n_batches, int32_t s
   rc = build_tables(*p, *s, &t, &err);
   if (rc) return set_err(rc, err);
   if ((rc = check_storage(t, storage))) return rc;
+  if (p->h > kMaxDeviceWidth) return set_err(TNC_E_DOMAIN, "boundary tensors above 2^40 entries are planned only");
   *bytes = (uint64_t)n_batches * batch_layout(*p, t, storage).per_batch();
   return TNC_OK;
 }
@@ -1171,6 +1250,7 @@ uint64_t tnc_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
 int tnc_debug_workspace_c128(tnc_plan_t plan, int32_t k, int32_t n_batches, uint64_t* bytes) {
   Plan* p = get(plan);
   if (!p || !bytes || n_batches < 0) return set_err(TNC_E_INVALID, "bad argument");
+  if (p->chi == 4) return set_err(TNC_E_DOMAIN, "the complex128 reference sweep covers bond dimension 2 only");
   std::shared_ptr<Schedule> s;
   std::string err;
   int rc = get_schedule(*p, k, &s, &err);
@@ -1187,6 +1267,7 @@ int tnc_debug_amplitudes_c128(tnc_plan_t plan, int32_t n_batches, const uint8_t*
   Plan* p = get(plan);
   if (!p || n_batches < 0 || (n_batches > 0 && (!d_bits || !d_out || !d_workspace)))
     return set_err(TNC_E_INVALID, "bad argument");
+  if (p->chi == 4) return set_err(TNC_E_DOMAIN, "the complex128 reference sweep covers bond dimension 2 only");
   if (n_batches == 0) return TNC_OK;
   std::shared_ptr<DevSched> ds;
   int rc = get_dev_sched(*p, k, &ds);
@@ -1294,18 +1375,57 @@ int tnc_profile_end(tnc_profile* out) {
   }
   std::memset(out, 0, sizeof(*out));
   int rc = TNC_OK;
+  std::vector<std::pair<int, double>> last;
   for (auto& r : recs) {
     float ms = 0.f;
     hipError_t e = hipEventSynchronize(r.b);
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
     if (e != hipSuccess && rc == TNC_OK) rc = hip_err(e, "event timing");
+    last.emplace_back(r.cls, (double)ms);
     if (r.cls == 0) out->init_ms += ms, out->init_launches++;
     if (r.cls == 1) out->pass_ms += ms, out->pass_launches++, out->pass_bytes += r.bytes;
     if (r.cls == 2) out->late_ms += ms, out->late_launches++;
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof_last.swap(last);
   return rc;
+}
+
+int tnc_profile_launches(int32_t* cls, double* ms, int64_t cap, int64_t* n) {
+  if (!n || cap < 0 || (cap > 0 && (!cls || !ms))) return set_err(TNC_E_INVALID, "bad argument");
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  *n = (int64_t)g_prof_last.size();
+  for (int64_t i = 0; i < cap && i < *n; ++i) {
+    cls[i] = g_prof_last[(size_t)i].first;
+    ms[i] = g_prof_last[(size_t)i].second;
+  }
+  return TNC_OK;
+}
+
+int tnc_plan_passes(tnc_plan_t plan, int32_t k, int32_t* out, int32_t cap, int32_t* n_passes) {
+  Plan* p = get(plan);
+  if (!p || !n_passes || cap < 0 || (cap > 0 && !out)) return set_err(TNC_E_INVALID, "bad argument");
+  std::shared_ptr<Schedule> s;
+  std::string err;
+  int rc = get_schedule(*p, k, &s, &err);
+  if (rc) return set_err(rc, err);
+  *n_passes = (int32_t)s->passes.size();
+  for (int32_t i = 0; i < cap && i < *n_passes; ++i) {
+    const Pass& ps = s->passes[(size_t)i];
+    int fused = 0;
+    for (const Phase& ph : ps.phases) fused += ph.mf == 1 ? 1 : 0;
+    int32_t* o = out + 7 * (size_t)i;
+    o[0] = ps.w.lo_bits;
+    o[1] = ps.w.win_lo;
+    o[2] = ps.w.win_len;
+    o[3] = ps.R;
+    o[4] = ps.op_end - ps.op_begin;
+    o[5] = (int32_t)ps.phases.size();
+    o[6] = fused;
+  }
+  return TNC_OK;
 }
 
 void tnc_release(tnc_plan_t plan) {
@@ -1328,6 +1448,50 @@ const char* tnc_strerror(int code) {
 }
 
 const char* tnc_last_error(void) { return g_err.c_str(); }
+
+int tnc_debug_lds_conflicts(tnc_plan_t plan, int32_t k, int64_t* stats) {
+  Plan* p = get(plan);
+  if (!p || !stats) return set_err(TNC_E_INVALID, "bad argument");
+  std::shared_ptr<Schedule> s;
+  std::string err;
+  int rc = get_schedule(*p, k, &s, &err);
+  if (rc) return set_err(rc, err);
+  HostTables t;
+  rc = build_tables(*p, *s, &t, &err);
+  if (rc) return set_err(rc, err);
+  // lanes 0..63 of a wave (thread index = lane); slot of register entry 0
+  // (the other entries differ by a constant XOR); a group of g lanes
+  // conflicts when two of its lanes meet the same slot modulo g
+  int64_t phases = 0, c16 = 0, c32 = 0;
+  for (const PassHost& ph : t.passes) {
+    const int TB = ph.w.tile_bits() - ph.R;
+    for (int q = 0; q < ph.n_phases; ++q) {
+      const uint32_t* po = t.poffs.data() + (size_t)(ph.phase_off + q) * kPhaseOffs;
+      const int lanes = std::min(64, 1 << TB);
+      uint32_t slot[64];
+      for (int l = 0; l < lanes; ++l) {
+        uint32_t vb = 0;
+        for (int b = 0; b < TB; ++b)
+          if ((l >> b) & 1) vb ^= po[kPhaseEntries + b];
+        slot[l] = (vb ^ po[0]) >> 3;
+      }
+      auto conflicted = [&](int g) {
+        for (int l0 = 0; l0 + g <= lanes; l0 += g)
+          for (int a = l0; a < l0 + g; ++a)
+            for (int b = a + 1; b < l0 + g; ++b)
+              if ((slot[a] & (uint32_t)(g - 1)) == (slot[b] & (uint32_t)(g - 1))) return true;
+        return false;
+      };
+      ++phases;
+      if (lanes >= 16 && conflicted(16)) ++c16;
+      if (lanes >= 32 && conflicted(32)) ++c32;
+    }
+  }
+  stats[0] = phases;
+  stats[1] = c16;
+  stats[2] = c32;
+  return TNC_OK;
+}
 
 int tnc_debug_execute_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits, int32_t k, tnc_c128* out) {
   Plan* p = get(plan);

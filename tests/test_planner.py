@@ -72,9 +72,25 @@ def test_rank_and_domain_errors():
     u = np.linalg.qr(z)[0]
     bad = list(c.gates)
     bad[0] = (bad[0][0], bad[0][1], W.GATE_DENSE4, u)
+    # a rank-4 entangler: refused under bond dimension 2, lowered with bond
+    # dimension 4 otherwise (even depth, k = 0 only; Sec. 6.2)
     with pytest.raises(TncError) as e:
-        Plan(c.n, c.d, c.one_qubit, bad)
+        Plan(c.n, c.d, c.one_qubit, bad, options=dict(bond=2))
     assert e.value.code == TNC_E_RANK
+    p4 = Plan(c.n, c.d, c.one_qubit, bad)
+    assert p4.info(0)["bond"] == 4 and p4.info(0)["width"] == c.d - 1
+    with pytest.raises(TncError) as e:
+        p4.info(1)
+    assert e.value.code == TNC_E_DOMAIN
+    c7 = W.brickwork_circuit(6, 7, 0, W.rng_for(305, 4))
+    bad7 = list(c7.gates)
+    bad7[0] = (bad7[0][0], bad7[0][1], W.GATE_DENSE4, u)
+    with pytest.raises(TncError) as e:
+        Plan(c7.n, c7.d, c7.one_qubit, bad7)
+    assert e.value.code == TNC_E_DOMAIN
+    with pytest.raises(TncError) as e:
+        Plan(c.n, c.d, c.one_qubit, list(c.gates), options=dict(bond=3))
+    assert e.value.code == TNC_E_INVALID
     off = list(c.gates) + [(1, 0, W.GATE_CZ, None)] if c.gates[0][1] == 1 else list(c.gates) + [(1, 1, W.GATE_CZ, None)]
     with pytest.raises(TncError) as e:
         Plan(c.n, c.d, c.one_qubit, off)
@@ -265,3 +281,23 @@ def test_ring_rejects_bad_wrap_gates():
     clash = list(c.gates) + [(2, 7, W.GATE_CZ, None)]  # layer 2 uses qubit 0 in the chain
     with pytest.raises(TncError):
         RingPlan(c.n, c.d, c.one_qubit, clash)
+
+
+LDS_CASES = [(cid, o) for cid in (2, 4) for o in (None, dict(max_tile_bits=12, math=2), dict(reg_bits=4, math=2),
+                                                   dict(max_tile_bits=13, low_bits=5, reg_bits=4, math=2),
+                                                   dict(max_tile_bits=12, reg_adapt=1),
+                                                   dict(max_tile_bits=14, low_bits=3))]
+LDS_CASES += [(5, dict(max_tile_bits=13, low_bits=5, reg_bits=4, math=2)), (5, dict(max_tile_bits=12, math=2))]
+
+
+@pytest.mark.parametrize("cid,opts", LDS_CASES)
+def test_lds_placement_is_conflict_free(cid, opts):
+    # every register phase of the precision, full-width and width-35 plans in
+    # the tile options the benchmark chooses from: the 16 lanes of a bank
+    # cycle of an 8-byte LDS access meet 16 different slots modulo 16, and
+    # the 32 lanes of a 32-lane cycle 32 modulo 32 (late_fold = -1 only skips
+    # the host fold of the join, which does not touch the pass tables)
+    p = Plan.from_circuit(W.config_circuit(cid), dict(opts or {}, late_fold=-1))
+    st = p.debug_lds_conflicts(8)
+    assert st["phases"] > 100
+    assert st["conflicted_16"] == 0 and st["conflicted_32"] == 0, st
