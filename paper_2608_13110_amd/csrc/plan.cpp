@@ -774,6 +774,9 @@ void plan_phases(Pass& ps, const std::vector<SweepOp>& ops, int R, bool fuse) {
         regs.push_back(hi);
         j += 2;
       }
+      // (a tile too small for one dense update: the table builder refuses
+      // the phase, which takes the update all the same)
+      if (j == i) j = i + 2;
       ph.op_end = j;
       ph.mf = 2;
       pad_regs_lds(regs, -1, T, Reff);
@@ -975,9 +978,9 @@ bool merge_into_dense(SweepOp& a, SweepOp& b, const SweepOp& e) {
 int schedule4(Plan& p, Schedule& s, std::string* err) {
   if (s.k != 0) return fail(err, kErrDomain, "open legs k >= 1 need entanglers of operator Schmidt rank <= 2");
   const int n = p.n, W = p.h;
-  s.last_fixed_row = n - 2;
+  s.last_fixed_row = p.spatial ? n - 1 : n - 2;
   s.m_fix = W;
-  for (int r = 1; r <= n - 2; ++r)
+  for (int r = 1; r <= (p.spatial ? 1 : n - 2); ++r)
     for (const SweepOp& op : p.row_ops[r]) {
       const size_t m = s.ops.size();
       if (m >= 2 && s.ops[m - 2].kind == OP_D4 && merge_into_dense(s.ops[m - 2], s.ops[m - 1], op)) continue;
@@ -993,14 +996,20 @@ int schedule4(Plan& p, Schedule& s, std::string* err) {
   // piece of a row 2^(W+1); build-up and the last row as for bond two.
   std::vector<double> cost;
   for (int j = 1; j <= p.m0; ++j) cost.push_back(j + 2.0);
-  const int hc = (W + 1) / 2;
-  for (int r = 1; r <= n - 2; ++r) {
-    for (int j = 0; j < hc - 1; ++j) cost.push_back(W + 3.0);
-    cost.push_back(W + 1.0);
+  if (p.spatial) {
+    // a two-qubit gate on the n-qubit state: 2^(n+2); a one-qubit gate 2^(n+1)
+    for (const SweepOp& op : s.ops)
+      if (op.kind != OP_D4H) cost.push_back(op.kind == OP_D4 ? W + 2.0 : W + 1.0);
+  } else {
+    const int hc = (W + 1) / 2;
+    for (int r = 1; r <= n - 2; ++r) {
+      for (int j = 0; j < hc - 1; ++j) cost.push_back(W + 3.0);
+      cost.push_back(W + 1.0);
+    }
   }
   for (int j = W; j >= 1; --j) cost.push_back(j + 1.0);
   s.log2_cost = log2_sum(cost);
-  s.width = W;
+  s.width = p.spatial ? n : W;
   return 0;
 }
 

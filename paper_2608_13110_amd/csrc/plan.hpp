@@ -175,6 +175,8 @@ struct Schedule {
 struct Plan {
   int n = 0, d = 0, h = 0;
   int chi = 2;                           // bond dimension of the lowering (2 or 4)
+  bool spatial = false;                  // bond 4 with n below the temporal width: the boundary
+                                         // is the n-qubit state, swept layer by layer (plan4.cpp)
   int parity1 = 1;                       // upper-qubit parity of layer 1's pairs
   std::vector<M2> one;                   // (d+1)*n one-qubit gates
   std::vector<std::vector<int>> X;       // X[c] = crossing layers of cut c, ascending

@@ -33,8 +33,18 @@
 // ascending in A -> B rows and descending in B -> A rows, so consecutive rows
 // meet at the top or the bottom, where the end 2x2 of the next row is merged
 // into the 4x4 before it (schedule assembly, plan.cpp).
+//
+// When n is below that width (n < d-1 at even depth, n <= d at odd depth)
+// the narrower boundary is the spatial one: the n-qubit state, swept layer by
+// layer (the constructive width min(n, d-1), resp. min(n, d), of Sec. 6.2).
+// Its slots are the qubits; each layer is a set of dense 4x4 updates (the
+// gate with the one-qubit layer after it) on the pattern pairs and 2x2s on
+// the qubits outside them; the last layer also projects every qubit onto its
+// output bit, (b_0, b_1) -> (b_x, 0), so that the tensor ends as the amplitude
+// in entry 0 and zeros elsewhere, which the late program sums.
 #include "plan.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace tnc {
@@ -202,11 +212,113 @@ void descending_row(const Plan& p, int q, std::vector<SweepOp>* ops) {
   }
 }
 
+// Dense 4x4 of a gate on (q, q+1) followed by one-qubit gates a (on q) and
+// b (on q+1), in the slot basis u = bit(q) + 2 bit(q+1) (the gate's own
+// basis is 2 x_q + x_{q+1}).
+void spatial_gate(const Plan& p, int layer, int q, const M2& a, const M2& b, cd M[4][4]) {
+  const std::vector<cd>& g = p.g4[pair_at(p, layer, q)];
+  auto sw = [](int u) { return ((u & 1) << 1) | (u >> 1); };
+  for (int o = 0; o < 4; ++o)
+    for (int u = 0; u < 4; ++u) {
+      cd acc = 0;
+      for (int t = 0; t < 4; ++t) acc += a(o & 1, t & 1) * b(o >> 1, t >> 1) * g[4 * sw(t) + sw(u)];
+      M[o][u] = acc;
+    }
+}
+
+// The projection of the last layer onto output bit x: (b_0, b_1) -> (b_x, 0).
+M2 project(int x) {
+  M2 m = M2::zero();
+  m(0, x) = 1;
+  return m;
+}
+
+int build_spatial4(Plan& p, std::string* err) {
+  const int n = p.n, d = p.d;
+  if (n > kMaxPlanWidth) return fail4(err, kErrDomain, "width above 69 is not supported");
+  // at least three slots (a pass tile holds a dense update and a thread
+  // bit): a two-qubit chain keeps a third slot that stays zero
+  p.h = std::max(n, 3);
+  p.chi = 4;
+  p.spatial = true;
+  // layer-0 product state: B0[a] = prod_q (L_0 |0>)_q[a_q]
+  p.m0 = n;
+  cd v[2];
+  start_vector(p, 0, 1, v);
+  p.init_v[0] = v[0];
+  p.init_v[1] = v[1];
+  p.init_seg.assign(n - 1, M2());
+  for (int q = 1; q < n; ++q) {
+    start_vector(p, q, 1, v);
+    M2 s;
+    s(0, 0) = s(0, 1) = v[0];
+    s(1, 0) = s(1, 1) = v[1];
+    p.init_seg[q - 1] = s;
+  }
+  for (int x = 0; x < 2; ++x) p.init_f[x][0] = p.init_f[x][1] = 1;
+  // layers 1..d, ascending in odd layers and descending in even ones
+  p.row_ops.assign(2, {});
+  std::vector<SweepOp>& ops = p.row_ops[1];
+  for (int l = 1; l <= d; ++l) {
+    const bool last = l == d;
+    std::vector<char> paired(n, 0);
+    std::vector<std::vector<SweepOp>> items(n);  // per lowest slot
+    for (int q = 0; q + 1 < n; ++q) {
+      if (p.g4[pair_at(p, l, q)].empty()) continue;  // not a pattern pair of this layer
+      paired[q] = paired[q + 1] = 1;
+      const M2& a = p.one[(size_t)l * n + q];
+      const M2& b = p.one[(size_t)l * n + q + 1];
+      std::vector<SweepOp> two;
+      for (int var = 0; var < 4; ++var) {
+        const int xq = var >> 1, xq1 = var & 1;
+        cd M[4][4];
+        spatial_gate(p, l, q, last ? project(xq) * a : a, last ? project(xq1) * b : b, M);
+        if (var == 0) {
+          push_dense(&two, q, l, M);
+          if (last) {
+            two[0].xrow[0] = two[1].xrow[0] = q;
+            two[0].xrow[1] = two[1].xrow[1] = q + 1;
+          }
+        }
+        for (int half = 0; half < 2; ++half)
+          for (int rr = 0; rr < 2; ++rr)
+            for (int c = 0; c < 4; ++c) two[half].mat[var][rr].a[c] = M[2 * half + rr][c];
+      }
+      items[q] = two;
+    }
+    for (int q = 0; q < n; ++q) {
+      if (paired[q]) continue;
+      SweepOp op = single_op(q, l);
+      const M2& a = p.one[(size_t)l * n + q];
+      if (last) {
+        op.xrow[0] = q;
+        op.mat[0][0] = op.mat[0][1] = op.mat[1][0] = op.mat[1][1] = project(0) * a;
+        op.mat[2][0] = op.mat[2][1] = op.mat[3][0] = op.mat[3][1] = project(1) * a;
+      } else {
+        for (auto& vv : op.mat)
+          for (auto& mm : vv) mm = a;
+      }
+      items[q] = {op};
+    }
+    if (l % 2) {
+      for (int q = 0; q < n; ++q)
+        for (const SweepOp& o : items[q]) ops.push_back(o);
+    } else {
+      for (int q = n - 1; q >= 0; --q)
+        for (const SweepOp& o : items[q]) ops.push_back(o);
+    }
+  }
+  return 0;
+}
+
 }  // namespace
 
 int build_rows4(Plan& p, std::string* err) {
   const int n = p.n, d = p.d;
-  if (d % 2) return fail4(err, kErrDomain, "bond dimension 4 is lowered for even depth only");
+  // the narrower of the two boundaries (Sec. 6.2: min(n, d-1) at even depth,
+  // min(n, d) at odd depth; the temporal one is built for even depth)
+  if (d % 2 ? n <= d : n < d - 1) return build_spatial4(p, err);
+  if (d % 2) return fail4(err, kErrDomain, "bond dimension 4 at odd depth needs n <= d");
   const int hc = d / 2;
   for (int c = 0; c < n - 1; ++c)
     if (int(p.X[c].size()) != hc) return fail4(err, kErrInvalid, "cut without d/2 crossings");
@@ -257,6 +369,33 @@ int build_rows4(Plan& p, std::string* err) {
 
 int build_late4(const Plan& p, Schedule& s, std::string* err) {
   const int n = p.n;
+  if (p.spatial) {
+    // the projected state: the amplitude in entry 0, zeros elsewhere; the
+    // late program sums every entry (identity removals, then <0|)
+    s.s_bits = 1;
+    s.join_u_bits = 0;
+    s.late.clear();
+    s.n_remove = 0;
+    s.join = {cd(1), cd(0)};
+    for (int q = 0; q < p.h; ++q) {  // (the spare slot of n = 2 included)
+      LateOp o;
+      o.kind = L_REMOVE;
+      const M2 id;
+      for (int b = 0; b < 2; ++b)
+        for (int e = 0; e < 4; ++e) o.m.push_back(id.a[e]);
+      s.late.push_back(o);
+      s.n_remove++;
+    }
+    LateOp dot;
+    dot.kind = L_DOT;
+    dot.xrow = 0;
+    for (int x = 0; x < 2; ++x) {
+      dot.m.push_back(cd(1));
+      dot.m.push_back(cd(0));
+    }
+    s.late.push_back(dot);
+    return 0;
+  }
   const int c = n - 2, q = n - 1;
   const std::vector<int>& X = p.X[c];
   const int hc = int(X.size());

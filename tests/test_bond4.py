@@ -11,10 +11,12 @@ import workloads as W
 from paper_2608_13110_amd import Plan
 from tests import helpers as H
 
-# (n, d, first parity): both cut types at the top, n >= d - 1 and n < d - 1,
-# rows of one crossing (d = 2) up to several passes per row
+# (n, d, first parity): temporal sweeps (n >= d - 1, even d) with both cut
+# types at the top, from rows of one crossing (d = 2) up to several passes
+# per row; spatial sweeps (n < d - 1, or n <= d at odd d), n = 2 included
 GENERIC = [(2, 2, 1), (2, 2, 0), (3, 2, 1), (3, 4, 0), (4, 4, 1), (5, 6, 0), (6, 6, 1), (7, 8, 0),
-           (8, 8, 1), (9, 10, 0), (10, 6, 1), (12, 12, 0), (16, 14, 1)]
+           (8, 8, 1), (9, 10, 0), (10, 6, 1), (12, 12, 0), (16, 14, 1),
+           (2, 4, 1), (2, 3, 0), (3, 6, 0), (5, 8, 1), (4, 9, 0), (7, 7, 1), (9, 13, 0), (12, 20, 1)]
 
 TILES = [dict(max_tile_bits=6, low_bits=2, reg_bits=3), dict(max_tile_bits=6, low_bits=1, reg_bits=5),
          dict(max_tile_bits=7, low_bits=3, reg_bits=2), dict(max_tile_bits=8, low_bits=4, reg_bits=4), None,
@@ -22,14 +24,17 @@ TILES = [dict(max_tile_bits=6, low_bits=2, reg_bits=3), dict(max_tile_bits=6, lo
          dict(max_tile_bits=8, low_bits=3, reg_bits=4, reg_adapt=1)]
 
 
-@pytest.mark.parametrize("n", [8, 12, 20])
-def test_width_is_d_minus_one_for_even_depth(n):
-    # Sec. 6.2: W = min(n, d-1) for even d; here n >= d - 1
-    for d in range(2, n + 2, 2):
+@pytest.mark.parametrize("n", [3, 8, 12, 20])
+def test_width_matches_the_bond_four_construction(n):
+    # Sec. 6.2: W = min(n, d-1) for even d and min(n, d) for odd d (odd d
+    # with n > d, the temporal sweep of odd depth, is not lowered)
+    for d in range(2, 2 * n + 3):
+        if d % 2 and n > d:
+            continue
         p = Plan.from_circuit(W.generic_brickwork_circuit(n, d, W.rng_for(401, n, d)))
         inf = p.info(0)
         assert inf["bond"] == 4
-        assert inf["width"] == min(n, d - 1) == inf["boundary_bits"]
+        assert inf["width"] == (min(n, d - 1) if d % 2 == 0 else min(n, d)), (n, d)
 
 
 def test_cost_point_matches_paper():
@@ -54,7 +59,7 @@ def test_host_execution_matches_oracle(n, d, fp):
 
 
 @pytest.mark.parametrize("opt", TILES)
-@pytest.mark.parametrize("n,d,fp", [(12, 12, 1), (16, 14, 0), (13, 16, 1), (20, 18, 0)])
+@pytest.mark.parametrize("n,d,fp", [(12, 12, 1), (16, 14, 0), (13, 16, 1), (20, 18, 0), (12, 20, 1), (15, 17, 0)])
 def test_device_emulation_matches_oracle(n, d, fp, opt):
     c = W.generic_brickwork_circuit(n, d, W.rng_for(405, n, d, fp), first_parity=fp)
     p = Plan.from_circuit(c, opt)

@@ -1,7 +1,7 @@
 """GPU parity of the bond-dimension-four path (Sec. 6.2, "Effect of bond
 dimension"): generic Haar-random two-qubit entanglers, lowered to dense 4x4
-updates of a (d-1)-slot boundary tensor, through the C ABI against the FP64
-oracle.
+updates of a (d-1)-slot temporal boundary tensor, or of the n-qubit state
+when that is narrower, through the C ABI against the FP64 oracle.
 
 Tolerance as for bond two: every amplitude within 1e-5 * max(|ref|, 2^(-n/2))
 (complex64 updates, FP64 late phase).  Where no state vector fits (width 33,
@@ -52,6 +52,11 @@ GENERIC = [
     (22, 20, 1, 2, FULL_OPTIONS),
     (24, 22, 0, 2, dict(max_tile_bits=12, reg_bits=4, reg_adapt=1)),
     (24, 24, 1, 2, dict(max_tile_bits=13, low_bits=5, reg_bits=5)),
+    # spatial sweeps (the n-qubit state is the narrower boundary)
+    (2, 4, 1, 3, None),
+    (5, 9, 0, 2, None),
+    (12, 20, 1, 2, dict(max_tile_bits=6, low_bits=2, reg_bits=3)),
+    (20, 26, 0, 2, FULL_OPTIONS),
 ]
 
 
@@ -60,7 +65,7 @@ def test_generic_brickwork_matches_oracle(n, d, fp, nb, opt):
     from paper_2608_13110_amd import Plan
     c = W.generic_brickwork_circuit(n, d, W.rng_for(501, n, d, fp), first_parity=fp)
     p = Plan.from_circuit(c, opt)
-    assert p.info(0)["bond"] == 4 and p.info(0)["width"] == d - 1
+    assert p.info(0)["bond"] == 4 and p.info(0)["width"] == (min(n, d - 1) if d % 2 == 0 else n)
     bits = W.random_bitstrings(n, nb, W.rng_for(502, n, d))
     ref = oracle.amplitudes(c, bits, 0)
     got = gpu_amps(p, bits)

@@ -82,7 +82,8 @@ def test_rank_and_domain_errors():
     with pytest.raises(TncError) as e:
         p4.info(1)
     assert e.value.code == TNC_E_DOMAIN
-    c7 = W.brickwork_circuit(6, 7, 0, W.rng_for(305, 4))
+    # odd depth: the spatial sweep covers n <= d; n > d is not lowered
+    c7 = W.brickwork_circuit(9, 7, 0, W.rng_for(305, 4))
     bad7 = list(c7.gates)
     bad7[0] = (bad7[0][0], bad7[0][1], W.GATE_DENSE4, u)
     with pytest.raises(TncError) as e:
