@@ -59,9 +59,10 @@ struct DevPhase {
   int8_t reg[8];
   int8_t cloc0;
   int8_t pad;   // 1: a fused phase (three updates as one 8x8 on the matrix cores);
-                // 2: a dense phase (n_ops / 2 dense 4x4 updates, update g on
-                // register bits (2g, 2g+1), its matrix rows in ops op_begin + 2g
-                // and op_begin + 2g + 1)
+                // 2: a dense phase (n_ops / 2 dense 4x4 updates in order, update g
+                // on the register-bit pair coded in bits 4g..4g+3 of reg[6..7]
+                // (dense_pair_code), its matrix rows in ops op_begin + 2g and
+                // op_begin + 2g + 1)
 };
 static_assert(sizeof(DevPhase) == 16, "DevPhase layout");
 
@@ -96,6 +97,7 @@ struct PassArgs {
   int lo_bits, win_lo, win_len;
   int n_tiles;           // batches << (h - T)
   int store;             // StoreMode of B
+  int kind;              // phase forms: 0 bond two, 1 bond four (dense)
   // 16-bit storage only: scales read (written by the previous writer, laid
   // out by in_map) and written (laid out by this pass's own tiles); batch
   // stride scale_stride floats

@@ -241,7 +241,7 @@ struct IterSlots {
   }
 };
 
-template <int R, bool MULTI, bool WU, int NT>
+template <int R, bool MULTI, bool WU, int NT, int KIND>
 __device__ __attribute__((always_inline)) inline void pass_body(const PassArgs& a, float2* lds, uint32_t bx,
                                                                 uint32_t gx) {
   constexpr int E = 1 << R;
@@ -290,7 +290,7 @@ __device__ __attribute__((always_inline)) inline void pass_body(const PassArgs& 
   const uint32_t rbase = (uint32_t)tile_in_block << (T + 3);
   for (int p = 0; p < a.n_phases; ++p) {
     const DevPhase P = load_phase(a.phases, p);
-    phase_dispatch<R, WU>(reinterpret_cast<char*>(lds), rbase, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs,
+    phase_dispatch<R, WU, KIND>(reinterpret_cast<char*>(lds), rbase, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs,
                           ctx, tt, TB, a.fmats + (size_t)p * kFusedWords);
     __syncthreads();
   }
@@ -306,21 +306,23 @@ __device__ __attribute__((always_inline)) inline void pass_body(const PassArgs& 
   }
 }
 
-template <int R, bool MULTI, bool WU, int NT = kBlock>
+// KIND 0: the bond-two phase forms (staircases, DUP, fused); KIND 1: the
+// bond-four ones (dense phases and single uncontrolled updates).
+template <int R, bool MULTI, bool WU, int NT = kBlock, int KIND = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_per_eu<R, WU, NT>()))) void k_pass(
     PassArgs a) {
   extern __shared__ float2 lds[];
-  pass_body<R, MULTI, WU, NT>(a, lds, blockIdx.x, gridDim.x);
+  pass_body<R, MULTI, WU, NT, KIND>(a, lds, blockIdx.x, gridDim.x);
 }
 
-template <int R, bool MULTI, bool WU, int NT = kBlock>
+template <int R, bool MULTI, bool WU, int NT = kBlock, int KIND = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_per_eu<R, WU, NT>()))) void k_pass_g(
     const Seg<PassArgs>* __restrict__ segs) {
   extern __shared__ float2 lds[];
   const Seg<PassArgs>* s = group_seg(segs);
   if (!s) return;
   const PassArgs a = s->a;
-  pass_body<R, MULTI, WU, NT>(a, lds, blockIdx.x, s->gx);
+  pass_body<R, MULTI, WU, NT, KIND>(a, lds, blockIdx.x, s->gx);
 }
 
 // The pass kernel on 16-bit block-scaled storage: the same tiles, phases,
@@ -330,7 +332,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_p
 // per block of this pass's tiles (taken from the block's largest component
 // after the pass).  4 entries (16 bytes) per HBM access, 2 when a thread
 // holds only 2 entries.
-template <int R, bool MULTI, int S, bool WU, int NT = kBlock>
+template <int R, bool MULTI, int S, bool WU, int NT = kBlock, int KIND = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_per_eu<R, WU, NT>()))) void k_pass16(
     PassArgs a) {
   extern __shared__ float2 lds[];
@@ -407,7 +409,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_p
   ctx.uniform = WU;
   for (int p = 0; p < a.n_phases; ++p) {
     const DevPhase P = load_phase(a.phases, p);
-    phase_dispatch<R, WU>(reinterpret_cast<char*>(lds), (uint32_t)tile_in_block << (T + 3), P,
+    phase_dispatch<R, WU, KIND>(reinterpret_cast<char*>(lds), (uint32_t)tile_in_block << (T + 3), P,
                           (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, TB,
                           a.fmats + (size_t)p * kFusedWords);
     __syncthreads();
@@ -514,15 +516,25 @@ hipError_t record_resolve(const ResolveArgs& a, Launch* L) {
 }
 
 template <int R, int NT, bool MULTI, bool WU>
-static void pick_pass(Launch* L) {
-  L->fn = reinterpret_cast<const void*>(&k_pass<R, MULTI, WU, NT>);
-  L->gfn = reinterpret_cast<const void*>(&k_pass_g<R, MULTI, WU, NT>);
+static void pick_pass(Launch* L, int kind) {
+  if (kind == 1) {
+    L->fn = reinterpret_cast<const void*>(&k_pass<R, MULTI, WU, NT, 1>);
+    L->gfn = reinterpret_cast<const void*>(&k_pass_g<R, MULTI, WU, NT, 1>);
+  } else {
+    L->fn = reinterpret_cast<const void*>(&k_pass<R, MULTI, WU, NT, 0>);
+    L->gfn = reinterpret_cast<const void*>(&k_pass_g<R, MULTI, WU, NT, 0>);
+  }
 }
 
 template <int R, int NT, bool MULTI, bool WU>
-static void pick_pass16(Launch* L, int store) {
-  if (store == STORE_F16) L->fn = reinterpret_cast<const void*>(&k_pass16<R, MULTI, STORE_F16, WU, NT>);
-  else L->fn = reinterpret_cast<const void*>(&k_pass16<R, MULTI, STORE_BF16, WU, NT>);
+static void pick_pass16(Launch* L, int store, int kind) {
+  if (kind == 1) {
+    if (store == STORE_F16) L->fn = reinterpret_cast<const void*>(&k_pass16<R, MULTI, STORE_F16, WU, NT, 1>);
+    else L->fn = reinterpret_cast<const void*>(&k_pass16<R, MULTI, STORE_BF16, WU, NT, 1>);
+  } else {
+    if (store == STORE_F16) L->fn = reinterpret_cast<const void*>(&k_pass16<R, MULTI, STORE_F16, WU, NT, 0>);
+    else L->fn = reinterpret_cast<const void*>(&k_pass16<R, MULTI, STORE_BF16, WU, NT, 0>);
+  }
 }
 
 // Block shape of a pass: one 2^(R+9)-entry tile per 512-thread block, one
@@ -540,18 +552,19 @@ static hipError_t record_pass_r(const PassArgs& a, Launch* L) {
   const long long blocks = ((long long)a.n_tiles + tiles_per_block - 1) / tiles_per_block;
   size_t lds = (size_t)tiles_per_block << (a.T + 3);
   if (s16) lds += (size_t)4 * NT;  // per-tile block maxima
+  if (a.kind != 0 && a.kind != 1) return hipErrorInvalidValue;
   if (TB == 9) {
-    if (s16) pick_pass16<R, 512, false, true>(L, a.store);
-    else pick_pass<R, 512, false, true>(L);
+    if (s16) pick_pass16<R, 512, false, true>(L, a.store, a.kind);
+    else pick_pass<R, 512, false, true>(L, a.kind);
   } else if (!multi) {
-    if (s16) pick_pass16<R, kBlock, false, true>(L, a.store);
-    else pick_pass<R, kBlock, false, true>(L);
+    if (s16) pick_pass16<R, kBlock, false, true>(L, a.store, a.kind);
+    else pick_pass<R, kBlock, false, true>(L, a.kind);
   } else if (TB >= 6) {
-    if (s16) pick_pass16<R, kBlock, true, true>(L, a.store);
-    else pick_pass<R, kBlock, true, true>(L);
+    if (s16) pick_pass16<R, kBlock, true, true>(L, a.store, a.kind);
+    else pick_pass<R, kBlock, true, true>(L, a.kind);
   } else {
-    if (s16) pick_pass16<R, kBlock, true, false>(L, a.store);
-    else pick_pass<R, kBlock, true, false>(L);
+    if (s16) pick_pass16<R, kBlock, true, false>(L, a.store, a.kind);
+    else pick_pass<R, kBlock, true, false>(L, a.kind);
   }
   set_arg(L, a);
   return set_shape(L, blocks, 1, NT, lds);
@@ -745,7 +758,12 @@ static void emulate_pass_r(const PassArgs& a) {
         continue;
       }
       for (int tt = 0; tt < tpt; ++tt)
-        phase_dispatch<R>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, (uint32_t)tt, TB);
+        if (a.kind == 1)
+          phase_dispatch<R, false, 1>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx,
+                                      (uint32_t)tt, TB);
+        else
+          phase_dispatch<R, false, 0>(region, 0u, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx,
+                                      (uint32_t)tt, TB);
     }
     if (s16) {
       const int nblk = 1 << (T - blk_bits);

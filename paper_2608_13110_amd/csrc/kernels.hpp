@@ -149,21 +149,22 @@ TNC_HD inline Regs<R> op_reg(Regs<R> v, const TNC_TBL float* __restrict__ m) {
   return v;
 }
 
-// A dense 4x4 on register bits (A, A+1): the entries with u = bit A +
-// 2 bit (A+1) become M (e_0 .. e_3); m: M row-major, 32 floats (re, im).
-template <int R, int A, class P>
+// A dense 4x4 on register bits (A, B), A < B: the entries with u = bit A +
+// 2 bit B become M (e_0 .. e_3); m: M row-major, 32 floats (re, im).
+template <int R, int A, int B, class P>
 TNC_HD inline Regs<R> op_dense(Regs<R> v, P m) {
   float k[32];
 #pragma unroll
   for (int e = 0; e < 32; ++e) k[e] = m[e];
 #pragma unroll
   for (int i = 0; i < (1 << R); ++i) {
-    if (i & (3 << A)) continue;
+    if (i & ((1 << A) | (1 << B))) continue;
     float ix[4], iy[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      ix[u] = v.x[i | (u << A)];
-      iy[u] = v.y[i | (u << A)];
+      const int j = i | ((u & 1) << A) | ((u >> 1) << B);
+      ix[u] = v.x[j];
+      iy[u] = v.y[j];
     }
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
@@ -173,8 +174,9 @@ TNC_HD inline Regs<R> op_dense(Regs<R> v, P m) {
         ox = ox + k[8 * o + 2 * u] * ix[u] - k[8 * o + 2 * u + 1] * iy[u];
         oy = oy + k[8 * o + 2 * u] * iy[u] + k[8 * o + 2 * u + 1] * ix[u];
       }
-      v.x[i | (o << A)] = ox;
-      v.y[i | (o << A)] = oy;
+      const int j = i | ((o & 1) << A) | ((o >> 1) << B);
+      v.x[j] = ox;
+      v.y[j] = oy;
     }
   }
   return v;
@@ -327,10 +329,20 @@ TNC_HD inline void phase_exec(char* base, uint32_t rbase, const DevPhase& P, con
   for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(base + off[i]) = make_float2(v.x[i], v.y[i]);
 }
 
-// A dense phase: G dense 4x4 updates, update g on register bits (2g, 2g+1)
-// with the 32 floats of ops op_begin + 2g, op_begin + 2g + 1 (rows 0-1,
-// rows 2-3).  Same register entries and LDS placement as phase_exec.
-template <int R, int G>
+// Between the updates of a dense phase: keeps each update's 32 matrix
+// values from being loaded ahead of the previous update (four updates' worth
+// would not fit the scalar registers and would move to vector registers).
+TNC_HD inline void dense_fence() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
+// A dense phase: n_ops / 2 dense 4x4 updates in order, update g on the
+// register-bit pair of its code (4 bits of reg[6..7]) with the 32 floats of
+// ops op_begin + 2g, op_begin + 2g + 1 (rows 0-1, rows 2-3).  Same register
+// entries and LDS placement as phase_exec.
+template <int R>
 TNC_HD inline void phase_dense(char* base, uint32_t rbase, const DevPhase& P, const TNC_TBL uint32_t* po,
                                const PhaseCtx<R>& c, uint32_t tt, int TB) {
   constexpr int E = 1 << R;
@@ -345,8 +357,49 @@ TNC_HD inline void phase_dense(char* base, uint32_t rbase, const DevPhase& P, co
     v.x[i] = t.x;
     v.y[i] = t.y;
   }
-  v = op_dense<R, 0>(v, c.rm + (size_t)P.op_begin * 16);
-  if constexpr (G >= 2) v = op_dense<R, 2>(v, c.rm + (size_t)(P.op_begin + 2) * 16);
+  const int G = P.n_ops / 2;
+  const uint32_t codes = (uint32_t)(uint8_t)P.reg[6] | ((uint32_t)(uint8_t)P.reg[7] << 8);
+  const TNC_TBL float* m = c.rm + (size_t)P.op_begin * 16;
+  // one straight-line form per pattern (dense_form_exists)
+  switch ((uint32_t)G << 16 | codes) {
+    case 1u << 16 | 0x0u:
+      v = op_dense<R, 0, 1>(v, m);
+      break;
+    case 2u << 16 | 0x40u:
+      if constexpr (R >= 3) {
+        v = op_dense<R, 0, 1>(v, m);
+        v = op_dense<R, 1, 2>(v, m + 32);
+      }
+      break;
+    case 2u << 16 | 0x70u:
+      if constexpr (R >= 4) {
+        v = op_dense<R, 0, 1>(v, m);
+        v = op_dense<R, 2, 3>(v, m + 32);
+      }
+      break;
+    case 3u << 16 | 0x940u:
+      if constexpr (R >= 5) {
+        v = op_dense<R, 0, 1>(v, m);
+        dense_fence();
+        v = op_dense<R, 1, 2>(v, m + 32);
+        dense_fence();
+        v = op_dense<R, 3, 4>(v, m + 64);
+      }
+      break;
+    case 4u << 16 | 0x3940u:
+      if constexpr (R >= 5) {
+        v = op_dense<R, 0, 1>(v, m);
+        dense_fence();
+        v = op_dense<R, 1, 2>(v, m + 32);
+        dense_fence();
+        v = op_dense<R, 3, 4>(v, m + 64);
+        dense_fence();
+        v = op_dense<R, 0, 4>(v, m + 96);
+      }
+      break;
+    default:
+      break;  // excluded on the host (dense_form_exists)
+  }
 #pragma unroll
   for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(base + off[i]) = make_float2(v.x[i], v.y[i]);
 }
@@ -436,20 +489,22 @@ __device__ __attribute__((always_inline)) inline void phase_tri(char* base, uint
 // device.
 TNC_HD constexpr bool phase_form_exists(int R, int n_ops, int form) {
   return form == 1   ? (R >= 3 && n_ops >= 3 && n_ops <= R + 2 && n_ops <= 7)
-         : form == 2 ? ((n_ops == 2 && R >= 2) || (n_ops == 4 && R >= 4)) && R <= 5
+         : form == 2 ? (R >= 2 && R <= 5 && n_ops >= 2 && n_ops <= 8 && n_ops % 2 == 0)
                      : (n_ops >= 1 && n_ops <= R && R <= 5);
 }
 
 // TRI: the kernel runs fused phases (P.pad = 1); the host plans them only for
-// kernels whose waves each lie inside one tile.
-template <int R, bool TRI = false>
+// kernels whose waves each lie inside one tile.  KIND 0: the bond-two forms;
+// KIND 1: the bond-four forms, dense phases (P.pad = 2) and single
+// uncontrolled updates (the host checks that a bond-four plan has no other).
+template <int R, bool TRI = false, int KIND = 0>
 TNC_HD inline void phase_dispatch(char* base, uint32_t rbase, const DevPhase& P, const TNC_TBL uint32_t* po,
                                   const PhaseCtx<R>& c, uint32_t tt, int TB, const float4* fm = nullptr) {
-  if (P.pad == 2) {
-    if constexpr (R >= 2) {
-      if (P.n_ops == 2) phase_dense<R, 1>(base, rbase, P, po, c, tt, TB);
-      if constexpr (R >= 4)
-        if (P.n_ops == 4) phase_dense<R, 2>(base, rbase, P, po, c, tt, TB);
+  if constexpr (KIND == 1) {
+    if (P.pad == 2) {
+      if constexpr (R >= 2) phase_dense<R>(base, rbase, P, po, c, tt, TB);
+    } else {
+      phase_exec<R, 1, 1>(base, rbase, P, po, c, tt, TB);
     }
     return;
   }

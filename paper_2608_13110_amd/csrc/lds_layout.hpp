@@ -1,5 +1,6 @@
-// LDS placement of a pass tile, shared by the kernels (kernels.hpp) and the
-// host planner (plan.cpp), which places each phase's lane bits by it.
+// LDS placement of a pass tile, and the table of dense phase forms, shared
+// by the kernels (kernels.hpp) and the host planner (plan.cpp), which places
+// each phase's lane bits and cuts each dense phase by them.
 #pragma once
 
 #include <cstdint>
@@ -44,5 +45,22 @@ TNC_LDS_HD inline uint32_t lane_slot_dir(int p) { return swz(1u << p) & 31u; }
 // (swz is linear: for disjoint bit sets, swz(a | b) = swz(a) ^ swz(b).)
 TNC_LDS_HD inline uint32_t pair_slot(uint32_t s) { return (s & ~1u) << 3; }
 TNC_LDS_HD inline bool pair_swapped(uint32_t s) { return (s & 1u) != 0u; }
+
+// Register-bit pairs (A, B), A < B < 5, numbered in lexicographic order:
+// the codes of a dense phase's updates.
+TNC_LDS_HD constexpr int dense_pair_code(int a, int b) {
+  return a == 0 ? b - 1 : a == 1 ? 2 + b : a == 2 ? 4 + b : 9;
+}
+
+// The dense phase forms: G updates whose codes (4 bits each, update 0 in the
+// low bits) are one of the register-bit patterns the planner produces, each
+// compiled as straight-line code: a wavefront step of two rows is (0,1)
+// (1,2), then (3,4) (0,4); a row alone is (0,1) (2,3).  The planner cuts a
+// phase to its longest prefix that has a form.
+TNC_LDS_HD constexpr bool dense_form_exists(int R, int G, uint32_t codes) {
+  return (G == 1 && codes == 0x0u && R >= 2) || (G == 2 && codes == 0x40u && R >= 3) ||
+         (G == 2 && codes == 0x70u && R >= 4) || (G == 3 && codes == 0x940u && R >= 5) ||
+         (G == 4 && codes == 0x3940u && R >= 5);
+}
 
 }  // namespace tnc

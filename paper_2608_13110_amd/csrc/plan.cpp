@@ -574,6 +574,38 @@ std::vector<Window> window_grid(const Plan& p, int hmax) {
   return ws;
 }
 
+// Windows overlapping by `ov` slots: the contiguous bottom [0, T-1], then
+// windows of T - C slots above C low slots, evenly spaced up to the top slot
+// (the bond-four wavefront's updates span three slots, so its windows
+// overlap by two: a unit at a boundary then lies wholly in one of them).
+std::vector<Window> window_grid_overlap(const Plan& p, int hmax, int ov) {
+  const int T = p.opt.max_tile_bits;
+  const int C = p.opt.low_bits;
+  std::vector<Window> ws;
+  Window w;
+  w.lo_bits = 0;
+  w.win_lo = 0;
+  w.win_len = std::min(hmax, T);
+  ws.push_back(w);
+  if (hmax <= T) return ws;
+  const int L = T - C;
+  const int S = T - ov, E = hmax - 1;
+  if (L <= ov) return window_grid(p, hmax);
+  const int m = std::max(1, (E - S + 1 - ov + (L - ov) - 1) / (L - ov));
+  const int last = E - L + 1;
+  for (int k = 0; k < m; ++k) {
+    Window x;
+    x.lo_bits = C;
+    x.win_lo = m == 1 ? std::max(S, last) : S + (int)std::lround((double)(last - S) * k / (m - 1));
+    x.win_len = std::min(L, hmax - x.win_lo);
+    if (x.win_lo < C) {  // would overlap the low slots: fall back
+      return window_grid(p, hmax);
+    }
+    ws.push_back(x);
+  }
+  return ws;
+}
+
 // GF(2) span of lane slot directions (bit masks), one basis vector per
 // leading bit.
 struct Gf2Basis {
@@ -761,18 +793,39 @@ void plan_phases(Pass& ps, const std::vector<SweepOp>& ops, int R, bool fuse) {
     Phase ph;
     ph.op_begin = i;
     if (ops[i].kind == OP_D4) {
-      // dense phase: up to two 4x4 updates on disjoint slot pairs, update g
-      // on register bits (2g, 2g+1)
+      // dense phase: up to four consecutive 4x4 updates whose slots fit in
+      // the register bits (they may share slots: the updates run in order)
       std::vector<int> regs;
-      int j = i;
-      while (j + 1 < ps.op_end && ops[j].kind == OP_D4 && int(regs.size()) + 2 <= std::min(4, Reff)) {
+      auto at = [&](int b) { return int(std::find(regs.begin(), regs.end(), b) - regs.begin()); };
+      int j = i, g = 0;
+      while (j + 1 < ps.op_end && ops[j].kind == OP_D4 && g < 4) {
         const int lo = ps.w.local(ops[j].target), hi = ps.w.local(ops[j].pair);
-        if (std::find(regs.begin(), regs.end(), lo) != regs.end() ||
-            std::find(regs.begin(), regs.end(), hi) != regs.end())
-          break;
-        regs.push_back(lo);
-        regs.push_back(hi);
+        const int need = int(regs.size()) + (at(lo) == int(regs.size()) ? 1 : 0) + (at(hi) == int(regs.size()) ? 1 : 0);
+        if (need > std::min(5, Reff)) break;
+        if (at(lo) == int(regs.size())) regs.push_back(lo);
+        if (at(hi) == int(regs.size())) regs.push_back(hi);
+        ph.dreg[g][0] = at(lo);
+        ph.dreg[g][1] = at(hi);
         j += 2;
+        ++g;
+      }
+      // the longest prefix with a kernel form (one update always has one)
+      while (g > 1) {
+        uint32_t codes = 0;
+        for (int q = 0; q < g; ++q)
+          codes |= (uint32_t)dense_pair_code(std::min(ph.dreg[q][0], ph.dreg[q][1]),
+                                             std::max(ph.dreg[q][0], ph.dreg[q][1])) << (4 * q);
+        if (dense_form_exists(std::min(5, Reff), g, codes)) break;
+        --g;
+        j -= 2;
+      }
+      // registers of the dropped updates go back to padding
+      {
+        std::vector<int> keep;
+        for (int q = 0; q < g; ++q)
+          for (int b : {ph.dreg[q][0], ph.dreg[q][1]})
+            if (std::find(keep.begin(), keep.end(), regs[b]) == keep.end()) keep.push_back(regs[b]);
+        if (keep.size() < regs.size()) regs.resize(keep.size());  // a prefix: first-seen order
       }
       // (a tile too small for one dense update: the table builder refuses
       // the phase, which takes the update all the same)
@@ -872,7 +925,7 @@ void split_triples(Pass& ps, const std::vector<SweepOp>& ops) {
 std::vector<Pass> plan_passes(const Plan& p, const std::vector<SweepOp>& ops, int R) {
   std::vector<Pass> passes;
   if (ops.empty()) return passes;
-  auto ws = window_grid(p, p.h);
+  auto ws = p.chi == 4 && !p.spatial ? window_grid_overlap(p, p.h, 2) : window_grid(p, p.h);
   int i = 0;
   const int nops = int(ops.size());
   while (i < nops) {
@@ -980,12 +1033,51 @@ int schedule4(Plan& p, Schedule& s, std::string* err) {
   const int n = p.n, W = p.h;
   s.last_fixed_row = p.spatial ? n - 1 : n - 2;
   s.m_fix = W;
-  for (int r = 1; r <= (p.spatial ? 1 : n - 2); ++r)
-    for (const SweepOp& op : p.row_ops[r]) {
-      const size_t m = s.ops.size();
-      if (m >= 2 && s.ops[m - 2].kind == OP_D4 && merge_into_dense(s.ops[m - 2], s.ops[m - 1], op)) continue;
-      s.ops.push_back(op);
+  auto emit = [&](const SweepOp& op) {
+    const size_t m = s.ops.size();
+    if (m >= 2 && s.ops[m - 2].kind == OP_D4 && merge_into_dense(s.ops[m - 2], s.ops[m - 1], op)) return;
+    s.ops.push_back(op);
+  };
+  auto emit_gate = [&](const std::vector<SweepOp>& ro, size_t at) {
+    emit(ro[at]);
+    emit(ro[at + 1]);
+  };
+  if (p.spatial) {
+    for (const SweepOp& op : p.row_ops[1]) emit(op);
+  } else {
+    // Rows go in pairs (A -> B row q, then B -> A row q+1), swept from the
+    // top down as one wavefront: a 4x4 of row q+1 on (2j, 2j+1) follows
+    // right after the 4x4 of row q on (2j-1, 2j), the last of its two
+    // predecessors, so consecutive updates share slots and one pass carries
+    // both rows through its window.  A row without a partner is listed on
+    // its own.  Row q's 2x2 on slot 0 goes first (it meets nothing of row q
+    // before row q+1's 4x4 on (0, 1)) and merges into the bottom 4x4 of the
+    // pair before; row q+1's top 2x2 merges into row q's top 4x4.
+    const int hc = (W + 1) / 2;
+    int q = 1;
+    while (q <= n - 2) {
+      const std::vector<SweepOp>& A = p.row_ops[q];
+      if (p.row_ascending[q] && q + 1 <= n - 2 && hc >= 2) {
+        const std::vector<SweepOp>& B = p.row_ops[q + 1];
+        // A: [2x2 on 0, 4x4 (2j-1, 2j) for j = 1..hc-1, two ops each]
+        // B: [2x2 on top, 4x4 (2j, 2j+1) for j = hc-2..0, two ops each]
+        auto a_at = [&](int j) { return (size_t)(1 + 2 * (j - 1)); };
+        auto b_at = [&](int j) { return (size_t)(1 + 2 * (hc - 2 - j)); };
+        emit(A[0]);
+        emit_gate(A, a_at(hc - 1));
+        emit(B[0]);
+        for (int j = hc - 2; j >= 1; --j) {
+          emit_gate(A, a_at(j));
+          emit_gate(B, b_at(j));
+        }
+        emit_gate(B, b_at(0));
+        q += 2;
+      } else {
+        for (const SweepOp& op : A) emit(op);
+        q += 1;
+      }
     }
+  }
   // a dense update holds two register bits
   s.reg_bits = std::max(2, std::min(p.opt.reg_bits, W));
   s.passes = plan_passes(p, s.ops, s.reg_bits);

@@ -127,13 +127,15 @@ constexpr int kMaxThreadBits = 9;
 // and tpos[4], tpos[5] (lane bits 4 and 5); op 0's control, if any, is
 // reg[R-1]; the staircase goes on on the vector ALUs: update 3 targets
 // reg[1] under tpos[5], update b > 3 reg[b-2] under reg[b-3].  mf = 2: a
-// dense phase of one or two 4x4 updates (OP_D4 + OP_D4H each), update g on
-// register bits (2g, 2g+1).  tpos[t] is the tile bit of thread bit t.
+// dense phase of up to four 4x4 updates (OP_D4 + OP_D4H each), update g on
+// register bits dreg[g] (its lower, upper slot).  tpos[t] is the tile bit
+// of thread bit t.
 struct Phase {
   int op_begin = 0, op_end = 0;
   int reg[kMaxReg] = {0};  // local tile bits held in registers, in register-bit order
   int mf = 0;
   int tpos[kMaxThreadBits] = {0};
+  int dreg[4][2] = {};     // dense phases: register bits of update g's lower and upper slot
 };
 
 struct Pass {

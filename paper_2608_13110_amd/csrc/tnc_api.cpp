@@ -167,6 +167,15 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
     if (std::find_if(fused_at.begin(), fused_at.end(), [](int v) { return v >= 0; }) != fused_at.end())
       t->fmats.assign((size_t)gp * kFusedWords, make_float4(0.f, 0.f, 0.f, 0.f));
   }
+  // dense updates whose lower slot sits on the higher register bit of their
+  // phase are stored with the two slots exchanged (the kernel takes bit 0 of
+  // the 4x4's index from the lower register bit)
+  std::vector<char> d4swap(nops, 0);
+  for (const Pass& ps : s.passes)
+    for (const Phase& pp : ps.phases)
+      if (pp.mf == 2)
+        for (int g = 0; g < (pp.op_end - pp.op_begin) / 2 && g < 4; ++g)
+          if (pp.dreg[g][0] > pp.dreg[g][1]) d4swap[pp.op_begin + 2 * g] = d4swap[pp.op_begin + 2 * g + 1] = 1;
   cd acc = 0;  // running rounding bias of the sweep (sum of rho - 1)
   size_t fused_left = 0;
   for (size_t o = 0; o < nops; ++o) {
@@ -191,8 +200,9 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
       for (int var = 0; var < 4; ++var) {
         cd K[16];
         float K32[32];
+        auto sw = [&](int u) { return d4swap[o] ? (((u & 1) << 1) | (u >> 1)) : u; };
         for (int rr = 0; rr < 4; ++rr)
-          for (int c = 0; c < 4; ++c) K[4 * rr + c] = (rr < 2 ? op : hb).mat[var][rr & 1].a[c];
+          for (int c = 0; c < 4; ++c) K[4 * rr + c] = (sw(rr) < 2 ? op : hb).mat[var][sw(rr) & 1].a[sw(c)];
         const cd r = round_entries(K, 16, acc, K32);
         if (var == 0) step = r;
         std::copy(K32, K32 + 16, t->mats.data() + (o * 4 + var) * 16);
@@ -235,6 +245,10 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
       // a fused phase holds two targets in lane bits: up to R + 2 updates;
       // every phase must have an instantiated kernel form
       if (!phase_form_exists(R, nops, pp.mf)) return fail_t("phase size without a kernel form");
+      // the bond-four kernels run dense phases and single uncontrolled updates only
+      if (p.chi == 4 && pp.mf != 2 &&
+          (nops != 1 || pp.mf != 0 || s.ops[pp.op_begin].kind != OP_CU || s.ops[pp.op_begin].control >= 0))
+        return fail_t("bond-four phase without a kernel form");
       DevPhase dp;
       std::memset(&dp, 0, sizeof(dp));
       dp.op_begin = pp.op_begin;
@@ -303,16 +317,25 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
         continue;
       }
       if (pp.mf == 2) {
-        // dense phase: update g = ops (2g, 2g+1) on register bits (2g, 2g+1)
+        // dense phase: update g = ops (2g, 2g+1) on register bits dreg[g];
+        // its code (the register-bit pair, lower bit first) in 4 bits of
+        // reg[6..7]
+        uint32_t codes = 0;
         for (int g = 0; g < nops / 2; ++g) {
           const SweepOp& a = s.ops[pp.op_begin + 2 * g];
           const SweepOp& b = s.ops[pp.op_begin + 2 * g + 1];
-          if (a.kind != OP_D4 || b.kind != OP_D4H || b.target != a.target || b.pair != a.pair ||
-              !ps.w.contains(a.target) || !ps.w.contains(a.pair) || ps.w.local(a.target) != pp.reg[2 * g] ||
-              ps.w.local(a.pair) != pp.reg[2 * g + 1] || b.xrow[0] != a.xrow[0] || b.xrow[1] != a.xrow[1])
+          const int P = pp.dreg[g][0], Q = pp.dreg[g][1];
+          if (a.kind != OP_D4 || b.kind != OP_D4H || b.target != a.target || b.pair != a.pair || P == Q || P < 0 ||
+              Q < 0 || P >= R || Q >= R || !ps.w.contains(a.target) || !ps.w.contains(a.pair) ||
+              ps.w.local(a.target) != pp.reg[P] || ps.w.local(a.pair) != pp.reg[Q] || b.xrow[0] != a.xrow[0] ||
+              b.xrow[1] != a.xrow[1])
             return fail_t("dense phase not canonical");
+          codes |= (uint32_t)dense_pair_code(std::min(P, Q), std::max(P, Q)) << (4 * g);
         }
+        if (!dense_form_exists(R, nops / 2, codes)) return fail_t("dense phase pattern without a kernel form");
         t->phases.back().pad = 2;
+        t->phases.back().reg[6] = (int8_t)(codes & 0xFFu);
+        t->phases.back().reg[7] = (int8_t)((codes >> 8) & 0xFFu);
       }
       // thread bits: every tile bit outside the registers exactly once
       {
@@ -658,6 +681,7 @@ PassArgs pass_args(const Plan& p, const PassHost& ph, const DevPhase* phases, co
   a.win_lo = ph.w.win_lo;
   a.win_len = ph.w.win_len;
   a.n_tiles = nb << (p.h - a.T);
+  a.kind = p.chi == 4 ? 1 : 0;
   return a;
 }
 
