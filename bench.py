@@ -350,7 +350,9 @@ def storage_modes(torch, W, Plan, profile_begin, profile_end, batches=16):
 BOND4 = dict(n=34, d=34, desc="bond4 n=34 d=34 w=33 (2^33 c64 boundary), Haar-random two-qubit gates, "
                                 "k=0, 1 batch/step")
 BOND4_CANDIDATES = [dict(max_tile_bits=13, low_bits=5, reg_bits=4), dict(max_tile_bits=13, low_bits=5, reg_bits=5),
-                    dict(max_tile_bits=12, low_bits=4, reg_bits=4), dict()]
+                    dict(max_tile_bits=13, low_bits=5, reg_bits=4, math=2),
+                    dict(max_tile_bits=13, low_bits=4, reg_bits=4, math=2),
+                    dict(max_tile_bits=13, low_bits=5, reg_bits=5, math=2)]
 
 
 def bond4_bench(torch, W, Plan, profile_begin, profile_end, steps=3):

@@ -683,12 +683,23 @@ static void emulate_tri(char* region, const DevPhase& P, const uint32_t* po, con
         vy[l][2 * j + 1] = out[l][3];
       }
     }
-    // the staircase tail, lane by lane
+    // the staircase tail (a unit phase: the next step's 4x4s), lane by lane
     for (int l = 0; l < 64; ++l) {
       Regs<R> v;
       for (int i = 0; i < E; ++i) {
         v.x[i] = vx[l][i];
         v.y[i] = vy[l][i];
+      }
+      if (P.pad == 3) {
+        if (P.n_ops == 8) {
+          v = op_dense<R, 1, 2>(v, rm + (size_t)(P.op_begin + 4) * 16);
+          v = op_dense<R, 0, 2>(v, rm + (size_t)(P.op_begin + 6) * 16);
+        }
+        for (int i = 0; i < E; ++i) {
+          vx[l][i] = v.x[i];
+          vy[l][i] = v.y[i];
+        }
+        continue;
       }
       if (P.n_ops >= 4) v = op_sel<R, 1>(v, rm + (size_t)(P.op_begin + 3) * 16 + 8 * ((l >> 5) & 1));
       if (P.n_ops >= 5) v = op_reg<R, 2, 1>(v, (const TNC_TBL float*)(rm + (size_t)(P.op_begin + 4) * 16));
@@ -751,7 +762,7 @@ static void emulate_pass_r(const PassArgs& a) {
     ctx.uniform = false;
     for (int p = 0; p < a.n_phases; ++p) {
       const DevPhase P = load_phase(a.phases, p);
-      if (P.pad == 1) {
+      if (P.pad == 1 || P.pad == 3) {
         if constexpr (R >= 3)
           emulate_tri<R>(region, P, a.poffs + p * kPhaseOffs, a.fmats + (size_t)p * kFusedWords,
                          a.rmats + (size_t)batch * a.rstride, TB);

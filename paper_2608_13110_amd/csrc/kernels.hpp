@@ -425,15 +425,37 @@ TNC_HD inline void phase_forms(char* base, uint32_t rbase, const DevPhase& P, co
 // tpos[t], whose LDS offset is po[kPhaseEntries + t].  Updates 3..N-1 then
 // go on on the vector ALUs: update 3 on register bit 1 under lane bit 5
 // (b2), update b > 3 on register bit b - 2 under register bit b - 3.
+// The complex 8x8 of a fused phase on the matrix cores (layout above): the
+// operands for groups with register bit R-1 clear are F[lane], for those
+// with it set F[64 + lane].
+template <int R>
+__device__ __attribute__((always_inline)) inline Regs<R> tri_product(Regs<R> v, const float4* __restrict__ F,
+                                                                     int lane) {
+  constexpr int G = (1 << R) / 2;
+  const float4 a0 = F[lane];
+  const float4 a1 = F[64 + lane];
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    const float4 a = j >= G / 2 ? a1 : a0;
+    tnc_floatx4 d = {0.f, 0.f, 0.f, 0.f};
+    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, v.x[2 * j], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, v.y[2 * j], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, v.x[2 * j + 1], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, v.y[2 * j + 1], d, 0, 0, 0);
+    v.x[2 * j] = d[0];
+    v.y[2 * j] = d[1];
+    v.x[2 * j + 1] = d[2];
+    v.y[2 * j + 1] = d[3];
+  }
+  return v;
+}
+
 template <int R, int N>
 __device__ __attribute__((always_inline)) inline void phase_tri(char* base, uint32_t rbase, const DevPhase& P,
                                                                 const TNC_TBL uint32_t* po, const float4* __restrict__ F,
                                                                 const PhaseCtx<R>& c, uint32_t tt, int TB) {
   constexpr int E = 1 << R;
-  constexpr int G = E / 2;
   const int lane = (int)(tt & 63u);
-  const float4 a0 = F[lane];
-  const float4 a1 = F[64 + lane];
   const uint32_t vb = phase_thread_base(rbase, po, tt, TB);
   uint32_t off[E];
 #pragma unroll
@@ -448,19 +470,7 @@ __device__ __attribute__((always_inline)) inline void phase_tri(char* base, uint
   // every LDS read in flight before the first product (the scheduler would
   // otherwise wait on each read in turn)
   __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int j = 0; j < G; ++j) {
-    const float4 a = j >= G / 2 ? a1 : a0;
-    tnc_floatx4 d = {0.f, 0.f, 0.f, 0.f};
-    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, v.x[2 * j], d, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, v.y[2 * j], d, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, v.x[2 * j + 1], d, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, v.y[2 * j + 1], d, 0, 0, 0);
-    v.x[2 * j] = d[0];
-    v.y[2 * j] = d[1];
-    v.x[2 * j + 1] = d[2];
-    v.y[2 * j + 1] = d[3];
-  }
+  v = tri_product<R>(v, F, lane);
   if constexpr (N >= 4) {
     const TNC_TBL float* m = c.rm + (size_t)(P.op_begin + 3) * 16;
     const bool hi = (lane >> 5) & 1;
@@ -480,16 +490,54 @@ __device__ __attribute__((always_inline)) inline void phase_tri(char* base, uint
 #pragma unroll
   for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(base + off[i]) = make_float2(v.x[i], v.y[i]);
 }
+
+// A bond-four unit phase (P.pad = 3): one wavefront step, the 4x4 on (b0,
+// b1) then the 4x4 on (b1, b2), as one complex 8x8 on the matrix cores (the
+// layout of phase_tri: b0 = register bit 0, b1 and b2 = lane bits 4 and 5);
+// with n_ops = 8, the next step's two updates follow on the vector ALUs, on
+// register bits (1, 2) and then (0, 2) (ops op_begin + 4 .. + 7; the first
+// of them does not read the product and can run beside it).
+template <int R>
+__device__ __attribute__((always_inline)) inline void phase_unit(char* base, uint32_t rbase, const DevPhase& P,
+                                                                 const TNC_TBL uint32_t* po, const float4* __restrict__ F,
+                                                                 const PhaseCtx<R>& c, uint32_t tt, int TB) {
+  constexpr int E = 1 << R;
+  const int lane = (int)(tt & 63u);
+  const uint32_t vb = phase_thread_base(rbase, po, tt, TB);
+  uint32_t off[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) off[i] = vb ^ po[i];
+  Regs<R> v;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const float2 t = *reinterpret_cast<const float2*>(base + off[i]);
+    v.x[i] = t.x;
+    v.y[i] = t.y;
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  v = tri_product<R>(v, F, lane);
+  if constexpr (R >= 3) {
+    if (P.n_ops == 8) {
+      const TNC_TBL float* m = c.rm + (size_t)(P.op_begin + 4) * 16;
+      v = op_dense<R, 1, 2>(v, m);
+      v = op_dense<R, 0, 2>(v, m + 32);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(base + off[i]) = make_float2(v.x[i], v.y[i]);
+}
 #endif
 
 // Register phases with an instantiated form: a canonical phase of 1..R
-// updates (form 0), a fused phase of 3..R+2 updates (form 1), or a dense
-// phase of one 4x4 (two ops; R >= 2) or two (four ops; R >= 4) (form 2);
+// updates (form 0), a fused phase of 3..R+2 updates (form 1), a dense phase
+// of one to four 4x4s (two ops each; form 2), or a bond-four unit phase of
+// two or four 4x4s (form 3);
 // the planner checks every phase against this before the tables reach the
 // device.
 TNC_HD constexpr bool phase_form_exists(int R, int n_ops, int form) {
   return form == 1   ? (R >= 3 && n_ops >= 3 && n_ops <= R + 2 && n_ops <= 7)
          : form == 2 ? (R >= 2 && R <= 5 && n_ops >= 2 && n_ops <= 8 && n_ops % 2 == 0)
+         : form == 3 ? (R >= 3 && R <= 5 && (n_ops == 4 || n_ops == 8))
                      : (n_ops >= 1 && n_ops <= R && R <= 5);
 }
 
@@ -503,6 +551,10 @@ TNC_HD inline void phase_dispatch(char* base, uint32_t rbase, const DevPhase& P,
   if constexpr (KIND == 1) {
     if (P.pad == 2) {
       if constexpr (R >= 2) phase_dense<R>(base, rbase, P, po, c, tt, TB);
+#if defined(__HIP_DEVICE_COMPILE__)
+    } else if (P.pad == 3) {
+      if constexpr (TRI && R >= 3) phase_unit<R>(base, rbase, P, po, fm, c, tt, TB);
+#endif
     } else {
       phase_exec<R, 1, 1>(base, rbase, P, po, c, tt, TB);
     }

@@ -788,10 +788,56 @@ void plan_phases(Pass& ps, const std::vector<SweepOp>& ops, int R, bool fuse) {
   const int T = ps.w.tile_bits();
   const int Reff = pass_reg_bits(R, T);
   fuse = fuse && Reff >= 3 && T - Reff >= 6 && T - Reff <= kMaxThreadBits;
+  // a bond-four wavefront step: 4x4s A on (a, a+1) and B on (a+1, a+2)
+  // without output-bit variants
+  auto unit_at = [&](int k) {
+    if (k + 3 >= ps.op_end || ops[k].kind != OP_D4 || ops[k + 2].kind != OP_D4) return false;
+    const SweepOp& A = ops[k];
+    const SweepOp& B = ops[k + 2];
+    return B.target == A.pair && B.pair == A.pair + 1 && A.pair == A.target + 1 && A.xrow[0] < 0 && A.xrow[1] < 0 &&
+           B.xrow[0] < 0 && B.xrow[1] < 0;
+  };
   int i = ps.op_begin;
   while (i < ps.op_end) {
     Phase ph;
     ph.op_begin = i;
+    if (fuse && unit_at(i)) {
+      // unit phase: A and B as one 8x8 on the matrix cores (b0 = register
+      // bit 0, b1 and b2 = lane bits 4 and 5), then the next step (C on
+      // (a-2, a-1), D on (a-1, a)) on register bits (1, 2) and (2, 0)
+      const int b0 = ps.w.local(ops[i].target), b1 = ps.w.local(ops[i].pair), b2 = ps.w.local(ops[i + 2].pair);
+      std::vector<int> regs = {b0};
+      int j = i + 4;
+      const int a = ops[i].target;
+      if (i + 7 < ps.op_end && ops[i + 4].kind == OP_D4 && ops[i + 6].kind == OP_D4 && a >= 2 &&
+          ops[i + 4].target == a - 2 && ops[i + 4].pair == a - 1 && ops[i + 6].target == a - 1 &&
+          ops[i + 6].pair == a) {
+        regs.push_back(ps.w.local(a - 2));
+        regs.push_back(ps.w.local(a - 1));
+        ph.dreg[2][0] = 1;
+        ph.dreg[2][1] = 2;
+        ph.dreg[3][0] = 2;
+        ph.dreg[3][1] = 0;
+        j = i + 8;
+      }
+      ph.op_end = j;
+      ph.mf = 3;
+      std::vector<int> rest;
+      for (int c = 0; c < T; ++c)
+        if (c != b1 && c != b2 && std::find(regs.begin(), regs.end(), c) == regs.end()) rest.push_back(c);
+      const std::vector<int> lanes = lane_order(rest, b1, b2);
+      for (int t = 0; t < 6; ++t) ph.tpos[t] = lanes[t];
+      std::vector<int> left(lanes.begin() + 6, lanes.end());
+      size_t q = 0;
+      while (int(regs.size()) < Reff) regs.push_back(left[q++]);
+      for (int r = 0; r < kMaxReg; ++r) ph.reg[r] = r < int(regs.size()) ? regs[r] : -1;
+      const int TB = T - Reff;
+      for (int t = 6; t < TB; ++t) ph.tpos[t] = left[q++];
+      for (int t = TB; t < kMaxThreadBits; ++t) ph.tpos[t] = -1;
+      ps.phases.push_back(ph);
+      i = j;
+      continue;
+    }
     if (ops[i].kind == OP_D4) {
       // dense phase: up to four consecutive 4x4 updates whose slots fit in
       // the register bits (they may share slots: the updates run in order)

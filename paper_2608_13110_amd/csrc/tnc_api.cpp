@@ -123,6 +123,28 @@ void fused_matrix(const SweepOp* op, int c, cd* U) {
   }
 }
 
+// A bond-four unit's two 4x4s (A on (b0, b1), then B on (b1, b2); ops
+// op[0..1] and op[2..3], variant 0) as one complex 8x8 on entry index
+// e = b0 + 2 b1 + 4 b2.  U[e' * 8 + e].
+void unit_matrix(const SweepOp* op, cd* U) {
+  auto m4 = [&](int k, int r, int c) { return (r < 2 ? op[k] : op[k + 1]).mat[0][r & 1].a[c]; };
+  for (int e = 0; e < 8; ++e) {
+    cd z[8] = {};
+    z[e] = 1;
+    for (int k = 0; k < 4; k += 2) {
+      const int lo = k == 0 ? 0 : 1;  // A on bits (0, 1), B on bits (1, 2)
+      cd w[8] = {};
+      for (int i = 0; i < 8; ++i) {
+        const int u = ((i >> lo) & 3);
+        const int rest = i & ~(3 << lo);
+        for (int o = 0; o < 4; ++o) w[rest | (o << lo)] += m4(k, o, u) * z[i];
+      }
+      std::copy(w, w + 8, z);
+    }
+    for (int eo = 0; eo < 8; ++eo) U[eo * 8 + e] = z[eo];
+  }
+}
+
 // Matrix-core operand of a fused phase for one control value: lane l holds,
 // at MFMA step s, A[l % 16][4 s + l / 16] of the real 16x16 form of U32.
 // Real index 4 g + t (rows) / 4 t + g (columns) stands for entry
@@ -155,9 +177,9 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
     int gp = 0;
     for (const Pass& ps : s.passes)
       for (const Phase& pp : ps.phases) {
-        if (pp.mf == 1) {
-          if (pp.op_end - pp.op_begin < 3) {
-            if (err) *err = "fused phase of fewer than three updates";
+        if (pp.mf == 1 || pp.mf == 3) {
+          if (pp.op_end - pp.op_begin < (pp.mf == 1 ? 3 : 4)) {
+            if (err) *err = "fused phase of too few updates";
             return TNC_E_INVALID;
           }
           fused_at[pp.op_begin] = gp;
@@ -173,14 +195,24 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
   std::vector<char> d4swap(nops, 0);
   for (const Pass& ps : s.passes)
     for (const Phase& pp : ps.phases)
-      if (pp.mf == 2)
-        for (int g = 0; g < (pp.op_end - pp.op_begin) / 2 && g < 4; ++g)
+      if (pp.mf == 2 || pp.mf == 3)
+        for (int g = pp.mf == 3 ? 2 : 0; g < (pp.op_end - pp.op_begin) / 2 && g < 4; ++g)
           if (pp.dreg[g][0] > pp.dreg[g][1]) d4swap[pp.op_begin + 2 * g] = d4swap[pp.op_begin + 2 * g + 1] = 1;
   cd acc = 0;  // running rounding bias of the sweep (sum of rho - 1)
   size_t fused_left = 0;
   for (size_t o = 0; o < nops; ++o) {
     const SweepOp& op = s.ops[o];
-    if (fused_at[o] >= 0) {
+    if (fused_at[o] >= 0 && op.kind == OP_D4) {
+      // a bond-four unit: its two 4x4s run as one product, which carries
+      // the bias (both control halves of the operand are the same)
+      cd U[64];
+      float U32[128];
+      unit_matrix(&s.ops[o], U);
+      const cd r = round_entries(U, 64, acc, U32);
+      for (int c = 0; c < 2; ++c) fused_operand(U32, t->fmats.data() + (size_t)fused_at[o] * kFusedWords + c * 64);
+      acc += r;
+      fused_left = 4;
+    } else if (fused_at[o] >= 0) {
       // the three updates run as one product: its rounding carries the bias
       cd U[64];
       float U32[128];
@@ -203,12 +235,14 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
         auto sw = [&](int u) { return d4swap[o] ? (((u & 1) << 1) | (u >> 1)) : u; };
         for (int rr = 0; rr < 4; ++rr)
           for (int c = 0; c < 4; ++c) K[4 * rr + c] = (sw(rr) < 2 ? op : hb).mat[var][sw(rr) & 1].a[sw(c)];
-        const cd r = round_entries(K, 16, acc, K32);
+        // (updates inside a unit product keep their own tables out of the bias)
+        const cd r = round_entries(K, 16, fused_left > 0 ? cd(0) : acc, K32);
         if (var == 0) step = r;
         std::copy(K32, K32 + 16, t->mats.data() + (o * 4 + var) * 16);
         std::copy(K32 + 16, K32 + 32, t->mats.data() + ((o + 1) * 4 + var) * 16);
       }
-      acc += step;
+      if (fused_left > 0) fused_left = fused_left > 2 ? fused_left - 2 : 0;
+      else acc += step;
       ++o;
       continue;
     }
@@ -245,8 +279,9 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
       // a fused phase holds two targets in lane bits: up to R + 2 updates;
       // every phase must have an instantiated kernel form
       if (!phase_form_exists(R, nops, pp.mf)) return fail_t("phase size without a kernel form");
-      // the bond-four kernels run dense phases and single uncontrolled updates only
-      if (p.chi == 4 && pp.mf != 2 &&
+      // the bond-four kernels run dense and unit phases and single
+      // uncontrolled updates only
+      if (p.chi == 4 && pp.mf != 2 && pp.mf != 3 &&
           (nops != 1 || pp.mf != 0 || s.ops[pp.op_begin].kind != OP_CU || s.ops[pp.op_begin].control >= 0))
         return fail_t("bond-four phase without a kernel form");
       DevPhase dp;
@@ -263,6 +298,55 @@ int build_tables(Plan& p, const Schedule& s, HostTables* t, std::string* err) {
       }
       t->phases.push_back(dp);
       const int T = ps.w.tile_bits();
+      if (pp.mf == 3) {
+        // bond-four unit: A on (reg0, tpos4), B on (tpos4, tpos5); tail C on
+        // (reg1, reg2), D on (reg2, reg0); every tile bit once among
+        // registers and thread bits
+        const int TB = T - R;
+        if ((nops != 4 && nops != 8) || R < 3 || TB < 6 || TB > kMaxThreadBits) return fail_t("bad unit phase shape");
+        uint32_t seen = 0;
+        for (int b = 0; b < R; ++b) seen |= 1u << pp.reg[b];
+        for (int q = 0; q < TB; ++q) {
+          if (pp.tpos[q] < 0 || pp.tpos[q] >= T || (seen >> pp.tpos[q] & 1u)) return fail_t("bad unit thread map");
+          seen |= 1u << pp.tpos[q];
+        }
+        auto is4 = [&](int o) {
+          return s.ops[o].kind == OP_D4 && s.ops[o + 1].kind == OP_D4H && ps.w.contains(s.ops[o].target) &&
+                 ps.w.contains(s.ops[o].pair);
+        };
+        const SweepOp& A = s.ops[pp.op_begin];
+        const SweepOp& B = s.ops[pp.op_begin + 2];
+        if (!is4(pp.op_begin) || !is4(pp.op_begin + 2) || ps.w.local(A.target) != pp.reg[0] ||
+            ps.w.local(A.pair) != pp.tpos[4] || ps.w.local(B.target) != pp.tpos[4] || ps.w.local(B.pair) != pp.tpos[5] ||
+            A.xrow[0] >= 0 || A.xrow[1] >= 0 || B.xrow[0] >= 0 || B.xrow[1] >= 0)
+          return fail_t("unit phase product not canonical");
+        if (nops == 8) {
+          const SweepOp& C = s.ops[pp.op_begin + 4];
+          const SweepOp& D = s.ops[pp.op_begin + 6];
+          if (!is4(pp.op_begin + 4) || !is4(pp.op_begin + 6) || ps.w.local(C.target) != pp.reg[1] ||
+              ps.w.local(C.pair) != pp.reg[2] || ps.w.local(D.target) != pp.reg[2] || ps.w.local(D.pair) != pp.reg[0] ||
+              pp.dreg[2][0] != 1 || pp.dreg[2][1] != 2 || pp.dreg[3][0] != 2 || pp.dreg[3][1] != 0)
+            return fail_t("unit phase tail not canonical");
+        }
+        t->phases.back().pad = 3;
+        for (int i = 0; i < kPhaseOffs; ++i) {
+          uint32_t w = 0;
+          if (i < (1 << R)) w = phase_entry_offset(dp, R, i);
+          else if (i >= kPhaseEntries && i - kPhaseEntries < TB) w = swz(1u << pp.tpos[i - kPhaseEntries]) << 3;
+          t->poffs.push_back(w);
+        }
+        for (int b = 0; b < nops; ++b) {
+          const int o = pp.op_begin + b;
+          DevOp d;
+          std::memset(&d, 0, sizeof(d));
+          d.cloc = -1;
+          d.xrow0 = (int16_t)s.ops[o].xrow[0];
+          d.xrow1 = (int16_t)s.ops[o].xrow[1];
+          d.mat = o;
+          t->ops[o] = d;
+        }
+        continue;
+      }
       if (pp.mf == 1) {
         // fused phase: targets reg[0], tpos[4], tpos[5]; op 0's control (if
         // any) reg[R-1]; every tile bit exactly once among registers and
@@ -1439,7 +1523,7 @@ int tnc_plan_passes(tnc_plan_t plan, int32_t k, int32_t* out, int32_t cap, int32
   for (int32_t i = 0; i < cap && i < *n_passes; ++i) {
     const Pass& ps = s->passes[(size_t)i];
     int fused = 0;
-    for (const Phase& ph : ps.phases) fused += ph.mf == 1 ? 1 : 0;
+    for (const Phase& ph : ps.phases) fused += (ph.mf == 1 || ph.mf == 3) ? 1 : 0;
     int32_t* o = out + 7 * (size_t)i;
     o[0] = ps.w.lo_bits;
     o[1] = ps.w.win_lo;

@@ -21,7 +21,10 @@ GENERIC = [(2, 2, 1), (2, 2, 0), (3, 2, 1), (3, 4, 0), (4, 4, 1), (5, 6, 0), (6,
 TILES = [dict(max_tile_bits=6, low_bits=2, reg_bits=3), dict(max_tile_bits=6, low_bits=1, reg_bits=5),
          dict(max_tile_bits=7, low_bits=3, reg_bits=2), dict(max_tile_bits=8, low_bits=4, reg_bits=4), None,
          dict(max_tile_bits=7, low_bits=2, reg_bits=4, math=2),
-         dict(max_tile_bits=8, low_bits=3, reg_bits=4, reg_adapt=1)]
+         dict(max_tile_bits=8, low_bits=3, reg_bits=4, reg_adapt=1),
+         # matrix-core unit phases (a wavefront step as one 8x8)
+         dict(max_tile_bits=9, low_bits=3, reg_bits=3, math=2),
+         dict(max_tile_bits=10, low_bits=3, reg_bits=4, math=2)]
 
 
 @pytest.mark.parametrize("n", [3, 8, 12, 20])
@@ -68,6 +71,14 @@ def test_device_emulation_matches_oracle(n, d, fp, opt):
     got = p.debug_emulate_device(bits, 0)
     per, l2 = H.amp_errors(got, ref, n)
     assert per < H.TOL_C64, (per, l2)
+
+
+def test_unit_phases_are_planned_with_matrix_cores():
+    c = W.generic_brickwork_circuit(20, 18, W.rng_for(407, 2))
+    p = Plan.from_circuit(c, dict(max_tile_bits=10, low_bits=3, reg_bits=4, math=2))
+    assert sum(q["fused_phases"] for q in p.passes(0)) > 0
+    p0 = Plan.from_circuit(c, dict(max_tile_bits=10, low_bits=3, reg_bits=4))
+    assert sum(q["fused_phases"] for q in p0.passes(0)) == 0
 
 
 def test_dense_phases_hold_one_or_two_updates():

@@ -52,6 +52,10 @@ GENERIC = [
     (22, 20, 1, 2, FULL_OPTIONS),
     (24, 22, 0, 2, dict(max_tile_bits=12, reg_bits=4, reg_adapt=1)),
     (24, 24, 1, 2, dict(max_tile_bits=13, low_bits=5, reg_bits=5)),
+    # matrix-core unit phases, in 64-thread-wave tiles and full-size tiles
+    (20, 18, 1, 2, dict(max_tile_bits=9, low_bits=3, reg_bits=3, math=2)),
+    (24, 22, 0, 2, dict(max_tile_bits=13, low_bits=4, reg_bits=4, math=2)),
+    (22, 20, 1, 2, dict(max_tile_bits=13, low_bits=5, reg_bits=5, math=2)),
     # spatial sweeps (the n-qubit state is the narrower boundary)
     (2, 4, 1, 3, None),
     (5, 9, 0, 2, None),
@@ -97,13 +101,15 @@ def test_forced_bond_four_matches_bond_two():
     assert H.amp_errors(got2, ref, 14)[0] < H.TOL_C64
 
 
+@pytest.mark.parametrize("math", [0, 2])
 @pytest.mark.parametrize("n,d,nb", [(26, 26, 8), (34, 34, 1)])
-def test_swap_network_at_width(n, d, nb):
+def test_swap_network_at_width(n, d, nb, math):
     # width 25 with several batches, and the full width-33 workload of the
-    # bench (2^33 complex64 entries, 64 GiB per batch) in its tile options
+    # bench (2^33 complex64 entries, 64 GiB per batch) in its tile options,
+    # with dense phases on the vector ALUs and with unit phases
     from paper_2608_13110_amd import Plan
     c = W.swap_network_circuit(n, d, W.rng_for(507, n, d), 1)
-    p = Plan.from_circuit(c, FULL_OPTIONS)
+    p = Plan.from_circuit(c, dict(FULL_OPTIONS, math=math))
     assert p.info(0)["width"] == d - 1
     bits = W.random_bitstrings(n, nb, W.rng_for(508, n))
     ref = oracle.product_amplitudes(c, bits)
