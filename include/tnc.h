@@ -103,6 +103,11 @@ typedef struct {
                             boundary tensor of d - 1 slots (the width min(n, d-1) for n >= d-1)
                             updated by dense 4x4s, and k = 0 only (TNC_E_DOMAIN otherwise) */
   int32_t reserved;
+  uint64_t mem_cap_bytes; /* device memory the plan may use per call, 0: no cap.  A batch whose
+                             workspace exceeds it: TNC_E_NOMEM (tnc_workspace_bytes,
+                             tnc_amplitudes, tnc_amplitudes_host).  tnc_amplitudes uses at most the
+                             cap of the caller's workspace and tnc_amplitudes_host allocates at
+                             most the cap; the batches then run in groups that fit */
 } tnc_options;
 
 typedef struct {

@@ -64,7 +64,7 @@ class Options(ctypes.Structure):
     _fields_ = [("max_tile_bits", ctypes.c_int32), ("reg_bits", ctypes.c_int32),
                 ("low_bits", ctypes.c_int32), ("math", ctypes.c_int32),
                 ("late_fold", ctypes.c_int32), ("reg_adapt", ctypes.c_int32),
-                ("bond", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("bond", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mem_cap_bytes", ctypes.c_uint64)]
 
 
 class Info(ctypes.Structure):
@@ -202,14 +202,17 @@ def _gate_array(gates: Sequence):
     return garr
 
 
-_OPTION_KEYS = ("max_tile_bits", "reg_bits", "low_bits", "math", "late_fold", "reg_adapt", "bond")
+_OPTION_KEYS = ("max_tile_bits", "reg_bits", "low_bits", "math", "late_fold", "reg_adapt", "bond", "mem_cap_bytes")
 
 
 def _options(options: dict) -> Options:
     unknown = set(options) - set(_OPTION_KEYS)
     if unknown:
         raise ValueError(f"unknown tile options: {sorted(unknown)}")
-    return Options(*[int(options.get(k, 0)) for k in _OPTION_KEYS])
+    o = Options()
+    for k in _OPTION_KEYS:
+        setattr(o, k, int(options.get(k, 0)))
+    return o
 
 
 class Plan:

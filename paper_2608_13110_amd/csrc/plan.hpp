@@ -155,6 +155,7 @@ struct Options {
   int reg_adapt = 0;        // 1: a pass uses reg_bits - 1 when that needs no more phases; 0: never
   int bond = 0;             // entangler bond dimension of the lowering: 0 the smallest that holds
                             // every gate, 2, or 4
+  uint64_t mem_cap_bytes = 0;  // device memory per call (0: no cap)
 };
 
 // Everything that depends on k (the number of open output legs).

@@ -1234,6 +1234,7 @@ int tnc_plan(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, c
     o.late_fold = opt->late_fold;
     o.reg_adapt = opt->reg_adapt;
     o.bond = opt->bond;
+    o.mem_cap_bytes = opt->mem_cap_bytes;
   }
   if (o.max_tile_bits < 6 || o.max_tile_bits > 14 || o.reg_bits < 1 || o.reg_bits > 5 || o.low_bits < 1 ||
       o.low_bits > o.max_tile_bits - 2 || (o.math != 0 && o.math != 2) || o.late_fold < -1 || o.late_fold > 8 ||
@@ -1306,7 +1307,10 @@ int tnc_workspace_bytes(tnc_plan_t plan, int32_t k, int32_t n_batches, int32_t s
   if (rc) return set_err(rc, err);
   if ((rc = check_storage(t, storage))) return rc;
   if (p->h > kMaxDeviceWidth) return set_err(TNC_E_DOMAIN, "boundary tensors above 2^40 entries are planned only");
-  *bytes = (uint64_t)n_batches * batch_layout(*p, t, storage).per_batch();
+  const uint64_t per = batch_layout(*p, t, storage).per_batch();
+  if (p->opt.mem_cap_bytes && per > p->opt.mem_cap_bytes)
+    return set_err(TNC_E_NOMEM, "one batch's workspace (" + std::to_string(per) + " bytes) exceeds mem_cap_bytes");
+  *bytes = (uint64_t)n_batches * per;
   return TNC_OK;
 }
 
@@ -1320,6 +1324,8 @@ int tnc_amplitudes(tnc_plan_t plan, int32_t n_batches, const uint8_t* d_bits, in
   std::shared_ptr<DevSched> ds;
   int rc = get_dev_sched(*p, k, &ds);
   if (rc) return rc;
+  // the cap bounds the part of the caller's workspace in use
+  if (p->opt.mem_cap_bytes) workspace_bytes = std::min<uint64_t>(workspace_bytes, p->opt.mem_cap_bytes);
   return run_device(*p, *ds, n_batches, d_bits, k, storage, d_out, d_workspace, workspace_bytes,
                     static_cast<hipStream_t>(stream));
 }
@@ -1391,6 +1397,14 @@ int tnc_amplitudes_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits,
   uint64_t ws = 0;
   int rc = tnc_workspace_bytes(plan, k, n_batches, storage, &ws);
   if (rc) return rc;
+  const size_t nbits = (size_t)n_batches * p->n, nout = (size_t)n_batches << k;
+  if (p->opt.mem_cap_bytes) {
+    // at most the cap in all: bits, output, and a workspace for as many
+    // batches as fit (tnc_amplitudes runs the batches in groups)
+    const uint64_t per = ws / (uint64_t)n_batches, fixed = nbits + nout * 16 + 512;
+    if (fixed + per > p->opt.mem_cap_bytes) return set_err(TNC_E_NOMEM, "one batch does not fit in mem_cap_bytes");
+    ws = std::min<uint64_t>(ws, (p->opt.mem_cap_bytes - fixed) / per * per);
+  }
   uint8_t* d_bits = nullptr;
   tnc_c128* d_out = nullptr;
   void* d_ws = nullptr;
@@ -1405,7 +1419,6 @@ int tnc_amplitudes_host(tnc_plan_t plan, int32_t n_batches, const uint8_t* bits,
     if (d_ws) (void)hipFree(d_ws);
     if (st) (void)hipStreamDestroy(st);
   };
-  const size_t nbits = (size_t)n_batches * p->n, nout = (size_t)n_batches << k;
   if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) {
     st = nullptr;
     return hip_err(e, "hipStreamCreate");

@@ -337,3 +337,19 @@ def test_empty_batch():
     out = p.amplitudes(bits, 3, workspace=torch.empty(p.workspace_bytes(3, 1), dtype=torch.uint8, device="cuda"))
     torch.cuda.synchronize()
     assert tuple(out.shape) == (0, 8)
+
+
+def test_memory_cap_runs_batches_in_groups():
+    # tnc_amplitudes_host under mem_cap_bytes allocates at most the cap and
+    # runs the batches in groups that fit: same amplitudes as without the cap
+    from paper_2608_13110_amd import Plan
+    c = H.mixed_circuit(14, 18, 931, first_parity=1, dense=0.3)
+    bits = W.random_bitstrings(14, 6, W.rng_for(932))
+    free = Plan.from_circuit(c)
+    per = free.workspace_bytes(3, 1)
+    capped = Plan.from_circuit(c, dict(mem_cap_bytes=2 * per + (1 << 16)))
+    print(f"  [gpu] capped host path n=14 d=18 k=3 cap={2 * per + (1 << 16)}", flush=True)
+    got = capped.amplitudes_host(bits, 3)
+    ref = oracle.amplitudes(c, bits, 3)
+    assert np.array_equal(got, free.amplitudes_host(bits, 3))
+    assert_close(got, ref, 14)

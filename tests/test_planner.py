@@ -302,3 +302,20 @@ def test_lds_placement_is_conflict_free(cid, opts):
     st = p.debug_lds_conflicts(8)
     assert st["phases"] > 100
     assert st["conflicted_16"] == 0 and st["conflicted_32"] == 0, st
+
+
+def test_memory_cap_bounds_the_workspace():
+    # tnc_options.mem_cap_bytes (the boundary's memory cap): a batch whose
+    # workspace exceeds it is refused with TNC_E_NOMEM; below it the plan is
+    # unchanged
+    from paper_2608_13110_amd import TNC_E_NOMEM
+    c = W.brickwork_circuit(16, 20, 8, W.rng_for(307, 1))
+    free = Plan.from_circuit(c)
+    per = free.workspace_bytes(3, 1)
+    assert Plan.from_circuit(c, dict(mem_cap_bytes=per)).workspace_bytes(3, 4) == 4 * per
+    with pytest.raises(TncError) as e:
+        Plan.from_circuit(c, dict(mem_cap_bytes=per - 1)).workspace_bytes(3, 1)
+    assert e.value.code == TNC_E_NOMEM
+    bits = W.random_bitstrings(16, 3, W.rng_for(307, 2))
+    capped = Plan.from_circuit(c, dict(mem_cap_bytes=per))
+    assert np.array_equal(capped.debug_execute_host(bits, 3), free.debug_execute_host(bits, 3))
