@@ -254,12 +254,16 @@ typedef struct tnc_ring_plan_s* tnc_ring_plan_t;
 int tnc_plan_ring(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, const tnc_gate2* gates,
                   const tnc_options* opt, tnc_ring_plan_t* out);
 /* Slice count, width of each slice, and device workspace for n_batches
- * batches (one slice's workspace plus a slice result buffer). */
+ * batches (a group of slices run together: their workspaces, results and
+ * launch segment tables; host only). */
 int tnc_ring_info(tnc_ring_plan_t ring, int32_t k, int32_t n_batches, int32_t* n_slices, int32_t* width,
                   uint64_t* workspace_bytes);
 /* Ring amplitudes, with the arguments of tnc_amplitudes (complex64 storage):
- * the slices run in index order on `stream`, each result added to d_out in
- * FP64.  The workspace must hold what tnc_ring_info reports. */
+ * the slices run in groups of up to 1024 on `stream` (the i-th launches of a
+ * group's slices as one grouped launch), their results added to d_out in
+ * slice order in FP64.  The workspace must hold what tnc_ring_info reports.
+ * The ring plan's pinned staging is reused call to call: one thread at a
+ * time per ring plan. */
 int tnc_ring_amplitudes(tnc_ring_plan_t ring, int32_t n_batches, const uint8_t* d_bits, int32_t k, tnc_c128* d_out,
                         void* d_workspace, uint64_t workspace_bytes, void* stream);
 /* Host emulation of every slice (tnc_debug_emulate_device) summed on the

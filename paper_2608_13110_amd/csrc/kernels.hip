@@ -1261,35 +1261,48 @@ hipError_t launch_op64(const Op64Args& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// log-XEB (Sec. 5.2): F = gamma + n ln 2 + mean_i ln p_i with p_i = |amp|^2
-// of the selected component of each batch (sel == nullptr: every component).
-// One block, FP64 throughout.  result = {F, SE, F - 1.96 SE, F + 1.96 SE, N}.
 // FP64 complex fill and sum (the ring's sum over slices).
 __global__ __launch_bounds__(kBlock) void k_fill_zero(double2* out, long long count) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) out[i] = make_double2(0.0, 0.0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_accumulate(double2* out, const double2* in, long long count) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) {
-    const double2 a = out[i], b = in[i];
-    out[i] = make_double2(a.x + b.x, a.y + b.y);
-  }
+// A launch whose status is its own (hipGetLastError after a launch would
+// also return, and clear, an error the caller had pending).  The arguments
+// are the kernel's parameters by value, in order.
+template <class... A>
+static hipError_t launch_direct(const void* fn, dim3 grid, dim3 block, hipStream_t s, A... args) {
+  void* argv[] = {static_cast<void*>(&args)...};
+  return hipLaunchKernel(fn, grid, block, argv, 0, s);
 }
 
 hipError_t launch_fill_zero(double2* out, long long count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, out, count);
-  return hipGetLastError();
+  return launch_direct(reinterpret_cast<const void*>(&k_fill_zero), dim3((unsigned)((count + kBlock - 1) / kBlock)),
+                       dim3(kBlock), s, out, count);
 }
 
-hipError_t launch_accumulate(double2* out, const double2* in, long long count, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_accumulate, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, out, in,
-                     count);
-  return hipGetLastError();
+// out[i] += in[r * stride + i] for r = 0..rows-1 in order (FP64).
+__global__ __launch_bounds__(kBlock) void k_accumulate_rows(double2* out, const double2* in, long long stride,
+                                                           int rows, long long count) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double2 acc = out[i];
+  for (int r = 0; r < rows; ++r) {
+    const double2 v = in[(long long)r * stride + i];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  out[i] = acc;
 }
+
+hipError_t launch_accumulate_rows(double2* out, const double2* in, long long stride, int rows, long long count,
+                                  hipStream_t s) {
+  if (count <= 0 || rows <= 0) return hipSuccess;
+  return launch_direct(reinterpret_cast<const void*>(&k_accumulate_rows),
+                       dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), s, out, in, stride, rows, count);
+}
+
 
 // Batched sampling (Sec. 4.2, steps 3-4): one block per batch.  Thread t
 // holds entries [t E, t E + E) of the batch's 2^k (E = 2^k / 256 or 1),
@@ -1362,18 +1375,21 @@ __global__ __launch_bounds__(kBlock) void k_frugal_accept(const double2* amps, l
 hipError_t launch_sample_batched(const double2* amps, int n_batches, int k, const double* u, int32_t* b, double* q,
                                  hipStream_t s) {
   if (n_batches <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sample_batched, dim3((unsigned)n_batches), dim3(kBlock), 0, s, amps, k, u, b, q);
-  return hipGetLastError();
+  return launch_direct(reinterpret_cast<const void*>(&k_sample_batched), dim3((unsigned)n_batches), dim3(kBlock), s,
+                       amps, k, u, b, q);
 }
 
 hipError_t launch_frugal_accept(const double2* amps, long long count, int n, double M, const double* u,
                                 uint8_t* accept, double* z, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const long long blocks = (count + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_frugal_accept, dim3((unsigned)blocks), dim3(kBlock), 0, s, amps, count, n, M, u, accept, z);
-  return hipGetLastError();
+  return launch_direct(reinterpret_cast<const void*>(&k_frugal_accept), dim3((unsigned)blocks), dim3(kBlock), s, amps,
+                       count, n, M, u, accept, z);
 }
 
+// log-XEB (Sec. 5.2): F = gamma + n ln 2 + mean_i ln p_i with p_i = |amp|^2
+// of the selected component of each batch (sel == nullptr: every component).
+// One block, FP64 throughout.  result = {F, SE, F - 1.96 SE, F + 1.96 SE, N}.
 __global__ __launch_bounds__(kBlock) void k_logxeb(const double2* amps, int n_batches, int k,
                                                    const int32_t* sel, int n_qubits, double* result) {
   __shared__ double s1[kBlock], s2[kBlock];
@@ -1414,8 +1430,8 @@ __global__ __launch_bounds__(kBlock) void k_logxeb(const double2* amps, int n_ba
 
 hipError_t launch_logxeb(const double2* amps, int n_batches, int k, const int32_t* sel, int n_qubits,
                          double* result, hipStream_t s) {
-  hipLaunchKernelGGL(k_logxeb, dim3(1), dim3(kBlock), 0, s, amps, n_batches, k, sel, n_qubits, result);
-  return hipGetLastError();
+  return launch_direct(reinterpret_cast<const void*>(&k_logxeb), dim3(1), dim3(kBlock), s, amps, n_batches, k, sel,
+                       n_qubits, result);
 }
 
 }  // namespace tnc

@@ -652,7 +652,9 @@ hipError_t launch_op64(const Op64Args& a, hipStream_t s);
 
 // Launchers of the kernels outside the amplitude path (kernels.hip).
 hipError_t launch_fill_zero(double2* out, long long count, hipStream_t s);
-hipError_t launch_accumulate(double2* out, const double2* in, long long count, hipStream_t s);
+// out[i] += sum over r < rows of in[r * stride + i], added in row order.
+hipError_t launch_accumulate_rows(double2* out, const double2* in, long long stride, int rows, long long count,
+                                  hipStream_t s);
 // Batched sampling handles up to 2^10 suffixes per batch: 4 per thread.
 constexpr int kMaxSampleEntries = 4;
 hipError_t launch_sample_batched(const double2* amps, int n_batches, int k, const double* u, int32_t* b, double* q,

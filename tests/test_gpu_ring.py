@@ -1,6 +1,7 @@
 """GPU tests of the ring geometry (Sec. 6.3) by slicing its wrap-pair CZ
-bonds: the sum over 2^m open-chain slices, through the C ABI, against the
-FP64 oracle's state vector of the ring itself."""
+bonds: the sum over 2^m open-chain slices (run in grouped launches of up to
+1024 slices), through the C ABI, against the FP64 oracle's state vector of
+the ring itself."""
 import numpy as np
 import pytest
 
@@ -23,7 +24,9 @@ def _device():
 
 @pytest.mark.parametrize("n,d,k,opts", [(6, 6, 0, None), (8, 8, 2, None), (10, 9, 2, None),
                                         (12, 12, 3, dict(max_tile_bits=6, low_bits=2, reg_bits=3)),
-                                        (16, 16, 4, None), (20, 20, 4, dict(max_tile_bits=8))])
+                                        (16, 16, 4, None), (20, 20, 4, dict(max_tile_bits=8)),
+                                        # 4096 slices: four groups of 1024
+                                        (24, 24, 2, None)])
 def test_ring_matches_oracle(n, d, k, opts):
     from paper_2608_13110_amd import RingPlan
     c = W.ring_circuit(n, d, n, W.rng_for(140, n, d))
