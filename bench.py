@@ -653,8 +653,8 @@ def cpu_baseline(W, torch, Plan):
     # (name, config id, restriction, batches, k, thread counts)
     plan_ = [("tiny n=12 d=12", 0, 12, 512, 3, (all_threads, 1)),
              ("precision restricted n=22 d=56", 2, 22, 16, 8, (all_threads, 1)),
-             ("medium restricted n=24 d=40", 1, 24, 64, 6, (all_threads,)),
-             ("full_width restricted n=24 d=66", 4, 24, 8, 8, (all_threads,))]
+             ("medium restricted n=24 d=40", 1, 24, 64, 6, (all_threads, 1)),
+             ("full_width restricted n=24 d=66", 4, 24, 8, 8, (all_threads, 1))]
     out = []
     head = None
     for name, cid, m, nb, k, threads in plan_:
@@ -669,6 +669,7 @@ def cpu_baseline(W, torch, Plan):
         rec = {"instance": name, "amplitudes": int(len(bits) << k)}
         z = None
         for th in threads:
+            log(f"cpu baseline: {name}, {th} thread(s)")
             if gomp is not None:
                 gomp.omp_set_num_threads(int(th))
             t0 = time.time()
