@@ -854,7 +854,8 @@ def main():
     if secondary is not None:
         line["secondary"] = {k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in secondary.items()
                              if k2 in ("workload", "amplitudes_per_s", "pass_gbs", "latency_ms_p50",
-                                       "latency_ms_p99", "ms_per_step", "steps", "pass_avg_ms")}
+                                       "latency_ms_p99", "ms_per_step", "steps", "pass_avg_ms", "tile_options",
+                                       "pass_classes")}
         line["secondary"]["hbm_frac"] = round(secondary["pass_gbs"] / HBM_PEAK_GBS, 4)
     if storage is not None:
         line["storage_modes"] = storage
