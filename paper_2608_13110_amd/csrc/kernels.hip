@@ -287,7 +287,10 @@ __device__ __attribute__((always_inline)) inline void pass_body(const PassArgs& 
   ctx.rm = (const TNC_TBL float*)(a.rmats + (size_t)batch * a.rstride);
   ctx.tb = 0;
   ctx.uniform = WU;
-  const uint32_t rbase = (uint32_t)tile_in_block << (T + 3);
+  // the phases address the LDS by whole LDS addresses: the tile's region
+  // base with the array's own address ORed in (the pass kernels declare no
+  // static LDS, so the dynamic array starts at LDS address 0)
+  const uint32_t rbase = lds_address(lds) | ((uint32_t)tile_in_block << (T + 3));
   for (int p = 0; p < a.n_phases; ++p) {
     const DevPhase P = load_phase(a.phases, p);
     phase_dispatch<R, WU, KIND>(reinterpret_cast<char*>(lds), rbase, P, (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs,
@@ -409,7 +412,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass_waves_p
   ctx.uniform = WU;
   for (int p = 0; p < a.n_phases; ++p) {
     const DevPhase P = load_phase(a.phases, p);
-    phase_dispatch<R, WU, KIND>(reinterpret_cast<char*>(lds), (uint32_t)tile_in_block << (T + 3), P,
+    phase_dispatch<R, WU, KIND>(reinterpret_cast<char*>(lds), lds_address(lds) | ((uint32_t)tile_in_block << (T + 3)), P,
                           (const TNC_TBL uint32_t*)a.poffs + p * kPhaseOffs, ctx, tt, TB,
                           a.fmats + (size_t)p * kFusedWords);
     __syncthreads();

@@ -114,6 +114,31 @@ TNC_HD inline DevPhase load_phase(const DevPhase* phases, int p) {
   return __builtin_bit_cast(DevPhase, w);
 }
 
+// The LDS address of a pointer into LDS (0 on the host, whose emulation
+// addresses its tile from the region pointer).
+TNC_HD inline uint32_t lds_address(const void* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+#else
+  (void)p;
+  return 0u;
+#endif
+}
+#if defined(__HIP_DEVICE_COMPILE__)
+// The LDS entry at LDS address `off`: the phase offsets are whole LDS
+// addresses (the tile's region base folded in once per block), so no
+// per-entry addition of the array's base.
+__device__ __attribute__((always_inline)) inline float2 lds_get(char*, uint32_t off) {
+  return *(const __attribute__((address_space(3))) float2*)(uintptr_t)off;
+}
+__device__ __attribute__((always_inline)) inline void lds_put(char*, uint32_t off, float2 v) {
+  *(__attribute__((address_space(3))) float2*)(uintptr_t)off = v;
+}
+#else
+inline float2 lds_get(char* base, uint32_t off) { return *reinterpret_cast<const float2*>(base + off); }
+inline void lds_put(char* base, uint32_t off, float2 v) { *reinterpret_cast<float2*>(base + off) = v; }
+#endif
+
 // Register-resident complex64 entries of a thread: separate real and
 // imaginary float arrays (keeps every element promotable to a VGPR).
 template <int R>
@@ -292,12 +317,13 @@ TNC_HD inline Regs<R> stair(Regs<R> v, const DevPhase& P, const PhaseCtx<R>& c) 
 
 // LDS byte offset of a thread's base entry in a phase: thread bit t adds the
 // tile bit the planner placed it on, whose offset is po[kPhaseEntries + t]
-// (wave-uniform table reads: scalar loads).
-TNC_HD inline uint32_t phase_thread_base(uint32_t rbase, const TNC_TBL uint32_t* po, uint32_t tt, int TB) {
+// (wave-uniform table reads: one wide scalar load).  No test of t against
+// the phase's thread-bit count: the table holds zero past it and the thread
+// index has no bit set there, so the loop is straight-line code.
+TNC_HD inline uint32_t phase_thread_base(uint32_t rbase, const TNC_TBL uint32_t* po, uint32_t tt) {
   uint32_t vb = rbase;
 #pragma unroll
-  for (int t = 0; t < kMaxThreadBitsDev; ++t)
-    if (t < TB) vb ^= (0u - ((tt >> t) & 1u)) & po[kPhaseEntries + t];
+  for (int t = 0; t < kMaxThreadBitsDev; ++t) vb ^= (0u - ((tt >> t) & 1u)) & po[kPhaseEntries + t];
   return vb;
 }
 
@@ -313,20 +339,20 @@ TNC_HD inline void phase_exec(char* base, uint32_t rbase, const DevPhase& P, con
   constexpr int E = 1 << R;
   PhaseCtx<R> c = c0;
   c.tb = tt;
-  const uint32_t vbase = phase_thread_base(rbase, po, tt, TB);
+  const uint32_t vbase = phase_thread_base(rbase, po, tt);
   uint32_t off[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) off[i] = vbase ^ po[i];
   Regs<R> v;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    const float2 t = *reinterpret_cast<const float2*>(base + off[i]);
+    const float2 t = lds_get(base, off[i]);
     v.x[i] = t.x;
     v.y[i] = t.y;
   }
   v = stair<R, N, K0>(v, P, c);
 #pragma unroll
-  for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(base + off[i]) = make_float2(v.x[i], v.y[i]);
+  for (int i = 0; i < E; ++i) lds_put(base, off[i], make_float2(v.x[i], v.y[i]));
 }
 
 // Between the updates of a dense phase: keeps each update's 32 matrix
@@ -346,14 +372,14 @@ template <int R>
 TNC_HD inline void phase_dense(char* base, uint32_t rbase, const DevPhase& P, const TNC_TBL uint32_t* po,
                                const PhaseCtx<R>& c, uint32_t tt, int TB) {
   constexpr int E = 1 << R;
-  const uint32_t vbase = phase_thread_base(rbase, po, tt, TB);
+  const uint32_t vbase = phase_thread_base(rbase, po, tt);
   uint32_t off[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) off[i] = vbase ^ po[i];
   Regs<R> v;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    const float2 t = *reinterpret_cast<const float2*>(base + off[i]);
+    const float2 t = lds_get(base, off[i]);
     v.x[i] = t.x;
     v.y[i] = t.y;
   }
@@ -401,7 +427,7 @@ TNC_HD inline void phase_dense(char* base, uint32_t rbase, const DevPhase& P, co
       break;  // excluded on the host (dense_form_exists)
   }
 #pragma unroll
-  for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(base + off[i]) = make_float2(v.x[i], v.y[i]);
+  for (int i = 0; i < E; ++i) lds_put(base, off[i], make_float2(v.x[i], v.y[i]));
 }
 
 template <int R, int N>
@@ -456,14 +482,14 @@ __device__ __attribute__((always_inline)) inline void phase_tri(char* base, uint
                                                                 const PhaseCtx<R>& c, uint32_t tt, int TB) {
   constexpr int E = 1 << R;
   const int lane = (int)(tt & 63u);
-  const uint32_t vb = phase_thread_base(rbase, po, tt, TB);
+  const uint32_t vb = phase_thread_base(rbase, po, tt);
   uint32_t off[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) off[i] = vb ^ po[i];
   Regs<R> v;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    const float2 t = *reinterpret_cast<const float2*>(base + off[i]);
+    const float2 t = lds_get(base, off[i]);
     v.x[i] = t.x;
     v.y[i] = t.y;
   }
@@ -488,7 +514,7 @@ __device__ __attribute__((always_inline)) inline void phase_tri(char* base, uint
   if constexpr (N >= 6) v = op_reg<R, 3, 2>(v, c.rm + (size_t)(P.op_begin + 5) * 16);
   if constexpr (N >= 7) v = op_reg<R, 4, 3>(v, c.rm + (size_t)(P.op_begin + 6) * 16);
 #pragma unroll
-  for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(base + off[i]) = make_float2(v.x[i], v.y[i]);
+  for (int i = 0; i < E; ++i) lds_put(base, off[i], make_float2(v.x[i], v.y[i]));
 }
 
 // A bond-four unit phase (P.pad = 3): one wavefront step, the 4x4 on (b0,
@@ -503,14 +529,14 @@ __device__ __attribute__((always_inline)) inline void phase_unit(char* base, uin
                                                                  const PhaseCtx<R>& c, uint32_t tt, int TB) {
   constexpr int E = 1 << R;
   const int lane = (int)(tt & 63u);
-  const uint32_t vb = phase_thread_base(rbase, po, tt, TB);
+  const uint32_t vb = phase_thread_base(rbase, po, tt);
   uint32_t off[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) off[i] = vb ^ po[i];
   Regs<R> v;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    const float2 t = *reinterpret_cast<const float2*>(base + off[i]);
+    const float2 t = lds_get(base, off[i]);
     v.x[i] = t.x;
     v.y[i] = t.y;
   }
@@ -524,7 +550,7 @@ __device__ __attribute__((always_inline)) inline void phase_unit(char* base, uin
     }
   }
 #pragma unroll
-  for (int i = 0; i < E; ++i) *reinterpret_cast<float2*>(base + off[i]) = make_float2(v.x[i], v.y[i]);
+  for (int i = 0; i < E; ++i) lds_put(base, off[i], make_float2(v.x[i], v.y[i]));
 }
 #endif
 
