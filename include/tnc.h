@@ -136,8 +136,10 @@ typedef struct {
  *              Pattern pairs without a gate are identity.  Copied.
  *   opt:       may be NULL.
  * Host only: no device memory is touched.  Returns TNC_OK and *out, or
- * TNC_E_INVALID / TNC_E_DOMAIN (n < 2, d < 2, width > 40, bond 4 at odd d) /
- * TNC_E_RANK (an entangler of rank > 2 with opt->bond = 2).
+ * TNC_E_INVALID / TNC_E_DOMAIN (n < 2, d < 2, a bond-two width above 40, a
+ * bond-four width above 69, bond four at odd d with n > d) / TNC_E_RANK (an
+ * entangler of rank > 2 with opt->bond = 2).  Bond-four plans of width 41..69
+ * are planned only (tnc_plan_info; the amplitude calls return TNC_E_DOMAIN).
  */
 int tnc_plan(int32_t n, int32_t d, const tnc_c128* one_qubit, int32_t n_gate2, const tnc_gate2* gates,
              const tnc_options* opt, tnc_plan_t* out);

@@ -106,6 +106,25 @@ def test_rank_and_domain_errors():
     assert e.value.code == TNC_E_DOMAIN
 
 
+def test_width_limits():
+    # bond two: widths up to 40 are planned (a 2^40-entry tensor is the
+    # device limit), wider ones refused; bond four: widths up to 69 are
+    # planned, above 40 for the path estimate only (no workspace)
+    ok = Plan.from_circuit(W.brickwork_circuit(82, 80, 4, W.rng_for(309, 1)))
+    assert ok.info(0)["width"] == 40 and ok.info(0)["workspace_per_batch"] > 0
+    with pytest.raises(TncError) as e:
+        Plan.from_circuit(W.brickwork_circuit(84, 82, 4, W.rng_for(309, 2)))
+    assert e.value.code == TNC_E_DOMAIN
+    p4 = Plan.from_circuit(W.generic_brickwork_circuit(44, 44, W.rng_for(309, 3)))
+    assert p4.info(0)["width"] == 43 and p4.info(0)["workspace_per_batch"] == 0
+    with pytest.raises(TncError) as e:
+        p4.workspace_bytes(0, 1)
+    assert e.value.code == TNC_E_DOMAIN
+    with pytest.raises(TncError) as e:
+        Plan.from_circuit(W.generic_brickwork_circuit(72, 72, W.rng_for(309, 4)))
+    assert e.value.code == TNC_E_DOMAIN
+
+
 CASES = [(2, 2, 1), (2, 5, 0), (3, 2, 0), (3, 7, 1), (4, 4, 0), (5, 6, 1), (6, 7, 0), (7, 8, 1),
          (8, 9, 0), (9, 12, 1), (10, 15, 0), (12, 12, 1), (13, 20, 0)]
 
