@@ -44,7 +44,7 @@ WORKLOADS = {
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.hpp", "device_tables.hpp"):
+    for f in ("kernels.hip", "kernels.hpp", "device_tables.hpp", "lds_layout.hpp"):
         with open(os.path.join(ROOT, "paper_2608_13110_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
