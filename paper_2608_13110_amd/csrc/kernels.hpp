@@ -127,12 +127,14 @@ TNC_HD inline uint32_t lds_address(const void* p) {
 #if defined(__HIP_DEVICE_COMPILE__)
 // The LDS entry at LDS address `off`: the phase offsets are whole LDS
 // addresses (the tile's region base folded in once per block), so no
-// per-entry addition of the array's base.
+// per-entry addition of the array's base.  Moved as one 64-bit word, so each
+// access stays a single ds_read_b64 / ds_write_b64 (the bank-cycle placement
+// is laid out for 8-byte accesses).
 __device__ __attribute__((always_inline)) inline float2 lds_get(char*, uint32_t off) {
-  return *(const __attribute__((address_space(3))) float2*)(uintptr_t)off;
+  return __builtin_bit_cast(float2, *(const __attribute__((address_space(3))) uint64_t*)(uintptr_t)off);
 }
 __device__ __attribute__((always_inline)) inline void lds_put(char*, uint32_t off, float2 v) {
-  *(__attribute__((address_space(3))) float2*)(uintptr_t)off = v;
+  *(__attribute__((address_space(3))) uint64_t*)(uintptr_t)off = __builtin_bit_cast(uint64_t, v);
 }
 #else
 inline float2 lds_get(char* base, uint32_t off) { return *reinterpret_cast<const float2*>(base + off); }
