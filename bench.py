@@ -85,11 +85,12 @@ MAIN_CANDIDATES = [dict(), dict(max_tile_bits=12, math=2), dict(reg_bits=4, math
                    dict(max_tile_bits=13, low_bits=5, reg_bits=4, math=2)]
 
 
-def pass_classes(plan, k, launches, h, bytes_per_entry=8):
+def pass_classes(plan, k, launches, h, bytes_per_entry=8, flops_per_op=14.0):
     """Pass launches of the timed steps grouped by window class (low slots,
     window start, window length): count per batch, updates, phases, average
-    ms and the fraction of the HBM peak (algorithmic bytes 2 * 2^h * entry
-    bytes per launch)."""
+    ms, the fraction of the HBM peak (algorithmic bytes 2 * 2^h * entry
+    bytes per launch) and the fraction of the FP32 vector peak (algorithmic
+    flops: flops_per_op per entry and update, matrix-core work included)."""
     passes = plan.passes(k)
     ms = [m for c, m in launches if c == 1]
     if not passes or len(ms) % len(passes):
@@ -109,9 +110,11 @@ def pass_classes(plan, k, launches, h, bytes_per_entry=8):
         avg = sum(g["ms"]) / len(g["ms"])
         ups = [q["updates"] for q in passes if (q["low_bits"], q["win_lo"], q["win_len"]) == key]
         phs = [q["phases"] for q in passes if (q["low_bits"], q["win_lo"], q["win_len"]) == key]
+        flops = sum(ups) / len(ups) * flops_per_op * (1 << h)
         out.append({"window": list(key), "passes_per_batch": g["n"],
                     "updates_avg": round(sum(ups) / len(ups), 2), "phases_avg": round(sum(phs) / len(phs), 2),
-                    "ms_avg": round(avg, 3), "hbm_frac": round(nbytes / (avg / 1e3) / 1e9 / HBM_PEAK_GBS, 4)})
+                    "ms_avg": round(avg, 3), "hbm_frac": round(nbytes / (avg / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "alu_frac": round(flops / (avg / 1e3) / 1e12 / FP32_VALU_PEAK_TFLOPS, 4)})
     return out
 
 
@@ -398,7 +401,7 @@ def bond4_bench(torch, W, Plan, profile_begin, profile_end, steps=3):
     torch.cuda.synchronize()
     wall = time.time() - t0
     prof = profile_end()
-    classes = pass_classes(plan, 0, profile_launches(), h)
+    classes = pass_classes(plan, 0, profile_launches(), h, flops_per_op=15.0)
     pass_s = prof["pass_ms"] / 1e3
     # algorithmic FLOPs per entry: 30 for a dense 4x4 (4 complex products,
     # 3 complex sums), 14 for a 2x2
