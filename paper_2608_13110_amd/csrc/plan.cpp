@@ -616,6 +616,14 @@ std::vector<Window> window_grid_overlap(const Plan& p, int hmax, int ov) {
     }
     ws.push_back(x);
   }
+  // the top turn one slot shorter when the window below still overlaps it by
+  // ov slots (as in window_grid)
+  const size_t nw = ws.size();
+  if (L <= 9 && nw >= 3 && ws[nw - 1].win_len == L && ws[nw - 1].win_lo + L - 1 == E &&
+      ws[nw - 2].win_lo + ws[nw - 2].win_len - 1 >= ws[nw - 1].win_lo + ov) {
+    ws[nw - 1].win_lo += 1;
+    ws[nw - 1].win_len -= 1;
+  }
   return ws;
 }
 
