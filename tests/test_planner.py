@@ -53,8 +53,9 @@ def test_partition_example_matches_paper():
 
 
 def test_width_and_cost_do_not_depend_on_gate_values():
-    # Abstract / Sec. 1: width and dense scheduled cost are independent of the
-    # one-qubit gate values and of the number and placement of T gates.
+    # Sec. 1: one-qubit gates are absorbed into the network without changing
+    # its shape, so the planned width and cost must not move when the gate
+    # values change or when T gates are added, removed or moved.
     ref = None
     for seed, nt in [(1, 0), (2, 30), (3, 300), (4, 700)]:
         c = W.brickwork_circuit(40, 33, nt, W.rng_for(304, seed))
