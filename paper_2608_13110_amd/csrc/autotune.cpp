@@ -1,9 +1,9 @@
 // Tile autotuner: times candidate pass tilings on the device.
 //
 // The width, the op sequence and hence the pass partition depend only on the
-// circuit's shape (n, d) and k, not on its gate values (Sec. 1 and Sec. 7: width and
-// scheduled cost are independent of the one-qubit gates and of the T
-// placement), so one synthetic circuit of the right shape stands for every
+// circuit's shape (n, d) and k, not on its gate values: one-qubit gates,
+// T gates included, are absorbed without changing the network (Sec. 1 and
+// Sec. 7).  So one synthetic circuit of the right shape stands for every
 // circuit of that shape: brickwork CZ layers with seeded random one-qubit
 // unitaries.
 #include <hip/hip_runtime.h>
