@@ -6,8 +6,8 @@
  * Method (arXiv 2608.13110):
  *   - circuit family: n qubits on an open chain, d layers of nearest-
  *     neighbour entanglers alternating between the pairs (1,2),(3,4),... and
- *     (2,3),(4,5),... (1-based), arbitrary one-qubit gates before, between
- *     and after the layers (Sec. 2.1); every entangler must have operator
+ *     (2,3),(4,5),... (1-based), a layer of one-qubit gates (any 2x2)
+ *     around each of them, d + 1 in all (Sec. 2.1); every entangler must have operator
  *     Schmidt rank <= 2 (Sec. 2.1, the operator-Schmidt-rank equation);
  *   - the amplitude psi(x) = <x|U|0^n> (Sec. 2.2) is contracted by the
  *     unsliced sweep of Alg. 1 (Sec. 3.1), width ceil(d/2) (Prop.

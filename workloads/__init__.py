@@ -6,9 +6,9 @@ request streams.  It contains none of the contraction arithmetic.
 
 Circuit family (Sec. 2.1 of arXiv 2608.13110): ``n`` qubits on an open chain,
 ``d`` entangling layers of nearest-neighbour CZ gates whose pattern alternates
-between the pairs (1,2),(3,4),... and (2,3),(4,5),... (1-based), one-qubit
-gates before, between and after the layers, and T gates inserted at some
-(qubit, one-qubit-layer) sites.
+between the pairs (1,2),(3,4),... and (2,3),(4,5),... (1-based), d + 1
+layers of one-qubit gates (one ahead of the first entangling layer, one
+behind each), and T gates inserted at some (qubit, one-qubit-layer) sites.
 
 Conventions (0-based everywhere):
   * qubit ``q`` is row ``q`` of the chain; gate ``(l, q)`` acts on ``(q, q+1)``.
