@@ -1,7 +1,7 @@
 // Bond-dimension-four lowering of the temporal-boundary contraction
 // (Sec. 6.2, "Effect of bond dimension").
 //
-// A generic two-qubit gate has operator Schmidt rank 4 (Sec. 2.1), so one
+// Generic two-qubit gates reach operator Schmidt rank 4 (Sec. 2.1), so one
 // binary copy index per crossing no longer carries it.  Written in matrix
 // units of its upper qubit q, a gate on (q, q+1) is
 //     G = sum_{a,b} |a><b| (x) U_ab,    U_ab[y'][y] = G[2a + y'][2b + y],

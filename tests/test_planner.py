@@ -53,8 +53,8 @@ def test_partition_example_matches_paper():
 
 
 def test_width_and_cost_do_not_depend_on_gate_values():
-    # Sec. 1: one-qubit gates are absorbed into the network without changing
-    # its shape, so the planned width and cost must not move when the gate
+    # Sec. 1: absorbing one-qubit gates leaves the shape of the network as
+    # it is, so the planned width and cost must not move when the gate
     # values change or when T gates are added, removed or moved.
     ref = None
     for seed, nt in [(1, 0), (2, 30), (3, 300), (4, 700)]:
